@@ -1,0 +1,196 @@
+/*
+ * dnnmg.h -- C-ABI of the MI355X (gfx950) DNN-MG hot path.
+ *
+ * The library advances the discrete incompressible Navier-Stokes system of
+ * Sec. 2.1 of "Deep neural networks for geometric multigrid methods"
+ * (Q1/Q1 finite elements with local projection stabilisation, Crank-Nicolson
+ * in time, eqs. nonlinearshort, varform, varformv) by Newton's method
+ * (eq. newton) whose linear systems are solved by GMRES preconditioned with a
+ * geometric multigrid V-cycle (Sec. 2.2), and applies the DNN-MG correction
+ * of Algorithm 1 (prolongation, patch-wise recurrent network, right-hand side
+ * on the fine level, restriction).
+ *
+ * Conventions shared by all calls
+ *   - Status: every call returns 0 (DNNMG_OK) or a negative DNNMG_E* code.
+ *     Arguments are validated before any device work; on error the message
+ *     is available from dnnmg_last_error().  No C++ exception or abort
+ *     crosses this boundary.
+ *   - Nodal vectors are interleaved: 3 doubles per node, (u, v, p), in the
+ *     library's node numbering of that level (dnnmg_level_coords gives the
+ *     coordinates).  Node numbering of a refinement: old vertices keep their
+ *     ids, then one node per edge in order of first appearance over the
+ *     cells, then one node per cell; cell c has children 4c..4c+3.
+ *   - Host pointers are borrowed for the duration of the call and copied.
+ *     Device pointers (the *_dev calls) are borrowed for the call only.
+ *   - The context owns every device allocation it makes (hipMalloc); states
+ *     and networks belong to their context and must be destroyed before it.
+ *   - Work is enqueued on params.stream (NULL: the default stream).  Calls
+ *     that return host data or statistics synchronise that stream.
+ */
+#ifndef DNNMG_H
+#define DNNMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DNNMG_OK 0
+#define DNNMG_EINVAL (-1)   /* bad argument (checked before device work)      */
+#define DNNMG_ENOMEM (-2)   /* device or host allocation failed               */
+#define DNNMG_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed     */
+#define DNNMG_ENOCONV (-4)  /* Newton or GMRES did not converge; state rolled back */
+#define DNNMG_ESTATE (-5)   /* call out of order (e.g. no mesh set up yet)    */
+
+typedef struct dnnmg_ctx dnnmg_ctx;
+typedef struct dnnmg_state dnnmg_state;
+typedef struct dnnmg_net dnnmg_net;
+
+/* Solver parameters.  Defaults (dnnmg_params_default) follow the readings of
+ * the paper's unstated constants: theta = 1/2 (Crank-Nicolson, Sec. 2.1),
+ * LPS parameter alpha_T = alpha0 / (nu / h_T^2 + 1/k) with alpha0 = 0.5,
+ * Newton with full steps and absolute tolerance 1e-10 on the l2 norm of the
+ * nonlinear residual, GMRES(30) with relative tolerance 1e-2 and at most 100
+ * iterations, V(2,2) cycles with additive cell-Vanka (omega = 0.8). */
+typedef struct {
+  double nu;              /* kinematic viscosity (the paper's 1/Re)              */
+  double alpha0;          /* LPS scale                                           */
+  double theta;           /* time-stepping weight, 0.5 = Crank-Nicolson          */
+  double u_mean;          /* mean inflow velocity of the parabolic profile       */
+  double channel_h;       /* channel height H of the inflow profile              */
+  double newton_tol;      /* absolute l2 tolerance on R = f - A(x)               */
+  int newton_max;         /* maximum Newton iterations per step                 */
+  double gmres_rtol;      /* relative GMRES tolerance                           */
+  int gmres_restart;      /* Krylov dimension before restart (<= 64)            */
+  int gmres_max;          /* maximum GMRES iterations per Newton step           */
+  int nu_pre, nu_post;    /* Vanka sweeps before / after the coarse correction */
+  double vanka_omega;     /* damping of the additive Vanka update               */
+  int precision;          /* 0: FP64 throughout; 1: mixed (FP32 smoother,
+                             transfers, Krylov vectors; FP64 residual, Newton
+                             update, coarse solve and Gram-Schmidt dots)        */
+  void *stream;           /* hipStream_t, or NULL for the default stream       */
+} dnnmg_params;
+
+/* Macro (coarsest) mesh.  Level 0 is this mesh refined once; finer levels are
+ * uniform refinements.  quad: 4 counter-clockwise vertex ids per cell.
+ * bedge: (v0, v1, tag) per boundary edge, tag 1 inflow, 2 wall, 3 outflow,
+ * 4 + k boundary of obstacle k.  curve: (cx, cy, a, b, phi) per obstacle, an
+ * ellipse onto which new boundary midpoints of tag 4 + k are projected. */
+typedef struct {
+  int n_vert;
+  const double *xy;       /* 2 * n_vert */
+  int n_cell;
+  const int *quad;        /* 4 * n_cell */
+  int n_bedge;
+  const int *bedge;       /* 3 * n_bedge */
+  int n_curve;
+  const double *curve;    /* 5 * n_curve */
+} dnnmg_coarse_mesh;
+
+typedef struct {
+  int newton_iters;       /* Newton iterations taken                            */
+  int gmres_iters;        /* total GMRES iterations over all Newton iterations  */
+  int gmres_iters_max;    /* largest GMRES count of a single Newton iteration  */
+  double res_initial;     /* ||R|| at the first Newton iterate                  */
+  double res_final;       /* ||R|| at the returned state                        */
+  int converged;          /* 1 if ||R|| <= newton_tol                           */
+  int fallback;           /* DNN-MG: 1 if the correction was switched off       */
+} dnnmg_step_stats;
+
+typedef struct {
+  int iters;              /* GMRES iterations                                   */
+  double res0;            /* ||rhs||                                            */
+  double res;             /* final GMRES residual estimate                      */
+} dnnmg_solve_stats;
+
+/* Fills *p with the defaults listed above (nu = 1e-3, u_mean = 1, H = 0.41,
+ * precision = 1, stream = NULL). */
+int dnnmg_params_default(dnnmg_params *p);
+
+/* Creates a context; the device is the current HIP device. */
+int dnnmg_create(const dnnmg_params *p, dnnmg_ctx **out);
+int dnnmg_destroy(dnnmg_ctx *ctx);
+/* Message of the last failed call on this context ("" if none). */
+const char *dnnmg_last_error(const dnnmg_ctx *ctx);
+/* Replaces nu, alpha0, theta, tolerances, omega and the stream; precision is
+ * fixed at creation.  Returns DNNMG_EINVAL for out-of-range values. */
+int dnnmg_set_params(dnnmg_ctx *ctx, const dnnmg_params *p);
+
+/* Mesh hierarchy setup (once): refines the macro mesh to levels
+ * 0..finest_level (Sec. 2.2 multigrid hierarchy; patches of 2x2 sibling
+ * cells, Sec. 2.1 LPS and Sec. 2.2 network patches), projecting new midpoints
+ * of obstacle edges onto the obstacle curve, and uploads all tables.
+ * finest_level in [0, 9]. */
+int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *macro, int finest_level);
+int dnnmg_level_info(const dnnmg_ctx *ctx, int level, int *n_nodes, int *n_cells,
+                     int *n_patches);
+/* Host copies of a level's node coordinates (2 * n_nodes doubles) and cells
+ * (4 * n_cells ints). */
+int dnnmg_level_coords(const dnnmg_ctx *ctx, int level, double *xy);
+int dnnmg_level_cells(const dnnmg_ctx *ctx, int level, int *quads);
+
+/* Solver state on one level: x (3 doubles per node, device-resident) and its
+ * time t.  Created as zero at t = 0. */
+int dnnmg_state_create(dnnmg_ctx *ctx, int level, dnnmg_state **out);
+int dnnmg_state_destroy(dnnmg_state *s);
+int dnnmg_state_set(dnnmg_state *s, const double *uvp, double t);
+int dnnmg_state_get(const dnnmg_state *s, double *uvp, double *t);
+/* Device address of the state's vector (owned by the state). */
+int dnnmg_state_device_ptr(dnnmg_state *s, double **uvp_dev);
+
+/* One time step t -> t + dt of the plain method on the state's level
+ * (Algorithm 1, lines 2-4): Newton (eq. newton) from x^(0) = x_{n-1} with the
+ * Dirichlet values of t + dt imposed; each Newton system solved by GMRES with
+ * one multigrid V-cycle per preconditioner application.  If the state holds a
+ * pending DNN-MG right-hand side (set by dnnmg_correct) it replaces f_n
+ * (Algorithm 1, line 3 with b_L^n).  On DNNMG_ENOCONV the state is restored
+ * to its value before the call. */
+int dnnmg_step(dnnmg_ctx *ctx, dnnmg_state *s, double dt, dnnmg_step_stats *stats);
+
+/* Assembles the Jacobian A'(x) (eq. newton) on levels 0..level at the state
+ * x (injected to coarser levels: their nodes are a prefix of the fine
+ * numbering), factorises the Vanka blocks and the level-0 LU.  dt enters
+ * through the mass term 1/k and alpha_T. */
+int dnnmg_linearize(dnnmg_ctx *ctx, const dnnmg_state *s, int level, double dt);
+/* Solves A'(x) w = rhs on `level` with the operators of the last
+ * dnnmg_linearize by GMRES + V-cycle; host in/out, 3 doubles per node. */
+int dnnmg_solve(dnnmg_ctx *ctx, int level, const double *rhs, double *w,
+                dnnmg_solve_stats *stats);
+
+/* Single-operation entry points used for parity checks (host in/out).
+ * Nonlinear residual R = f_n - A_n(x) (eqs. varform, varformv), Dirichlet
+ * velocity rows g(t_new) - x. */
+int dnnmg_residual(dnnmg_ctx *ctx, int level, const double *x, const double *x_old,
+                   double t_new, double dt, double *r);
+/* y = A'(x) w with the operator of the last dnnmg_linearize on `level`. */
+int dnnmg_jacobian_apply(dnnmg_ctx *ctx, int level, const double *w, double *y);
+/* One additive cell-Vanka sweep on `level` (operator of the last linearize). */
+int dnnmg_vanka_sweep(dnnmg_ctx *ctx, int level, const double *x, const double *b,
+                      double *x_out);
+/* One V(nu_pre, nu_post)-cycle on `level` from a zero initial guess. */
+int dnnmg_vcycle(dnnmg_ctx *ctx, int level, const double *b, double *x);
+/* Prolongation level-1 -> level (bilinear in parent coordinates) and
+ * restriction level -> level-1 (its transpose, Dirichlet rows zeroed). */
+int dnnmg_prolong(dnnmg_ctx *ctx, int level, const double *coarse, double *fine);
+int dnnmg_restrict(dnnmg_ctx *ctx, int level, const double *fine, double *coarse);
+
+/* Instrumentation (not part of the method).  When enabled, the library
+ * records a pair of HIP events on its stream around every launch of its main
+ * kernels and accumulates their durations per "kernel@Llevel" key; enabling
+ * clears earlier totals. */
+int dnnmg_profile_enable(dnnmg_ctx *ctx, int on);
+/* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
+ * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
+int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
+/* Storage statistics of a level's operator, for traffic models:
+ * q_blocks = number of 3x3 Q1 blocks (sum of the node neighbour counts),
+ * x_entries = LPS-extra pressure entries, q_slots / x_slots = the same with
+ * the SELL padding included. */
+int dnnmg_level_stats(const dnnmg_ctx *ctx, int level, long long *q_blocks, long long *x_entries,
+                      long long *q_slots, long long *x_slots);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNNMG_H */

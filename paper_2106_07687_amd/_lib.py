@@ -1,0 +1,298 @@
+"""ctypes binding of include/dnnmg.h (argument marshalling only).
+
+Every numerical step runs in the HIP kernels of libdnnmg.so; this module only
+converts numpy arrays / torch device pointers to C arguments and status codes
+to exceptions.  If the library has not been built the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdnnmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dnnmg.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
+          ESTATE: "ESTATE"}
+
+
+class DnnmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("nu", C.c_double), ("alpha0", C.c_double), ("theta", C.c_double),
+                ("u_mean", C.c_double), ("channel_h", C.c_double),
+                ("newton_tol", C.c_double), ("newton_max", C.c_int),
+                ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int), ("gmres_max", C.c_int),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vanka_omega", C.c_double),
+                ("precision", C.c_int), ("stream", C.c_void_p)]
+
+
+class CoarseMesh(C.Structure):
+    _fields_ = [("n_vert", C.c_int), ("xy", C.POINTER(C.c_double)),
+                ("n_cell", C.c_int), ("quad", C.POINTER(C.c_int)),
+                ("n_bedge", C.c_int), ("bedge", C.POINTER(C.c_int)),
+                ("n_curve", C.c_int), ("curve", C.POINTER(C.c_double))]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int), ("gmres_iters", C.c_int),
+                ("gmres_iters_max", C.c_int), ("res_initial", C.c_double),
+                ("res_final", C.c_double), ("converged", C.c_int), ("fallback", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("res0", C.c_double), ("res", C.c_double)]
+
+
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int)
+_SIGS = {
+    "dnnmg_params_default": (C.c_int, [C.POINTER(Params)]),
+    "dnnmg_create": (C.c_int, [C.POINTER(Params), C.POINTER(_P)]),
+    "dnnmg_destroy": (C.c_int, [_P]),
+    "dnnmg_last_error": (C.c_char_p, [_P]),
+    "dnnmg_set_params": (C.c_int, [_P, C.POINTER(Params)]),
+    "dnnmg_setup_mesh": (C.c_int, [_P, C.POINTER(CoarseMesh), C.c_int]),
+    "dnnmg_level_info": (C.c_int, [_P, C.c_int, _IP, _IP, _IP]),
+    "dnnmg_level_coords": (C.c_int, [_P, C.c_int, _DP]),
+    "dnnmg_level_cells": (C.c_int, [_P, C.c_int, _IP]),
+    "dnnmg_state_create": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+    "dnnmg_state_destroy": (C.c_int, [_P]),
+    "dnnmg_state_set": (C.c_int, [_P, _DP, C.c_double]),
+    "dnnmg_state_get": (C.c_int, [_P, _DP, _DP]),
+    "dnnmg_state_device_ptr": (C.c_int, [_P, C.POINTER(_P)]),
+    "dnnmg_step": (C.c_int, [_P, _P, C.c_double, C.POINTER(StepStats)]),
+    "dnnmg_linearize": (C.c_int, [_P, _P, C.c_int, C.c_double]),
+    "dnnmg_solve": (C.c_int, [_P, C.c_int, _DP, _DP, C.POINTER(SolveStats)]),
+    "dnnmg_residual": (C.c_int, [_P, C.c_int, _DP, _DP, C.c_double, C.c_double, _DP]),
+    "dnnmg_jacobian_apply": (C.c_int, [_P, C.c_int, _DP, _DP]),
+    "dnnmg_vanka_sweep": (C.c_int, [_P, C.c_int, _DP, _DP, _DP]),
+    "dnnmg_vcycle": (C.c_int, [_P, C.c_int, _DP, _DP]),
+    "dnnmg_prolong": (C.c_int, [_P, C.c_int, _DP, _DP]),
+    "dnnmg_restrict": (C.c_int, [_P, C.c_int, _DP, _DP]),
+    "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
+    "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
+                                    C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libdnnmg.so and declares the signatures (no device work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                           "`python -m paper_2106_07687_amd.build` first")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Names of all functions declared in include/dnnmg.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(dnnmg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Context:
+    """Owner of one dnnmg_ctx (the calls are the C calls of the same names)."""
+
+    def __init__(self, precision=1, stream=None, **kw):
+        self.lib = load()
+        p = Params()
+        self.lib.dnnmg_params_default(C.byref(p))
+        p.precision = precision
+        for k, v in kw.items():
+            setattr(p, k, v)
+        if stream is not None:
+            p.stream = stream
+        self.params = p
+        h = _P()
+        self._check(self.lib.dnnmg_create(C.byref(p), C.byref(h)), ctx=None)
+        self.h = h
+        self.finest = -1
+
+    def _check(self, rc, ctx="self"):
+        if rc != OK:
+            msg = self.lib.dnnmg_last_error(self.h if ctx == "self" else None)
+            raise DnnmgError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dnnmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        self._check(self.lib.dnnmg_set_params(self.h, C.byref(self.params)))
+
+    def setup_mesh(self, macro, finest_level):
+        xy = _f64(macro.xy).reshape(-1)
+        q = np.ascontiguousarray(macro.quads, dtype=np.int32).reshape(-1)
+        be = np.ascontiguousarray(macro.bedges, dtype=np.int32).reshape(-1)
+        cv = _f64(macro.curves).reshape(-1)
+        if cv.size == 0:
+            cv = np.zeros(5)
+        m = CoarseMesh(macro.n_vert, _dp(xy), macro.n_cell, q.ctypes.data_as(_IP),
+                       be.size // 3, be.ctypes.data_as(_IP), macro.curves.shape[0], _dp(cv))
+        self._check(self.lib.dnnmg_setup_mesh(self.h, C.byref(m), finest_level))
+        self.finest = finest_level
+
+    def level_info(self, level):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.lib.dnnmg_level_info(self.h, level, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def level_coords(self, level):
+        n = self.level_info(level)[0]
+        out = np.empty(2 * n)
+        self._check(self.lib.dnnmg_level_coords(self.h, level, _dp(out)))
+        return out.reshape(n, 2)
+
+    def level_cells(self, level):
+        c = self.level_info(level)[1]
+        out = np.empty(4 * c, dtype=np.int32)
+        self._check(self.lib.dnnmg_level_cells(self.h, level, out.ctypes.data_as(_IP)))
+        return out.reshape(c, 4)
+
+    def state(self, level):
+        return State(self, level)
+
+    def profile_enable(self, on=True):
+        self._check(self.lib.dnnmg_profile_enable(self.h, 1 if on else 0))
+
+    def profile_report(self):
+        """{key: (launches, total_ms)} of the profiled kernel launches."""
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.dnnmg_profile_report(self.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            k, n, ms = line.split()
+            out[k] = (int(n), float(ms))
+        return out
+
+    def level_stats(self, level):
+        v = [C.c_longlong() for _ in range(4)]
+        self._check(self.lib.dnnmg_level_stats(self.h, level, *[C.byref(x) for x in v]))
+        return dict(zip(("q_blocks", "x_entries", "q_slots", "x_slots"), (x.value for x in v)))
+
+    def step(self, state, dt):
+        st = StepStats()
+        rc = self.lib.dnnmg_step(self.h, state.h, dt, C.byref(st))
+        self._check(rc)
+        return st.as_dict()
+
+    def linearize(self, state, level, dt):
+        self._check(self.lib.dnnmg_linearize(self.h, state.h, level, dt))
+
+    def _nodes(self, level):
+        return self.level_info(level)[0]
+
+    def solve(self, level, rhs):
+        rhs = _f64(rhs)
+        out = np.empty(3 * self._nodes(level))
+        st = SolveStats()
+        self._check(self.lib.dnnmg_solve(self.h, level, _dp(rhs), _dp(out), C.byref(st)))
+        return out, dict(iters=st.iters, res0=st.res0, res=st.res)
+
+    def residual(self, level, x, x_old, t_new, dt):
+        x, xo = _f64(x), _f64(x_old)
+        out = np.empty(3 * self._nodes(level))
+        self._check(self.lib.dnnmg_residual(self.h, level, _dp(x), _dp(xo), t_new, dt, _dp(out)))
+        return out
+
+    def jacobian_apply(self, level, w):
+        w = _f64(w)
+        out = np.empty(3 * self._nodes(level))
+        self._check(self.lib.dnnmg_jacobian_apply(self.h, level, _dp(w), _dp(out)))
+        return out
+
+    def vanka_sweep(self, level, x, b):
+        x, b = _f64(x), _f64(b)
+        out = np.empty(3 * self._nodes(level))
+        self._check(self.lib.dnnmg_vanka_sweep(self.h, level, _dp(x), _dp(b), _dp(out)))
+        return out
+
+    def vcycle(self, level, b):
+        b = _f64(b)
+        out = np.empty(3 * self._nodes(level))
+        self._check(self.lib.dnnmg_vcycle(self.h, level, _dp(b), _dp(out)))
+        return out
+
+    def prolong(self, level, coarse):
+        coarse = _f64(coarse)
+        out = np.empty(3 * self._nodes(level))
+        self._check(self.lib.dnnmg_prolong(self.h, level, _dp(coarse), _dp(out)))
+        return out
+
+    def restrict(self, level, fine):
+        fine = _f64(fine)
+        out = np.empty(3 * self._nodes(level - 1))
+        self._check(self.lib.dnnmg_restrict(self.h, level, _dp(fine), _dp(out)))
+        return out
+
+
+class State:
+    def __init__(self, ctx: Context, level: int):
+        self.ctx = ctx
+        self.level = level
+        h = _P()
+        ctx._check(ctx.lib.dnnmg_state_create(ctx.h, level, C.byref(h)))
+        self.h = h
+
+    def set(self, uvp, t):
+        uvp = _f64(uvp)
+        self.ctx._check(self.ctx.lib.dnnmg_state_set(self.h, _dp(uvp), t))
+
+    def get(self):
+        n = self.ctx._nodes(self.level)
+        out = np.empty(3 * n)
+        t = C.c_double()
+        self.ctx._check(self.ctx.lib.dnnmg_state_get(self.h, _dp(out), C.byref(t)))
+        return out, t.value
+
+    def device_ptr(self):
+        p = _P()
+        self.ctx._check(self.ctx.lib.dnnmg_state_device_ptr(self.h, C.byref(p)))
+        return p.value
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.dnnmg_state_destroy(self.h)
+        self.h = None

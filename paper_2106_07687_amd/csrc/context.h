@@ -1,0 +1,196 @@
+// Library context: device copies of the mesh hierarchy, operators, and the
+// Newton / GMRES / multigrid drivers (host code that enqueues the kernels of
+// kernels.h on the context's stream).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dnnmg.h"
+#include "kernels.h"
+#include "mesh.h"
+
+namespace dnnmg {
+
+struct DnnmgError {
+  int code;
+  std::string msg;
+};
+
+// Thin owner of one hipMalloc'ed array.
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess)
+      throw DnnmgError{DNNMG_ENOMEM, "hipMalloc failed"};
+    n = count;
+  }
+  void upload(const std::vector<T> &h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty() &&
+        hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+      throw DnnmgError{DNNMG_EDEVICE, "hipMemcpyAsync H2D failed"};
+  }
+};
+
+void check(hipError_t e, const char *what);
+
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// each profiled launch, resolved (synchronising) when queried.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    std::string key;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, long>> acc;   // key -> (total ms, launches)
+  hipEvent_t take();
+  void resolve();
+  void clear();
+  ~Profiler();
+};
+
+class Ctx;
+// RAII: records a start event at construction and a stop event at destruction.
+struct ProfScope {
+  Profiler *p;
+  std::string key;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler &pr, hipStream_t st, const char *name, int level);
+  ~ProfScope();
+};
+
+struct DevLevel {
+  HostLevel h;
+  DevBuf<double2> xy;
+  DevBuf<int4> cells;
+  DevBuf<uint8_t> flag, cslot, pslot, vslot;
+  DevBuf<int> cadj_ptr, cadj, padj_ptr, padj, patch_nodes, wq, wx, oq, ox, colq, colx;
+  DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
+  DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
+  double sP_dt = -1.0, sP_nu = -1.0, sP_alpha0 = -1.0;
+  LevelView view() const;
+};
+
+// Operator storage and work vectors of one level in precision T.
+template <typename T>
+struct OpLevel {
+  DevBuf<T> JQ, JX, inv, delta, r, b, x, t;
+};
+
+class Ctx;
+
+// Newton-GMRES-multigrid solver in working precision T (float: mixed mode).
+template <typename T>
+class Solver {
+ public:
+  explicit Solver(Ctx *c) : ctx_(c) {}
+  void setup(int finest);
+  void linearize(const double *x_dev, int level, double dt);   // J, Vanka, coarse inverse
+  void vanka_sweep(int l, T *x, const T *b, bool zero_start);
+  void vcycle(int l, const T *b, T *x);                         // x = V(b), zero start
+  int gmres(int level, const T *b, T *x, double rtol, int restart, int maxit, double *res0,
+            double *res);
+  void spmv(int l, const T *x, const T *b, T *y);               // y = b - J x or J x
+  void prolong_add(int l, const T *ec, T *xf);
+  void restrict_to(int l, const T *rf, T *rc);
+  OpLevel<T> &op(int l) { return ops_[l]; }
+
+ private:
+  Ctx *ctx_;
+  int lin_level_ = -1;
+  std::vector<OpLevel<T>> ops_;
+  DevBuf<double> W_, invT_;
+  int n0_ = 0;
+  // GMRES workspace
+  int gm_level_ = -1, gm_m_ = 0;
+  DevBuf<T> V_, Z_, w_;
+  DevBuf<double> partial_, hdev_;
+  std::vector<double> hhost_;
+  void ensure_gmres(int level, int m);
+};
+
+class Ctx {
+ public:
+  dnnmg_ctx *owner = nullptr;   // the C handle wrapping this context
+  dnnmg_params prm{};
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  Profiler prof;
+  std::vector<std::unique_ptr<DevLevel>> levels;
+  int finest = -1;
+  std::unique_ptr<Solver<float>> s32;
+  std::unique_ptr<Solver<double>> s64;
+  // FP64 scratch for residual evaluation / Newton on the finest used level
+  DevBuf<double> R, xo_save, tmp64a, tmp64b;
+  DevBuf<double> red_partial, red_out;
+
+  Phys phys(double dt, double t) const {
+    Phys p;
+    p.nu = prm.nu;
+    p.theta = prm.theta;
+    p.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
+    p.alpha0 = prm.alpha0;
+    p.u_mean = prm.u_mean;
+    p.H = prm.channel_h;
+    p.t = t;
+    return p;
+  }
+  void ensure_lps(int l, double dt);
+  double norm2_f64(const double *x, int n);   // ||x||_2, synchronising
+  void residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
+                double dt, double *R);
+};
+
+struct State {
+  Ctx *ctx;
+  int level;
+  double t = 0.0;
+  DevBuf<double> x;
+  DevBuf<double> pending_rhs;   // DNN-MG right-hand side for the next step
+  bool has_pending = false;
+};
+
+inline int blocks(size_t n, int bs) { return static_cast<int>((n + bs - 1) / bs); }
+
+}  // namespace dnnmg
+
+struct dnnmg_ctx {
+  dnnmg::Ctx impl;
+};
+struct dnnmg_state {
+  dnnmg::State impl;
+};

@@ -1,0 +1,808 @@
+// gfx950 kernels of the Newton-GMRES-multigrid time step (Sec. 2.1, 2.2).
+//
+// Operator storage ("node-row SELL-64"): the Jacobian of a level is stored by
+// node rows.  Nodes are grouped in slices of 64 consecutive nodes (one
+// wavefront).  For slice s the Q1 part has wq[s] slots; slot k of node i holds
+// the 3x3 block J[(i,f),(j,g)] for the k-th node j sharing a cell with i, at
+//     JQ[((oq[s] + k) * 9 + 3 f + g) * 64 + lane],  lane = i mod 64,
+// so that one load instruction of a wavefront reads 256 (FP32) or 512 (FP64)
+// contiguous bytes.  The LPS-extra part holds the pressure-pressure entries to
+// nodes that share a patch but no cell with i (wx[s] slots, JX / colx).
+// Padding slots point at the row's own node and hold zeros.
+//
+// Vectors are interleaved, 3 values per node (u, v, p).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dnnmg {
+constexpr int kS = 64;
+
+// ---------------------------------------------------------------- geometry
+struct LevelView {
+  int N, C, NP;
+  const double2 *xy;        // N
+  const int4 *cells;        // C
+  const uint8_t *flag;      // N
+  const int *cadj_ptr, *cadj;
+  const uint8_t *cslot;     // 4 per cadj entry
+  const int *padj_ptr, *padj;
+  const uint8_t *pslot;     // 9 per padj entry
+  const int *patch_nodes;   // 9 * NP (row-major per patch)
+  const int *wq, *wx, *oq, *ox;
+  const int *colq, *colx;
+  const uint8_t *vslot;     // 16 per cell
+};
+
+struct Phys {
+  double nu, theta, inv_dt, alpha0, u_mean, H, t;
+};
+
+struct TransferView {
+  int Nc, Ec, Nf;
+  const int *edge_ends;   // 2 Ec
+  const int4 *ccells;     // coarse cells
+  const int *rptr, *ridx; // restriction lists
+  const uint8_t *cflag;   // coarse node flags
+};
+
+// Internal linkage: every translation unit that launches kernels gets its own
+// copy of the (non-template) kernels and constant tables.
+namespace {
+
+__device__ __forceinline__ double ramp(double t) {
+  return t < 1.0 ? 0.5 * (1.0 - cos(M_PI * t)) : 1.0;
+}
+
+// Reference corner signs of the bilinear basis on [-1, 1]^2.
+__device__ __constant__ double kVX[4] = {-1.0, 1.0, 1.0, -1.0};
+__device__ __constant__ double kVY[4] = {-1.0, -1.0, 1.0, 1.0};
+
+// Values, physical gradients and det J of the Q1 basis at Gauss point q.
+__device__ __forceinline__ void q1_point(const double X[4], const double Y[4], int q,
+                                         double N[4], double gx[4], double gy[4],
+                                         double &det) {
+  const double g = 0.57735026918962576451;   // 1 / sqrt(3)
+  const double xi = (q == 1 || q == 2) ? g : -g;
+  const double eta = (q >= 2) ? g : -g;
+  double dxi[4], deta[4];
+  double j11 = 0, j12 = 0, j21 = 0, j22 = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    N[a] = 0.25 * (1.0 + kVX[a] * xi) * (1.0 + kVY[a] * eta);
+    dxi[a] = 0.25 * kVX[a] * (1.0 + kVY[a] * eta);
+    deta[a] = 0.25 * kVY[a] * (1.0 + kVX[a] * xi);
+    j11 += dxi[a] * X[a];
+    j12 += deta[a] * X[a];
+    j21 += dxi[a] * Y[a];
+    j22 += deta[a] * Y[a];
+  }
+  det = j11 * j22 - j12 * j21;
+  const double id = 1.0 / det;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    gx[a] = (j22 * dxi[a] - j21 * deta[a]) * id;
+    gy[a] = (-j12 * dxi[a] + j11 * deta[a]) * id;
+  }
+}
+
+__device__ __forceinline__ void dirichlet_value(const Phys &ph, uint8_t fl, double y, double &gu,
+                                                double &gv) {
+  gu = 0.0;
+  gv = 0.0;
+  if (fl & 2) gu = 6.0 * ph.u_mean * ramp(ph.t) * y * (ph.H - y) / (ph.H * ph.H);
+}
+
+// ------------------------------------------------------------------ LPS
+// Fluctuation K = I - I_2h on a patch (lexicographic 3x3 nodes): corners 0,
+// edge nodes minus the mean of their two corners, centre minus the mean of
+// the four corners.  kK[m][q] = K_{m q}.
+__device__ __constant__ double kK[9][9] = {
+    {0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {-0.5, 1, -0.5, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {-0.5, 0, 0, 1, 0, 0, -0.5, 0, 0},
+    {-0.25, 0, -0.25, 0, 1, 0, -0.25, 0, -0.25},
+    {0, 0, -0.5, 0, 0, 1, 0, 0, -0.5},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, -0.5, 1, -0.5},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+__device__ __constant__ int kChildToPatch[4][4] = {{0, 1, 4, 3}, {1, 2, 5, 4}, {4, 5, 8, 7}, {3, 4, 7, 6}};
+
+// Patch matrix s_P = K^T (sum_T alpha_T S_T) K of the LPS term, one thread per
+// patch, stored SoA: sP[(9 q + m) * NP + P].
+__global__ void k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
+  const int P = blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= L.NP) return;
+  double S[9][9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) S[i][j] = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int4 cn = L.cells[4 * P + k];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      X[a] = L.xy[nn[a]].x;
+      Y[a] = L.xy[nn[a]].y;
+    }
+    double St[4][4] = {};
+    double area = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      area += det;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) St[a][b] += det * (gx[a] * gx[b] + gy[a] * gy[b]);
+    }
+    const double alpha = ph.alpha0 / (ph.nu / area + ph.inv_dt);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) S[kChildToPatch[k][a]][kChildToPatch[k][b]] += alpha * St[a][b];
+  }
+  // SK = S K ; out = K^T SK
+  for (int q = 0; q < 9; ++q) {
+    double row[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) {
+        double skmj = 0.0;
+#pragma unroll
+        for (int n = 0; n < 9; ++n) skmj += S[m][n] * kK[n][j];
+        s += kK[m][q] * skmj;
+      }
+      row[j] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) sP[(9 * q + j) * L.NP + P] = row[j];
+  }
+}
+
+// -------------------------------------------------------------- residual
+// R = f_n - A_n(x) for every node (eqs. varform, varformv), gathered per node
+// over the node's cells (row a of each element) and patches; Dirichlet
+// velocity rows hold g(t_new) - x.  FP64 throughout.
+__global__ void k_residual(LevelView L, Phys ph, const double *__restrict__ x,
+                           const double *__restrict__ xo, const double *__restrict__ rhs,
+                           const double *__restrict__ sP, double *__restrict__ R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const double th = ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  double Au = 0.0, Av = 0.0, Ap = 0.0;
+  for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
+    const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+    const int4 cn = L.cells[c];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4], U[4], V[4], P[4], Uo[4], Vo[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double2 p = L.xy[nn[b]];
+      X[b] = p.x;
+      Y[b] = p.y;
+      U[b] = x[3 * nn[b]];
+      V[b] = x[3 * nn[b] + 1];
+      P[b] = x[3 * nn[b] + 2];
+      Uo[b] = rhs ? 0.0 : xo[3 * nn[b]];
+      Vo[b] = rhs ? 0.0 : xo[3 * nn[b] + 1];
+    }
+    const double tho = rhs ? 0.0 : 1.0 - th;   // old-state terms only without rhs
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      double u = 0, v = 0, p = 0, uo = 0, vo = 0;
+      double ux = 0, uy = 0, vx = 0, vy = 0, uox = 0, uoy = 0, vox = 0, voy = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        u += N[b] * U[b];
+        v += N[b] * V[b];
+        p += N[b] * P[b];
+        uo += N[b] * Uo[b];
+        vo += N[b] * Vo[b];
+        ux += gx[b] * U[b];
+        uy += gy[b] * U[b];
+        vx += gx[b] * V[b];
+        vy += gy[b] * V[b];
+        uox += gx[b] * Uo[b];
+        uoy += gy[b] * Uo[b];
+        vox += gx[b] * Vo[b];
+        voy += gy[b] * Vo[b];
+      }
+      const double mu = idt * (u - uo) + th * (u * ux + v * uy) + tho * (uo * uox + vo * uoy);
+      const double mv = idt * (v - vo) + th * (u * vx + v * vy) + tho * (uo * vox + vo * voy);
+      const double Na = N[a], ga = gx[a], ha = gy[a];
+      Au += det * (mu * Na + nu * ((th * ux + tho * uox) * ga + (th * uy + tho * uoy) * ha) - p * ga);
+      Av += det * (mv * Na + nu * ((th * vx + tho * vox) * ga + (th * vy + tho * voy) * ha) - p * ha);
+      Ap += det * (ux + vy) * Na;
+    }
+  }
+  for (int e = L.padj_ptr[i]; e < L.padj_ptr[i + 1]; ++e) {
+    const int Pp = L.padj[e] / 9, q = L.padj[e] % 9;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m)
+      s += sP[(9 * q + m) * L.NP + Pp] * x[3 * L.patch_nodes[9 * Pp + m] + 2];
+    Ap += s;
+  }
+  double ru = -Au, rv = -Av;
+  if (rhs) {
+    ru += rhs[3 * i];
+    rv += rhs[3 * i + 1];
+  }
+  const uint8_t fl = L.flag[i];
+  if (fl & 1) {
+    double gu, gv;
+    dirichlet_value(ph, fl, L.xy[i].y, gu, gv);
+    ru = gu - x[3 * i];
+    rv = gv - x[3 * i + 1];
+  }
+  R[3 * i] = ru;
+  R[3 * i + 1] = rv;
+  R[3 * i + 2] = -Ap;
+}
+
+// Explicit part of the velocity rows of f_n (eq. varformv) for a given
+// velocity field v: 1/k (v, phi) - (1 - theta)((v.grad) v, phi)
+// - (1 - theta) nu (grad v, grad phi); pressure rows 0.  This is Rhs() of
+// Algorithm 1 (line 7) without external force.
+__global__ void k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const double tho = 1.0 - ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  double fu = 0.0, fv = 0.0;
+  for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
+    const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+    const int4 cn = L.cells[c];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4], U[4], V[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double2 p = L.xy[nn[b]];
+      X[b] = p.x;
+      Y[b] = p.y;
+      U[b] = xv[3 * nn[b]];
+      V[b] = xv[3 * nn[b] + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        u += N[b] * U[b];
+        v += N[b] * V[b];
+        ux += gx[b] * U[b];
+        uy += gy[b] * U[b];
+        vx += gx[b] * V[b];
+        vy += gy[b] * V[b];
+      }
+      const double Na = N[a], ga = gx[a], ha = gy[a];
+      fu += det * ((idt * u - tho * (u * ux + v * uy)) * Na - tho * nu * (ux * ga + uy * ha));
+      fv += det * ((idt * v - tho * (u * vx + v * vy)) * Na - tho * nu * (vx * ga + vy * ha));
+    }
+  }
+  out[3 * i] = fu;
+  out[3 * i + 1] = fv;
+  out[3 * i + 2] = 0.0;
+}
+
+// Sets the Dirichlet velocity values of time ph.t.
+__global__ void k_impose_bc(LevelView L, Phys ph, double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const uint8_t fl = L.flag[i];
+  if (fl & 1) {
+    double gu, gv;
+    dirichlet_value(ph, fl, L.xy[i].y, gu, gv);
+    x[3 * i] = gu;
+    x[3 * i + 1] = gv;
+  }
+}
+
+// -------------------------------------------------------------- Jacobian
+template <typename T>
+__global__ void k_fill(T *__restrict__ a, size_t n, T v) {
+  size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) a[i] = v;
+}
+
+// A_n'(x) (eq. newton): one thread per node row; each of the node's cells
+// contributes row a of its element matrix, each of its patches row q of s_P.
+// Values are computed in FP64 and stored as T into the thread's own row
+// (zeroed beforehand), so there are no write conflicts.
+template <typename T>
+__global__ void k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
+                           const double *__restrict__ sP, T *__restrict__ JQ, T *__restrict__ JX) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const int s = i / kS, lane = i % kS;
+  const double th = ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  const size_t base = static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+  const uint8_t fl = L.flag[i];
+  const bool dir = fl & 1;
+  for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
+    const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+    const int4 cn = L.cells[c];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4], U[4], V[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double2 p = L.xy[nn[b]];
+      X[b] = p.x;
+      Y[b] = p.y;
+      U[b] = x[3 * nn[b]];
+      V[b] = x[3 * nn[b] + 1];
+    }
+    double blk[4][9];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) blk[b][k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        u += N[b] * U[b];
+        v += N[b] * V[b];
+        ux += gx[b] * U[b];
+        uy += gy[b] * U[b];
+        vx += gx[b] * V[b];
+        vy += gy[b] * V[b];
+      }
+      const double Na = N[a], ga = gx[a], ha = gy[a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double Nb = N[b];
+        const double d = det * (idt * Nb * Na + th * (u * gx[b] + v * gy[b]) * Na +
+                                th * nu * (gx[b] * ga + gy[b] * ha));
+        const double r = det * th * Nb * Na;
+        blk[b][0] += d + r * ux;   // (u,u)
+        blk[b][1] += r * uy;       // (u,v)
+        blk[b][2] -= det * Nb * ga;  // (u,p)
+        blk[b][3] += r * vx;       // (v,u)
+        blk[b][4] += d + r * vy;   // (v,v)
+        blk[b][5] -= det * Nb * ha;  // (v,p)
+        blk[b][6] += det * gx[b] * Na;  // (p,u)
+        blk[b][7] += det * gy[b] * Na;  // (p,v)
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int k = L.cslot[4 * e + b];
+      T *dst = JQ + base + static_cast<size_t>(k) * 9 * kS;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (dir && r < 6) continue;
+        dst[r * kS] = static_cast<T>(static_cast<double>(dst[r * kS]) + blk[b][r]);
+      }
+    }
+  }
+  const size_t xbase = static_cast<size_t>(L.ox[s]) * kS + lane;
+  for (int e = L.padj_ptr[i]; e < L.padj_ptr[i + 1]; ++e) {
+    const int Pp = L.padj[e] / 9, q = L.padj[e] % 9;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const double v = sP[(9 * q + m) * L.NP + Pp];
+      const int sl = L.pslot[9 * e + m];
+      T *dst = (sl & 0x80) ? JX + xbase + static_cast<size_t>(sl & 0x7f) * kS
+                           : JQ + base + (static_cast<size_t>(sl) * 9 + 8) * kS;
+      *dst = static_cast<T>(static_cast<double>(*dst) + v);
+    }
+  }
+  if (dir) {
+    // identity velocity rows: the self slot holds 1 on (u,u) and (v,v)
+    for (int k = 0; k < L.wq[s]; ++k)
+      if (L.colq[(L.oq[s] + k) * kS + lane] == i) {
+        JQ[base + static_cast<size_t>(k) * 9 * kS] = static_cast<T>(1);
+        JQ[base + (static_cast<size_t>(k) * 9 + 4) * kS] = static_cast<T>(1);
+        break;
+      }
+  }
+}
+
+// -------------------------------------------------------------- SpMV
+// y = b - J x (if b) or y = J x, T precision.
+template <typename T>
+__global__ void k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                       const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const int s = i / kS, lane = i % kS;
+  const int wq = L.wq[s], wx = L.wx[s];
+  const T *jq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+  const int *cq = L.colq + static_cast<size_t>(L.oq[s]) * kS + lane;
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int k = 0; k < wq; ++k) {
+    const int j = cq[k * kS];
+    const T x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+    const T *m = jq + static_cast<size_t>(k) * 9 * kS;
+    a0 += m[0] * x0 + m[kS] * x1 + m[2 * kS] * x2;
+    a1 += m[3 * kS] * x0 + m[4 * kS] * x1 + m[5 * kS] * x2;
+    a2 += m[6 * kS] * x0 + m[7 * kS] * x1 + m[8 * kS] * x2;
+  }
+  const T *jx = JX + static_cast<size_t>(L.ox[s]) * kS + lane;
+  const int *cx = L.colx + static_cast<size_t>(L.ox[s]) * kS + lane;
+  for (int k = 0; k < wx; ++k) a2 += jx[k * kS] * x[3 * cx[k * kS] + 2];
+  if (b) {
+    y[3 * i] = b[3 * i] - a0;
+    y[3 * i + 1] = b[3 * i + 1] - a1;
+    y[3 * i + 2] = b[3 * i + 2] - a2;
+  } else {
+    y[3 * i] = a0;
+    y[3 * i + 1] = a1;
+    y[3 * i + 2] = a2;
+  }
+}
+
+// -------------------------------------------------------------- Vanka
+// Factorisation of the 12x12 cell blocks J|_{c,c} (4 nodes x 3 fields) by
+// Gauss-Jordan elimination with partial pivoting.  A group of 16 lanes works
+// on one cell; lane r < 12 holds row r = 3 a + f.  Pivot search and pivot-row
+// broadcast use wavefront shuffles.  The inverse is stored SoA:
+// inv[(12 r + j) * C + c].
+template <typename T>
+__global__ void k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restrict__ inv) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = gid >> 4;
+  const int r = threadIdx.x & 15;
+  const bool live = (c < L.C) && (r < 12);
+  double A[12], E[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    A[j] = 0.0;
+    E[j] = (j == r) ? 1.0 : 0.0;
+  }
+  if (live) {
+    const int a = r / 3, f = r % 3;
+    const int4 cn = L.cells[c];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    const int na = nn[a];
+    const int s = na / kS, lane = na % kS;
+    const T *row = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int k = L.vslot[16 * c + 4 * a + b];
+#pragma unroll
+      for (int g = 0; g < 3; ++g)
+        A[3 * b + g] = static_cast<double>(row[(static_cast<size_t>(k) * 9 + 3 * f + g) * kS]);
+    }
+  } else {
+    if (r < 12) A[r] = 1.0;
+  }
+  bool used = (r >= 12);
+  int order = 0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double val = used ? -1.0 : fabs(A[k]);
+    int idx = r;
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(val, off, 16);
+      const int oi = __shfl_xor(idx, off, 16);
+      if (ov > val || (ov == val && oi < idx)) {
+        val = ov;
+        idx = oi;
+      }
+    }
+    double prow[12], pe[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      prow[j] = __shfl(A[j], idx, 16);
+      pe[j] = __shfl(E[j], idx, 16);
+    }
+    const double piv = prow[k];
+    const double ip = piv != 0.0 ? 1.0 / piv : 0.0;
+    if (r == idx) {
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        A[j] *= ip;
+        E[j] *= ip;
+      }
+      used = true;
+      order = k;
+    } else {
+      const double fct = A[k] * ip;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        A[j] -= fct * prow[j];
+        E[j] -= fct * pe[j];
+      }
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order + j) * L.C + c] = static_cast<T>(E[j]);
+  }
+}
+
+// delta_c = inv_c r|_c, one thread per cell, stored SoA delta[(3a+f) * C + c].
+template <typename T>
+__global__ void k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
+                              T *__restrict__ delta) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L.C) return;
+  const int4 cn = L.cells[c];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  T rc[12];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
+    delta[static_cast<size_t>(i) * L.C + c] = s;
+  }
+}
+
+// x_j += omega / m_j * sum over the cells containing j of their corrections.
+template <typename T>
+__global__ void k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+    a0 += delta[static_cast<size_t>(3 * a) * L.C + c];
+    a1 += delta[static_cast<size_t>(3 * a + 1) * L.C + c];
+    a2 += delta[static_cast<size_t>(3 * a + 2) * L.C + c];
+  }
+  const T w = omega / static_cast<T>(e1 - e0);
+  x[3 * i] += w * a0;
+  x[3 * i + 1] += w * a1;
+  x[3 * i + 2] += w * a2;
+}
+
+// -------------------------------------------------------------- transfers
+
+
+// x_fine += P e_coarse (bilinear interpolation in parent coordinates).
+template <typename T>
+__global__ void k_prolong_add(TransferView tv, const T *__restrict__ ec, T *__restrict__ xf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= tv.Nf) return;
+  T v0, v1, v2;
+  if (f < tv.Nc) {
+    v0 = ec[3 * f];
+    v1 = ec[3 * f + 1];
+    v2 = ec[3 * f + 2];
+  } else if (f < tv.Nc + tv.Ec) {
+    const int a = tv.edge_ends[2 * (f - tv.Nc)], b = tv.edge_ends[2 * (f - tv.Nc) + 1];
+    v0 = T(0.5) * (ec[3 * a] + ec[3 * b]);
+    v1 = T(0.5) * (ec[3 * a + 1] + ec[3 * b + 1]);
+    v2 = T(0.5) * (ec[3 * a + 2] + ec[3 * b + 2]);
+  } else {
+    const int4 cn = tv.ccells[f - tv.Nc - tv.Ec];
+    v0 = T(0.25) * (ec[3 * cn.x] + ec[3 * cn.y] + ec[3 * cn.z] + ec[3 * cn.w]);
+    v1 = T(0.25) * (ec[3 * cn.x + 1] + ec[3 * cn.y + 1] + ec[3 * cn.z + 1] + ec[3 * cn.w + 1]);
+    v2 = T(0.25) * (ec[3 * cn.x + 2] + ec[3 * cn.y + 2] + ec[3 * cn.z + 2] + ec[3 * cn.w + 2]);
+  }
+  xf[3 * f] += v0;
+  xf[3 * f + 1] += v1;
+  xf[3 * f + 2] += v2;
+}
+
+// r_coarse = P^T r_fine with the Dirichlet velocity rows of the coarse level zeroed.
+template <typename T>
+__global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= tv.Nc) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int e = tv.rptr[j]; e < tv.rptr[j + 1]; ++e) {
+    const int f = tv.ridx[e];
+    const T w = f < tv.Nc ? T(1) : (f < tv.Nc + tv.Ec ? T(0.5) : T(0.25));
+    a0 += w * rf[3 * f];
+    a1 += w * rf[3 * f + 1];
+    a2 += w * rf[3 * f + 2];
+  }
+  if (tv.cflag[j] & 1) {
+    a0 = 0;
+    a1 = 0;
+  }
+  rc[3 * j] = a0;
+  rc[3 * j + 1] = a1;
+  rc[3 * j + 2] = a2;
+}
+
+// -------------------------------------------------------------- coarse solve
+// Dense copy of the level-0 operator (FP64, row-major n x n, n = 3 N); padding
+// slots add zeros.
+template <typename T>
+__global__ void k_dense_from_sell(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                  double *__restrict__ A, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;   // row stride n (= 2 * 3 N for the Gauss-Jordan workspace)
+  const int s = i / kS, lane = i % kS;
+  for (int k = 0; k < L.wq[s]; ++k) {
+    const int j = L.colq[(L.oq[s] + k) * kS + lane];
+    for (int f = 0; f < 3; ++f)
+      for (int g = 0; g < 3; ++g)
+        A[static_cast<size_t>(3 * i + f) * n + 3 * j + g] +=
+            static_cast<double>(JQ[(static_cast<size_t>(L.oq[s] + k) * 9 + 3 * f + g) * kS + lane]);
+  }
+  for (int k = 0; k < L.wx[s]; ++k) {
+    const int j = L.colx[(L.ox[s] + k) * kS + lane];
+    A[static_cast<size_t>(3 * i + 2) * n + 3 * j + 2] +=
+        static_cast<double>(JX[static_cast<size_t>(L.ox[s] + k) * kS + lane]);
+  }
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix
+// held in the left half of W (n x 2n, row-major; the right half must hold the
+// identity).  One workgroup; the inverse is written transposed into invT
+// (invT[k * n + i] = A^{-1}[i][k]) so that the solve reads it coalesced.
+__global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict__ W,
+                                                       double *__restrict__ invT) {
+  __shared__ double sval[1024];
+  __shared__ int sidx[1024];
+  __shared__ int piv;
+  const int tid = threadIdx.x, nt = blockDim.x, w = 2 * n;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += nt) {
+      const double v = fabs(W[static_cast<size_t>(i) * w + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    sval[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double ov = sval[tid + off];
+        const int oi = sidx[tid + off];
+        if (ov > sval[tid] || (ov == sval[tid] && oi < sidx[tid])) {
+          sval[tid] = ov;
+          sidx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) piv = sidx[0];
+    __syncthreads();
+    const int p = piv;
+    if (p != k)
+      for (int j = tid; j < w; j += nt) {
+        const double t = W[static_cast<size_t>(k) * w + j];
+        W[static_cast<size_t>(k) * w + j] = W[static_cast<size_t>(p) * w + j];
+        W[static_cast<size_t>(p) * w + j] = t;
+      }
+    __syncthreads();
+    const double ip = 1.0 / W[static_cast<size_t>(k) * w + k];
+    __syncthreads();
+    for (int j = tid; j < w; j += nt) W[static_cast<size_t>(k) * w + j] *= ip;
+    __syncthreads();
+    // eliminate column k from all other rows
+    for (int t = tid; t < n * w; t += nt) {
+      const int i = t / w, j = t % w;
+      if (i == k || j < k) continue;
+      const double fct = W[static_cast<size_t>(i) * w + k];
+      if (j == k) continue;
+      W[static_cast<size_t>(i) * w + j] -= fct * W[static_cast<size_t>(k) * w + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nt)
+      if (i != k) W[static_cast<size_t>(i) * w + k] = 0.0;
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += nt) {
+    const int i = t / n, k = t % n;
+    invT[static_cast<size_t>(k) * n + i] = W[static_cast<size_t>(i) * w + n + k];
+  }
+}
+
+__global__ void k_identity_right(int n, double *__restrict__ W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  W[static_cast<size_t>(i) * 2 * n + n + i] = 1.0;
+}
+
+// x = A^{-1} b with the stored transposed inverse (FP64 arithmetic).
+template <typename T>
+__global__ void k_dense_solve(int n, const double *__restrict__ invT, const T *__restrict__ b,
+                              T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += invT[static_cast<size_t>(k) * n + i] * static_cast<double>(b[k]);
+  x[i] = static_cast<T>(s);
+}
+
+// -------------------------------------------------------------- BLAS-1
+// partial[b * m + v] = sum over this block's chunk of V[v] . w  (FP64 accumulation)
+template <typename T>
+__global__ void k_multidot(int n, int m, const T *__restrict__ Vb, size_t ld, const T *__restrict__ w,
+                           double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const int v = blockIdx.y;
+  const T *vv = Vb + static_cast<size_t>(v) * ld;
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    s += static_cast<double>(vv[i]) * static_cast<double>(w[i]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * m + v] = sh[0];
+}
+
+// out[v] = sum_b partial[b * m + v]  (one block per v, deterministic order)
+__global__ void k_reduce_partials(int nb, int m, const double *__restrict__ partial,
+                                  double *__restrict__ out) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[static_cast<size_t>(b) * m + v];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+// w -= sum_v h[v] V[v]   (h read from device memory)
+template <typename T>
+__global__ void k_multi_axpy(int n, int m, const T *__restrict__ Vb, size_t ld,
+                             const double *__restrict__ h, T *__restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += h[v] * static_cast<double>(Vb[static_cast<size_t>(v) * ld + i]);
+  w[i] = static_cast<T>(static_cast<double>(w[i]) - s);
+}
+
+// x = sum_v y[v] Z[v]  (y on device)
+template <typename T>
+__global__ void k_combine(int n, int m, const T *__restrict__ Zb, size_t ld,
+                          const double *__restrict__ y, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += y[v] * static_cast<double>(Zb[static_cast<size_t>(v) * ld + i]);
+  x[i] = static_cast<T>(static_cast<double>(x[i]) + s);
+}
+
+template <typename T>
+__global__ void k_scale_copy(int n, double a, const T *__restrict__ x, T *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<T>(a * static_cast<double>(x[i]));
+}
+
+template <typename A, typename B>
+__global__ void k_convert(int n, const A *__restrict__ x, B *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<B>(x[i]);
+}
+
+template <typename T>
+__global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += static_cast<double>(w[i]);
+}
+
+}  // namespace
+}  // namespace dnnmg

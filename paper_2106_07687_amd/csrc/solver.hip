@@ -1,0 +1,405 @@
+// Host drivers: mesh upload, Jacobian linearisation, additive cell-Vanka,
+// V-cycle, right-preconditioned GMRES (Sec. 2.2) and the FP64 residual.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "context.h"
+
+namespace dnnmg {
+
+void check(hipError_t e, const char *what) {
+  if (e != hipSuccess)
+    throw DnnmgError{DNNMG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+#define LAUNCH_CHECK(name) check(hipGetLastError(), name)
+
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void Profiler::resolve() {
+  for (auto &r : pending) {
+    check(hipEventSynchronize(r.b), "profiler sync");
+    float ms = 0.0f;
+    check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    auto &v = acc[r.key];
+    v.first += ms;
+    v.second += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+
+void Profiler::clear() {
+  resolve();
+  acc.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto &r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler &pr, hipStream_t st, const char *name, int level)
+    : p(pr.on ? &pr : nullptr), s(st) {
+  if (!p) return;
+  key = std::string(name) + "@L" + std::to_string(level);
+  a = p->take();
+  check(hipEventRecord(a, s), "hipEventRecord");
+}
+
+ProfScope::~ProfScope() {
+  if (!p) return;
+  hipEvent_t b = p->take();
+  if (hipEventRecord(b, s) != hipSuccess) return;
+  p->pending.push_back({key, a, b});
+  if (p->pending.size() > 8192) p->resolve();
+}
+
+LevelView DevLevel::view() const {
+  LevelView v;
+  v.N = h.N;
+  v.C = h.C;
+  v.NP = h.NP;
+  v.xy = xy.p;
+  v.cells = cells.p;
+  v.flag = flag.p;
+  v.cadj_ptr = cadj_ptr.p;
+  v.cadj = cadj.p;
+  v.cslot = cslot.p;
+  v.padj_ptr = padj_ptr.p;
+  v.padj = padj.p;
+  v.pslot = pslot.p;
+  v.patch_nodes = patch_nodes.p;
+  v.wq = wq.p;
+  v.wx = wx.p;
+  v.oq = oq.p;
+  v.ox = ox.p;
+  v.colq = colq.p;
+  v.colx = colx.p;
+  v.vslot = vslot.p;
+  return v;
+}
+
+void Ctx::ensure_lps(int l, double dt) {
+  DevLevel &L = *levels[l];
+  if (L.sP.p && L.sP_dt == dt && L.sP_nu == prm.nu && L.sP_alpha0 == prm.alpha0) return;
+  if (!L.sP.p) L.sP.alloc(static_cast<size_t>(81) * L.h.NP);
+  hipLaunchKernelGGL(k_lps_patch, dim3(blocks(L.h.NP, 64)), dim3(64), 0, stream, L.view(),
+                     phys(dt, 0.0), L.sP.p);
+  LAUNCH_CHECK("k_lps_patch");
+  L.sP_dt = dt;
+  L.sP_nu = prm.nu;
+  L.sP_alpha0 = prm.alpha0;
+}
+
+double Ctx::norm2_f64(const double *x, int n) {
+  const int nb = std::min(blocks(n, 256), 1024);
+  if (red_partial.n < static_cast<size_t>(nb)) red_partial.alloc(1024);
+  if (!red_out.p) red_out.alloc(64);
+  hipLaunchKernelGGL(k_multidot<double>, dim3(nb, 1), dim3(256), 0, stream, n, 1, x, size_t(0), x,
+                     red_partial.p);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, stream, nb, 1, red_partial.p,
+                     red_out.p);
+  LAUNCH_CHECK("norm");
+  double h = 0.0;
+  check(hipMemcpyAsync(&h, red_out.p, sizeof(double), hipMemcpyDeviceToHost, stream), "norm D2H");
+  check(hipStreamSynchronize(stream), "norm sync");
+  return std::sqrt(h);
+}
+
+void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
+                   double dt, double *Rout) {
+  ensure_lps(l, dt);
+  DevLevel &L = *levels[l];
+  ProfScope ps(prof, stream, "residual", l);
+  hipLaunchKernelGGL(k_residual, dim3(blocks(L.h.N, 128)), dim3(128), 0, stream, L.view(),
+                     phys(dt, t_new), x, xo, rhs, L.sP.p, Rout);
+  LAUNCH_CHECK("k_residual");
+}
+
+// ------------------------------------------------------------------ Solver
+template <typename T>
+void Solver<T>::setup(int finest) {
+  ops_.clear();
+  ops_.resize(finest + 1);
+  for (int l = 0; l <= finest; ++l) {
+    const HostLevel &h = ctx_->levels[l]->h;
+    OpLevel<T> &o = ops_[l];
+    o.JQ.alloc(static_cast<size_t>(h.totq) * 9 * kS);
+    o.JX.alloc(static_cast<size_t>(std::max(h.totx, 1)) * kS);
+    o.inv.alloc(static_cast<size_t>(144) * h.C);
+    o.delta.alloc(static_cast<size_t>(12) * h.C);
+    o.r.alloc(3 * static_cast<size_t>(h.N));
+    o.b.alloc(3 * static_cast<size_t>(h.N));
+    o.x.alloc(3 * static_cast<size_t>(h.N));
+    o.t.alloc(3 * static_cast<size_t>(h.N));
+  }
+  n0_ = 3 * ctx_->levels[0]->h.N;
+  W_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
+  invT_.alloc(static_cast<size_t>(n0_) * n0_);
+  lin_level_ = -1;
+}
+
+template <typename T>
+void Solver<T>::linearize(const double *x_dev, int level, double dt) {
+  hipStream_t s = ctx_->stream;
+  for (int l = 0; l <= level; ++l) {
+    ctx_->ensure_lps(l, dt);
+    DevLevel &L = *ctx_->levels[l];
+    OpLevel<T> &o = ops_[l];
+    hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, o.JQ.p, o.JQ.n, T(0));
+    hipLaunchKernelGGL(k_fill<T>, dim3(256), dim3(256), 0, s, o.JX.p, o.JX.n, T(0));
+    {
+      ProfScope ps(ctx_->prof, s, "assemble", l);
+      hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(L.h.N, 64)), dim3(64), 0, s, L.view(),
+                         ctx_->phys(dt, 0.0), x_dev, L.sP.p, o.JQ.p, o.JX.p);
+    }
+    LAUNCH_CHECK("k_assemble");
+    if (l > 0) {
+      ProfScope ps(ctx_->prof, s, "vanka_factor", l);
+      hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 16, 256)),
+                         dim3(256), 0, s, L.view(), o.JQ.p, o.inv.p);
+      LAUNCH_CHECK("k_vanka_factor");
+    }
+  }
+  // level-0 dense inverse (FP64)
+  DevLevel &L0 = *ctx_->levels[0];
+  hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, W_.p, W_.n, 0.0);
+  hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
+                     ops_[0].JQ.p, ops_[0].JX.p, W_.p, 2 * n0_);
+  hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
+  {
+    ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, n0_, W_.p, invT_.p);
+  }
+  LAUNCH_CHECK("coarse inverse");
+  lin_level_ = level;
+}
+
+template <typename T>
+void Solver<T>::spmv(int l, const T *x, const T *b, T *y) {
+  DevLevel &L = *ctx_->levels[l];
+  OpLevel<T> &o = ops_[l];
+  ProfScope ps(ctx_->prof, ctx_->stream, b ? "residual_spmv" : "spmv", l);
+  hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, 256)), dim3(256), 0, ctx_->stream, L.view(),
+                     o.JQ.p, o.JX.p, x, b, y);
+  LAUNCH_CHECK("k_spmv");
+}
+
+template <typename T>
+void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
+  DevLevel &L = *ctx_->levels[l];
+  OpLevel<T> &o = ops_[l];
+  hipStream_t s = ctx_->stream;
+  const T *r = b;
+  if (!zero_start) {
+    spmv(l, x, b, o.r.p);
+    r = o.r.p;
+  }
+  {
+    ProfScope ps(ctx_->prof, s, "vanka_apply", l);
+    hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, 256)), dim3(256), 0, s, L.view(),
+                       o.inv.p, r, o.delta.p);
+  }
+  {
+    ProfScope ps(ctx_->prof, s, "vanka_update", l);
+    hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, 256)), dim3(256), 0, s, L.view(),
+                       o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x);
+  }
+  LAUNCH_CHECK("vanka");
+}
+
+template <typename T>
+void Solver<T>::prolong_add(int l, const T *ec, T *xf) {
+  DevLevel &F = *ctx_->levels[l];
+  DevLevel &Cl = *ctx_->levels[l - 1];
+  TransferView tv{F.h.Nc, F.h.Ec, F.h.N, F.edge_ends.p, Cl.cells.p, F.rptr.p, F.ridx.p, Cl.flag.p};
+  ProfScope ps(ctx_->prof, ctx_->stream, "prolong", l);
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(F.h.N, 256)), dim3(256), 0, ctx_->stream, tv, ec,
+                     xf);
+  LAUNCH_CHECK("k_prolong_add");
+}
+
+template <typename T>
+void Solver<T>::restrict_to(int l, const T *rf, T *rc) {
+  DevLevel &F = *ctx_->levels[l];
+  DevLevel &Cl = *ctx_->levels[l - 1];
+  TransferView tv{F.h.Nc, F.h.Ec, F.h.N, F.edge_ends.p, Cl.cells.p, F.rptr.p, F.ridx.p, Cl.flag.p};
+  ProfScope ps(ctx_->prof, ctx_->stream, "restrict", l);
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(F.h.Nc, 256)), dim3(256), 0, ctx_->stream, tv, rf,
+                     rc);
+  LAUNCH_CHECK("k_restrict");
+}
+
+template <typename T>
+void Solver<T>::vcycle(int l, const T *b, T *x) {
+  hipStream_t s = ctx_->stream;
+  if (l == 0) {
+    ProfScope ps(ctx_->prof, s, "coarse_solve", 0);
+    hipLaunchKernelGGL(k_dense_solve<T>, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, invT_.p, b, x);
+    LAUNCH_CHECK("k_dense_solve");
+    return;
+  }
+  DevLevel &L = *ctx_->levels[l];
+  OpLevel<T> &o = ops_[l];
+  OpLevel<T> &oc = ops_[l - 1];
+  const size_t n = 3 * static_cast<size_t>(L.h.N);
+  hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x, n, T(0));
+  const int nu1 = ctx_->prm.nu_pre, nu2 = ctx_->prm.nu_post;
+  for (int k = 0; k < nu1; ++k) vanka_sweep(l, x, b, k == 0);
+  spmv(l, x, b, o.r.p);
+  restrict_to(l, o.r.p, oc.b.p);
+  vcycle(l - 1, oc.b.p, oc.x.p);
+  prolong_add(l, oc.x.p, x);
+  for (int k = 0; k < nu2; ++k) vanka_sweep(l, x, b, false);
+}
+
+template <typename T>
+void Solver<T>::ensure_gmres(int level, int m) {
+  const size_t n = 3 * static_cast<size_t>(ctx_->levels[level]->h.N);
+  if (gm_level_ == level && gm_m_ >= m) return;
+  V_.alloc((m + 1) * n);
+  Z_.alloc(m * n);
+  w_.alloc(n);
+  partial_.alloc(static_cast<size_t>(1024) * (m + 2));
+  hdev_.alloc(static_cast<size_t>(2 * (m + 2)));
+  hhost_.assign(2 * (m + 2), 0.0);
+  gm_level_ = level;
+  gm_m_ = m;
+}
+
+// Right-preconditioned restarted GMRES (Saad) with classical Gram-Schmidt
+// applied twice (FP64 dot products) and Givens rotations.  x = 0 on entry is
+// assumed (Newton corrections); returns the iteration count.
+template <typename T>
+int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int maxit,
+                     double *res0, double *res_out) {
+  hipStream_t s = ctx_->stream;
+  const int n = 3 * ctx_->levels[level]->h.N;
+  const size_t ld = static_cast<size_t>(n);
+  restart = std::max(1, std::min(restart, 64));
+  ensure_gmres(level, restart);
+  const int nb = std::min(blocks(n, 256), 1024);
+  auto dots = [&](int m, const T *w, double *out_dev) {
+    ProfScope ps(ctx_->prof, s, "gs_dots", level);
+    hipLaunchKernelGGL(k_multidot<T>, dim3(nb, m), dim3(256), 0, s, n, m, V_.p, ld, w, partial_.p);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(m), dim3(256), 0, s, nb, m, partial_.p, out_dev);
+  };
+  hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x,
+                     static_cast<size_t>(n), T(0));
+  // beta0 = ||b||
+  hipLaunchKernelGGL(k_multidot<T>, dim3(nb, 1), dim3(256), 0, s, n, 1, b, ld, b, partial_.p);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, nb, 1, partial_.p, hdev_.p);
+  double beta0 = 0.0;
+  check(hipMemcpyAsync(&beta0, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s), "gmres D2H");
+  check(hipStreamSynchronize(s), "gmres sync");
+  beta0 = std::sqrt(beta0);
+  if (res0) *res0 = beta0;
+  if (res_out) *res_out = beta0;
+  if (beta0 == 0.0) return 0;
+  const int m = restart;
+  std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  int it = 0;
+  double resid = beta0;
+  OpLevel<T> &o = ops_[level];
+  bool first = true;
+  while (it < maxit) {
+    double beta;
+    if (first) {
+      beta = beta0;
+      hipLaunchKernelGGL(k_scale_copy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, 1.0 / beta, b,
+                         V_.p);
+    } else {
+      spmv(level, x, b, o.t.p);   // r = b - J x
+      hipLaunchKernelGGL(k_multidot<T>, dim3(nb, 1), dim3(256), 0, s, n, 1, o.t.p, ld, o.t.p,
+                         partial_.p);
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, nb, 1, partial_.p, hdev_.p);
+      check(hipMemcpyAsync(&beta, hdev_.p, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      check(hipStreamSynchronize(s), "sync");
+      beta = std::sqrt(beta);
+      hipLaunchKernelGGL(k_scale_copy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, 1.0 / beta,
+                         o.t.p, V_.p);
+    }
+    first = false;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      T *vj = V_.p + static_cast<size_t>(j) * ld;
+      T *zj = Z_.p + static_cast<size_t>(j) * ld;
+      vcycle(level, vj, zj);
+      spmv(level, zj, nullptr, w_.p);
+      // CGS2
+      dots(j + 1, w_.p, hdev_.p);
+      hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld,
+                         hdev_.p, w_.p);
+      dots(j + 1, w_.p, hdev_.p + (j + 1));
+      hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld,
+                         hdev_.p + (j + 1), w_.p);
+      hipLaunchKernelGGL(k_multidot<T>, dim3(nb, 1), dim3(256), 0, s, n, 1, w_.p, ld, w_.p,
+                         partial_.p);
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, nb, 1, partial_.p,
+                         hdev_.p + 2 * (j + 1));
+      LAUNCH_CHECK("gmres iteration");
+      check(hipMemcpyAsync(hhost_.data(), hdev_.p, sizeof(double) * (2 * (j + 1) + 1),
+                           hipMemcpyDeviceToHost, s),
+            "gmres D2H");
+      check(hipStreamSynchronize(s), "gmres sync");
+      const double hn = std::sqrt(std::max(hhost_[2 * (j + 1)], 0.0));
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hhost_[i] + hhost_[j + 1 + i];
+      H[(j + 1) * m + j] = hn;
+      if (j + 1 <= m && hn > 0.0)
+        hipLaunchKernelGGL(k_scale_copy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, 1.0 / hn,
+                           w_.p, V_.p + static_cast<size_t>(j + 1) * ld);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+        H[i * m + j] = t;
+      }
+      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+      cs[j] = H[j * m + j] / den;
+      sn[j] = H[(j + 1) * m + j] / den;
+      H[j * m + j] = den;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jend = j + 1;
+      resid = std::fabs(g[j + 1]);
+      if (resid <= rtol * beta0 || it >= maxit) break;
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int k = i + 1; k < jend; ++k) sacc -= H[i * m + k] * y[k];
+      y[i] = sacc / H[i * m + i];
+    }
+    check(hipMemcpyAsync(hdev_.p, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, s), "H2D");
+    hipLaunchKernelGGL(k_combine<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, jend, Z_.p, ld,
+                       hdev_.p, x);
+    LAUNCH_CHECK("gmres combine");
+    if (resid <= rtol * beta0) break;
+  }
+  check(hipStreamSynchronize(s), "gmres end");
+  if (res_out) *res_out = resid;
+  return it;
+}
+
+template class Solver<float>;
+template class Solver<double>;
+
+}  // namespace dnnmg

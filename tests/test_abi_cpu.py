@@ -1,0 +1,57 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dnnmg.h, and rejects bad arguments before any device work."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import paper_2106_07687_amd as P
+from paper_2106_07687_amd import _lib
+from synthetic import channel_obstacle
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load()
+    syms = P.header_symbols()
+    assert len(syms) >= 20
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_defaults_and_invalid_params():
+    lib = P.load()
+    p = _lib.Params()
+    assert lib.dnnmg_params_default(C.byref(p)) == 0
+    assert (p.theta, p.alpha0, p.nu_pre, p.nu_post, p.gmres_restart) == (0.5, 0.5, 2, 2, 30)
+    h = C.c_void_p()
+    for field, bad in (("nu", -1.0), ("theta", 0.0), ("gmres_restart", 65), ("precision", 2),
+                       ("vanka_omega", 0.0), ("gmres_rtol", 1.5)):
+        q = _lib.Params()
+        lib.dnnmg_params_default(C.byref(q))
+        setattr(q, field, bad)
+        assert lib.dnnmg_create(C.byref(q), C.byref(h)) == _lib.EINVAL, field
+    assert lib.dnnmg_create(None, C.byref(h)) == _lib.EINVAL
+
+
+def test_calls_out_of_order_and_bad_mesh_are_rejected_without_device_work():
+    ctx = P.Context(precision=0)
+    with pytest.raises(P.DnnmgError) as e:
+        ctx.level_info(0)
+    assert e.value.code == _lib.ESTATE
+    m = channel_obstacle(0)
+    with pytest.raises(P.DnnmgError) as e:
+        ctx.setup_mesh(m, 12)            # finest level out of range
+    assert e.value.code == _lib.EINVAL
+    bad = channel_obstacle(0)
+    bad.quads = bad.quads.copy()
+    bad.quads[0, 0] = 10_000             # vertex id out of range
+    with pytest.raises(P.DnnmgError) as e:
+        ctx.setup_mesh(bad, 1)
+    assert e.value.code == _lib.EINVAL
+    assert "out of range" in str(e.value)
+    bad2 = channel_obstacle(0)
+    bad2.bedges = bad2.bedges.copy()
+    bad2.bedges[0, 2] = 9                # obstacle tag without a curve
+    with pytest.raises(P.DnnmgError):
+        ctx.setup_mesh(bad2, 1)
+    ctx.close()
