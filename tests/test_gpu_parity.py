@@ -145,14 +145,16 @@ def test_fp64_time_steps_match_oracle(c1):
     solution within 1e-10 relative L2 per field at every step."""
     macro, lev, ctx, prob = c1
     L = lev[3]
-    ctx.set_params(newton_tol=1e-12)
+    # parity runs: tolerances well below the 1e-10 relative bar (the velocity
+    # is O(1e-4) during the first steps of the inflow ramp)
+    ctx.set_params(newton_tol=1e-14)
     st = ctx.state(3)
     x_ref = np.zeros(3 * L.n_nodes)
     worst = 0.0
     try:
         for n in range(1, 11):
             info = ctx.step(st, DT)
-            x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=1e-13)
+            x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=1e-15)
             xg, t = st.get()
             assert abs(t - n * DT) < 1e-15
             for f in range(3):
@@ -191,7 +193,7 @@ def test_rectangle_without_obstacle():
     # degenerate geometry: no curved boundary, a single macro cell row
     macro = rectangle(3, 1, 1.2, 0.41, nu=0.01)
     lev = mesh.hierarchy(macro, 2)
-    ctx = _ctx(0, nu=0.01)
+    ctx = _ctx(0, nu=0.01, newton_tol=1e-14)
     ctx.setup_mesh(macro, 2)
     prob = fem.Problem(nu=0.01, dt=DT)
     x = random_state(lev[2].n_nodes, 3)
@@ -200,5 +202,6 @@ def test_rectangle_without_obstacle():
     st = ctx.state(2)
     ctx.step(st, DT)
     xg, _ = st.get()
-    xr = solver.newton_step(lev[2], prob, np.zeros(3 * lev[2].n_nodes), DT, tol=1e-13)
-    assert rel(xg, xr) < 1e-9
+    xr = solver.newton_step(lev[2], prob, np.zeros(3 * lev[2].n_nodes), DT, tol=1e-15)
+    e = float(rel(xg, xr))
+    assert e < 1e-10, e
