@@ -175,6 +175,57 @@ int dnnmg_vcycle(dnnmg_ctx *ctx, int level, const double *b, double *x);
 int dnnmg_prolong(dnnmg_ctx *ctx, int level, const double *coarse, double *fine);
 int dnnmg_restrict(dnnmg_ctx *ctx, int level, const double *fine, double *coarse);
 
+/* ---------------------------------------------------------------- DNN-MG
+ * Patch network of Sec. 2.2 / Sec. 3.1: a stack of bias-free GRU cells with
+ * hidden size `hidden` and `layers` layers followed by a bias-free dense head
+ * (the structure whose parameter count 3H(I+H) + 6H^2(n-1) + HO reproduces
+ * Table 1).  Patches are the 2x2 level-L cells of one level-(L-1) cell; the
+ * network corrects the velocity on level F = L + m_levels, so a patch has
+ * S x S fine nodes with S = 2^(m_levels+1) + 1, input size
+ * I = 6 S^2 + 4 ([u, v, p, r_u, r_v, r_p] at the patch nodes, channel-major,
+ * then aspect ratio, mid-line skew, h_P / mean h_P and the patch Peclet
+ * number) and output size O = 2 S^2 (u then v corrections).
+ * Requires coarse_level >= 1 and coarse_level + m_levels <= finest level;
+ * hidden a multiple of 32.  Weights start at zero. */
+int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers,
+                     dnnmg_net **out);
+int dnnmg_net_destroy(dnnmg_net *net);
+int dnnmg_net_info(const dnnmg_net *net, int *n_in, int *n_out, int *n_patches,
+                   long long *n_params);
+/* Host FP32 weights in the order: per layer W_ih (3H x I_l, gate rows r, z, n)
+ * then W_hh (3H x H); then W_out (O x H), all row-major.  mu / sigma: the
+ * 10 standardisation pairs (6 nodal channels, 4 features), x^ = (x - mu) /
+ * sigma; out_scale: scales of the predicted u and v.  NULL leaves a part
+ * unchanged.  The device keeps FP32 masters and BF16 working copies. */
+int dnnmg_net_set_weights(dnnmg_net *net, const float *w, const float *mu, const float *sigma,
+                          const float *out_scale);
+int dnnmg_net_get_weights(const dnnmg_net *net, float *w);
+/* Starts a DNN-MG simulation from the coarse state: GRU hidden states 0 and
+ * the stored previous fine velocity v_prev = P^m x (coarse). */
+int dnnmg_net_reset(dnnmg_net *net, const dnnmg_state *coarse);
+/* One GRU time step of all patches on host inputs X (n_patches x n_in,
+ * already standardised); writes Y (n_patches x n_out) and advances the
+ * hidden states (BF16 MFMA GEMMs, FP32 accumulation and gates). */
+int dnnmg_net_forward(dnnmg_net *net, const float *X, float *Y);
+
+/* Optional host copies of the intermediate results of dnnmg_correct. */
+typedef struct {
+  float *inputs;          /* n_patches x n_in standardised inputs (FP32)     */
+  float *outputs;         /* n_patches x n_out network outputs               */
+  double *correction;     /* 2 x N_F scatter-averaged (u, v) corrections     */
+  double *rhs_coarse;     /* 3 x N_L restricted right-hand side b^L          */
+} dnnmg_correct_out;
+
+/* DNN-MG correction after a coarse step (Algorithm 1, lines 6-9): x~ = P^m x
+ * on level F; fine residual r^F = f^F(v_prev) - A^F(x~) (Dirichlet rows 0,
+ * divided by the lumped mass); per-patch network; scatter-average of the
+ * velocity corrections d (0 on Dirichlet nodes); b^F = Rhs(x~ + d) (explicit
+ * velocity rows of eq. varformv with time step dt); b^L = (P^m)^T b^F stored
+ * in the state as the right-hand side of its next dnnmg_step; v_prev <-
+ * x~ + d.  dbg may be NULL. */
+int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt,
+                  dnnmg_correct_out *dbg);
+
 /* Instrumentation (not part of the method).  When enabled, the library
  * records a pair of HIP events on its stream around every launch of its main
  * kernels and accumulates their durations per "kernel@Llevel" key; enabling

@@ -59,6 +59,11 @@ class SolveStats(C.Structure):
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int)
+_FP = C.POINTER(C.c_float)
+
+
+class CorrectOut(C.Structure):
+    _fields_ = [("inputs", _FP), ("outputs", _FP), ("correction", _DP), ("rhs_coarse", _DP)]
 _SIGS = {
     "dnnmg_params_default": (C.c_int, [C.POINTER(Params)]),
     "dnnmg_create": (C.c_int, [C.POINTER(Params), C.POINTER(_P)]),
@@ -83,6 +88,14 @@ _SIGS = {
     "dnnmg_vcycle": (C.c_int, [_P, C.c_int, _DP, _DP]),
     "dnnmg_prolong": (C.c_int, [_P, C.c_int, _DP, _DP]),
     "dnnmg_restrict": (C.c_int, [_P, C.c_int, _DP, _DP]),
+    "dnnmg_net_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_P)]),
+    "dnnmg_net_destroy": (C.c_int, [_P]),
+    "dnnmg_net_info": (C.c_int, [_P, _IP, _IP, _IP, C.POINTER(C.c_longlong)]),
+    "dnnmg_net_set_weights": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
+    "dnnmg_net_get_weights": (C.c_int, [_P, _FP]),
+    "dnnmg_net_reset": (C.c_int, [_P, _P]),
+    "dnnmg_net_forward": (C.c_int, [_P, _FP, _FP]),
+    "dnnmg_correct": (C.c_int, [_P, _P, _P, C.c_double, C.POINTER(CorrectOut)]),
     "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
@@ -266,6 +279,66 @@ class Context:
         out = np.empty(3 * self._nodes(level - 1))
         self._check(self.lib.dnnmg_restrict(self.h, level, _dp(fine), _dp(out)))
         return out
+
+
+def _fp(a):
+    return None if a is None else a.ctypes.data_as(_FP)
+
+
+class Net:
+    """Owner of one dnnmg_net (patch GRU network of one simulation)."""
+
+    def __init__(self, ctx: Context, coarse_level: int, m_levels: int, hidden: int, layers: int):
+        self.ctx = ctx
+        h = _P()
+        ctx._check(ctx.lib.dnnmg_net_create(ctx.h, coarse_level, m_levels, hidden, layers, C.byref(h)))
+        self.h = h
+        a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_longlong()
+        ctx._check(ctx.lib.dnnmg_net_info(h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        self.n_in, self.n_out, self.n_patches, self.n_params = a.value, b.value, c.value, d.value
+        self.hidden, self.layers = hidden, layers
+        self.coarse_level, self.m_levels = coarse_level, m_levels
+
+    def set_weights(self, w=None, mu=None, sigma=None, out_scale=None):
+        cv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        w, mu, sigma, out_scale = cv(w), cv(mu), cv(sigma), cv(out_scale)
+        if w is not None and w.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} weights, got {w.size}")
+        self.ctx._check(self.ctx.lib.dnnmg_net_set_weights(self.h, _fp(w), _fp(mu), _fp(sigma),
+                                                           _fp(out_scale)))
+
+    def get_weights(self):
+        w = np.empty(self.n_params, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.dnnmg_net_get_weights(self.h, _fp(w)))
+        return w
+
+    def reset(self, state):
+        self.ctx._check(self.ctx.lib.dnnmg_net_reset(self.h, state.h))
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.empty((self.n_patches, self.n_out), dtype=np.float32)
+        self.ctx._check(self.ctx.lib.dnnmg_net_forward(self.h, _fp(X), _fp(Y)))
+        return Y
+
+    def correct(self, state, dt, debug=False):
+        if not debug:
+            self.ctx._check(self.ctx.lib.dnnmg_correct(self.ctx.h, state.h, self.h, dt, None))
+            return None
+        nf = self.ctx._nodes(self.coarse_level + self.m_levels)
+        nl = self.ctx._nodes(self.coarse_level)
+        out = dict(inputs=np.empty((self.n_patches, self.n_in), dtype=np.float32),
+                   outputs=np.empty((self.n_patches, self.n_out), dtype=np.float32),
+                   correction=np.empty((nf, 2)), rhs_coarse=np.empty(3 * nl))
+        d = CorrectOut(_fp(out["inputs"]), _fp(out["outputs"]), _dp(out["correction"]),
+                       _dp(out["rhs_coarse"]))
+        self.ctx._check(self.ctx.lib.dnnmg_correct(self.ctx.h, state.h, self.h, dt, C.byref(d)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.dnnmg_net_destroy(self.h)
+        self.h = None
 
 
 class State:

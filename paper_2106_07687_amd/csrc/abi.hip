@@ -92,13 +92,15 @@ int step_impl(Ctx &c, State &st, double dt, dnnmg_step_stats *stats) {
   hipStream_t s = c.stream;
   const double t_new = st.t + dt;
   check(hipMemcpyAsync(c.xo_save.p, st.x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "save");
-  hipLaunchKernelGGL(k_impose_bc, dim3(blocks(N, 256)), dim3(256), 0, s, c.levels[l]->view(),
-                     c.phys(dt, t_new), st.x.p);
   dnnmg_step_stats loc{};
   bool ok = false;
   OpLevel<T> &o = S.op(l);
+  bool use_pending = st.has_pending;
+retry:
+  hipLaunchKernelGGL(k_impose_bc, dim3(blocks(N, 256)), dim3(256), 0, s, c.levels[l]->view(),
+                     c.phys(dt, t_new), st.x.p);
   for (int it = 0; it <= c.prm.newton_max; ++it) {
-    c.residual(l, st.x.p, c.xo_save.p, st.has_pending ? st.pending_rhs.p : nullptr, t_new, dt,
+    c.residual(l, st.x.p, c.xo_save.p, use_pending ? st.pending_rhs.p : nullptr, t_new, dt,
                c.R.p);
     const double nr = c.norm2_f64(c.R.p, n);
     if (it == 0) loc.res_initial = nr;
@@ -119,6 +121,16 @@ int step_impl(Ctx &c, State &st, double dt, dnnmg_step_stats *stats) {
     loc.gmres_iters_max = std::max(loc.gmres_iters_max, k);
     hipLaunchKernelGGL(k_add_to_f64<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, o.x.p, st.x.p);
     check(hipGetLastError(), "newton update");
+  }
+  if (!ok && use_pending) {
+    // switch-off of the network for this step (Sec. 3.3): redo the step with
+    // the plain right-hand side f_n(x_{n-1})
+    check(hipMemcpyAsync(st.x.p, c.xo_save.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s),
+          "fallback restore");
+    use_pending = false;
+    loc.fallback = 1;
+    loc.gmres_iters_max = 0;
+    goto retry;
   }
   loc.converged = ok ? 1 : 0;
   if (stats) *stats = loc;

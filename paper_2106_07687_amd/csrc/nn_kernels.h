@@ -1,0 +1,232 @@
+// gfx950 kernels of the DNN-MG patch network (Algorithm 1, lines 6-9):
+// patch gather with input standardisation, BF16 MFMA GEMMs with FP32
+// accumulation, GRU gate update, output scatter-average, and the backward
+// counterparts used by BPTT training.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace dnnmg {
+
+struct PatchView {
+  int B;              // patches
+  int S2;             // fine nodes per patch (S * S)
+  int NF;             // fine nodes
+  const int *grid;    // B * S2 fine node ids (lexicographic in the parent frame)
+  const int *nadj_ptr, *nadj;   // fine node -> (patch * S2 + q)
+  const double *inv_mass;       // NF, 1 / lumped mass
+  const double *feat;           // 4 * B: aspect, skew, h_rel, h
+  const uint8_t *flag;          // NF fine node flags
+};
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ float sigmoidf_(float a) { return 1.0f / (1.0f + __expf(-a)); }
+
+// C[M x N] (fp32, ldc) = A[M x K] * B[N x K]^T (+ C if accumulate), A and B
+// BF16 row-major with leading dimensions lda, ldb (elements, multiples of 8),
+// K a multiple of 32.  64 x 64 tile per workgroup of 256 threads (4 waves,
+// each 32 x 32 as 2 x 2 MFMA 16x16x16 blocks), BK = 32 staged through LDS.
+constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
+
+__global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const uint16_t *__restrict__ A,
+                                                      int lda, const uint16_t *__restrict__ Bm, int ldb,
+                                                      float *__restrict__ Cm, int ldc, int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lc = (tid & 3) * 8;   // loader: row, 8-element chunk
+  for (int k0 = 0; k0 < K; k0 += GBK) {
+    uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+    if (bm + lr < M) va = *reinterpret_cast<const uint4 *>(A + static_cast<size_t>(bm + lr) * lda + k0 + lc);
+    if (bn + lr < N) vb = *reinterpret_cast<const uint4 *>(Bm + static_cast<size_t>(bn + lr) * ldb + k0 + lc);
+    __syncthreads();
+    *reinterpret_cast<uint4 *>(&As[lr][lc]) = va;
+    *reinterpret_cast<uint4 *>(&Bs[lr][lc]) = vb;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      bf16x4 a[2], b[2];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
+        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
+        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
+                      static_cast<short>(pa[3])};
+        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
+                      static_cast<short>(pb[3])};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = bn + wn * 32 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M) {
+          float *c = Cm + static_cast<size_t>(row) * ldc + col;
+          *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+    }
+}
+
+// GRU gate update for one layer (gate rows r, z, n):
+// r = s(gi_r + gh_r), z = s(gi_z + gh_z), n = tanh(gi_n + r gh_n),
+// h = (1 - z) n + z h.  Optionally stores r, z, n, gh_n for the backward pass.
+__global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const float *__restrict__ Gh,
+                            float *__restrict__ h, uint16_t *__restrict__ hb, int ldhb,
+                            float *__restrict__ save) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(B) * H) return;
+  const int b = static_cast<int>(t / H), j = static_cast<int>(t % H);
+  const float *gi = Gi + static_cast<size_t>(b) * 3 * H;
+  const float *gh = Gh + static_cast<size_t>(b) * 3 * H;
+  const float r = sigmoidf_(gi[j] + gh[j]);
+  const float z = sigmoidf_(gi[H + j] + gh[H + j]);
+  const float n = tanhf(gi[2 * H + j] + r * gh[2 * H + j]);
+  const float hp = h[t];
+  const float hn = (1.0f - z) * n + z * hp;
+  h[t] = hn;
+  hb[static_cast<size_t>(b) * ldhb + j] = f2bf(hn);
+  if (save) {
+    float *s = save + static_cast<size_t>(b) * 4 * H;
+    s[j] = r;
+    s[H + j] = z;
+    s[2 * H + j] = n;
+    s[3 * H + j] = gh[2 * H + j];
+  }
+}
+
+// Patch gather (Algorithm 1, l. 7 inputs): one workgroup per patch writes the
+// standardised input row [u, v, p, r_u, r_v, r_p at the S2 patch nodes;
+// aspect, skew, h_rel, Peclet] as BF16 into X (ld = ldx, padding zeroed).
+// Residual rows are divided by the lumped mass; Dirichlet velocity residual
+// rows are zero.
+__global__ void __launch_bounds__(128) k_patch_gather(PatchView pv, const double *__restrict__ xt,
+                                                      const double *__restrict__ R, const float *__restrict__ mu,
+                                                      const float *__restrict__ sg, double nu,
+                                                      uint16_t *__restrict__ X, int ldx, float *__restrict__ Xf) {
+  __shared__ double smax[128];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int S2 = pv.S2;
+  uint16_t *row = X + static_cast<size_t>(p) * ldx;
+  float *rowf = Xf ? Xf + static_cast<size_t>(p) * ldx : nullptr;
+  double sp = 0.0;
+  for (int q = tid; q < S2; q += blockDim.x) {
+    const int i = pv.grid[static_cast<size_t>(p) * S2 + q];
+    const double u = xt[3 * i], v = xt[3 * i + 1], pr = xt[3 * i + 2];
+    const double im = pv.inv_mass[i];
+    const bool dir = pv.flag[i] & 1;
+    const double ru = dir ? 0.0 : R[3 * i] * im, rv = dir ? 0.0 : R[3 * i + 1] * im;
+    const double rp = R[3 * i + 2] * im;
+    const double vals[6] = {u, v, pr, ru, rv, rp};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float s = static_cast<float>((vals[c] - mu[c]) / sg[c]);
+      row[c * S2 + q] = f2bf(s);
+      if (rowf) rowf[c * S2 + q] = s;
+    }
+    sp = fmax(sp, sqrt(u * u + v * v));
+  }
+  smax[tid] = sp;
+  __syncthreads();
+  for (int off = 64; off > 0; off >>= 1) {
+    if (tid < off) smax[tid] = fmax(smax[tid], smax[tid + off]);
+    __syncthreads();
+  }
+  const int I = 6 * S2 + 4;
+  if (tid < 4) {
+    const double *f = pv.feat + static_cast<size_t>(p) * 4;
+    const double val = tid < 3 ? f[tid] : smax[0] * f[3] / nu;
+    const float s = static_cast<float>((val - mu[6 + tid]) / sg[6 + tid]);
+    row[6 * S2 + tid] = f2bf(s);
+    if (rowf) rowf[6 * S2 + tid] = s;
+  }
+  for (int c = I + tid; c < ldx; c += blockDim.x) {
+    row[c] = 0;
+    if (rowf) rowf[c] = 0.0f;
+  }
+}
+
+// Scatter-average of the predicted corrections to fine nodes, zero on
+// Dirichlet nodes, then v_c = x~ + d (velocity), pressure 0:
+// vc[3 i + f] = x~[3 i + f] + s_f * mean_{(p, q) ∋ i} Y[p][f * S2 + q].
+__global__ void k_patch_scatter(PatchView pv, const float *__restrict__ Y, int ldy,
+                                const float *__restrict__ oscale, const double *__restrict__ xt,
+                                double *__restrict__ vc, double *__restrict__ d_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pv.NF) return;
+  double du = 0.0, dv = 0.0;
+  const int e0 = pv.nadj_ptr[i], e1 = pv.nadj_ptr[i + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int p = pv.nadj[e] / pv.S2, q = pv.nadj[e] % pv.S2;
+    du += Y[static_cast<size_t>(p) * ldy + q];
+    dv += Y[static_cast<size_t>(p) * ldy + pv.S2 + q];
+  }
+  const double inv = e1 > e0 ? 1.0 / (e1 - e0) : 0.0;
+  du *= inv * oscale[0];
+  dv *= inv * oscale[1];
+  if (pv.flag[i] & 1) {
+    du = 0.0;
+    dv = 0.0;
+  }
+  vc[3 * i] = xt[3 * i] + du;
+  vc[3 * i + 1] = xt[3 * i + 1] + dv;
+  vc[3 * i + 2] = 0.0;
+  if (d_out) {
+    d_out[2 * i] = du;
+    d_out[2 * i + 1] = dv;
+  }
+}
+
+__global__ void k_f32_to_bf16(size_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = f2bf(a[i]);
+}
+
+// Copy of a row-major [rows x cols] FP32 matrix into a BF16 matrix with
+// leading dimension ld >= cols (padding columns zero).
+__global__ void k_pack_bf16(int rows, int cols, const float *__restrict__ a, int ld,
+                            uint16_t *__restrict__ b) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(rows) * ld) return;
+  const int r = static_cast<int>(t / ld), c = static_cast<int>(t % ld);
+  b[t] = c < cols ? f2bf(a[static_cast<size_t>(r) * cols + c]) : 0;
+}
+
+}  // namespace
+}  // namespace dnnmg
