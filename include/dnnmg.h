@@ -226,6 +226,26 @@ typedef struct {
 int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt,
                   dnnmg_correct_out *dbg);
 
+/* Training (loss of eq. loss): X holds T x B standardised input rows
+ * (T time steps of B patch sequences, n_in floats each, step-major), D the
+ * T x B x n_out target rows in network output units.  Loss =
+ * sum_t sum_b ||Y_t,b - D_t,b||^2 / B with the hidden state of every sequence
+ * starting at 0 (independent of the network's inference state).  Exact
+ * backpropagation through time with the forward pass recomputed from
+ * checkpoints every `ckpt` steps; BF16 MFMA GEMMs with FP32 accumulation,
+ * FP32 gates and gradients.
+ * dnnmg_net_gradient: host inputs, writes the FP32 gradient (n_params, flat
+ * weight order) and the loss; no update.
+ * dnnmg_train_step / _dev: one Adam step (beta = 0.9, 0.999, eps = 1e-8,
+ * bias-corrected) on the FP32 masters with learning rate lr, then refreshes
+ * the BF16 copies; _dev takes device pointers (borrowed for the call). */
+int dnnmg_net_gradient(dnnmg_net *net, const float *X, const float *D, int T, int B, int ckpt,
+                       float *grad, float *loss);
+int dnnmg_train_step(dnnmg_net *net, const float *X, const float *D, int T, int B, int ckpt,
+                     float lr, float *loss);
+int dnnmg_train_step_dev(dnnmg_net *net, const float *X_dev, const float *D_dev, int T, int B,
+                         int ckpt, float lr, float *loss);
+
 /* Instrumentation (not part of the method).  When enabled, the library
  * records a pair of HIP events on its stream around every launch of its main
  * kernels and accumulates their durations per "kernel@Llevel" key; enabling

@@ -96,6 +96,9 @@ _SIGS = {
     "dnnmg_net_reset": (C.c_int, [_P, _P]),
     "dnnmg_net_forward": (C.c_int, [_P, _FP, _FP]),
     "dnnmg_correct": (C.c_int, [_P, _P, _P, C.c_double, C.POINTER(CorrectOut)]),
+    "dnnmg_net_gradient": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, _FP, _FP]),
+    "dnnmg_train_step": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
+    "dnnmg_train_step_dev": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
@@ -320,6 +323,33 @@ class Net:
         Y = np.empty((self.n_patches, self.n_out), dtype=np.float32)
         self.ctx._check(self.ctx.lib.dnnmg_net_forward(self.h, _fp(X), _fp(Y)))
         return Y
+
+    def gradient(self, X, D, ckpt=8):
+        """X: (T, B, n_in), D: (T, B, n_out) host arrays -> (loss, grad)."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        D = np.ascontiguousarray(D, dtype=np.float32)
+        T, B = X.shape[:2]
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        self.ctx._check(self.ctx.lib.dnnmg_net_gradient(self.h, _fp(X), _fp(D), T, B, ckpt, _fp(g),
+                                                        C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, D, lr=1e-3, ckpt=8):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        D = np.ascontiguousarray(D, dtype=np.float32)
+        T, B = X.shape[:2]
+        loss = C.c_float()
+        self.ctx._check(self.ctx.lib.dnnmg_train_step(self.h, _fp(X), _fp(D), T, B, ckpt, lr,
+                                                      C.byref(loss)))
+        return loss.value
+
+    def train_step_dev(self, X_ptr, D_ptr, T, B, lr=1e-3, ckpt=8):
+        """Device-pointer variant (e.g. torch tensors' data_ptr())."""
+        loss = C.c_float()
+        self.ctx._check(self.ctx.lib.dnnmg_train_step_dev(self.h, X_ptr, D_ptr, T, B, ckpt, lr,
+                                                          C.byref(loss)))
+        return loss.value
 
     def correct(self, state, dt, debug=False):
         if not debug:

@@ -4,43 +4,11 @@
 #include <cmath>
 #include <cstring>
 
-#include "context.h"
-#include "nn_kernels.h"
+#include "net.h"
 
 using namespace dnnmg;
 
 namespace dnnmg {
-
-// Device-resident patch network of one simulation (weights, GRU state,
-// work buffers) for patches of level L and fine level F = L + m.
-struct Net {
-  Ctx *ctx = nullptr;
-  int L = 0, m = 0, F = 0, S = 0, S2 = 0, B = 0;
-  int I = 0, H = 0, layers = 0, O = 0, K0 = 0;   // K0: padded input width
-  long long nparam = 0;
-  std::vector<long long> off_ih, off_hh;       // offsets in the flat weight vector
-  long long off_out = 0;
-  DevBuf<float> w32;                           // FP32 master weights (flat)
-  std::vector<DevBuf<uint16_t>> wih_b, whh_b;  // BF16 working copies
-  DevBuf<uint16_t> wout_b;
-  DevBuf<float> mu, sg, oscale;
-  std::vector<DevBuf<float>> h;                // [B x H] per layer
-  std::vector<DevBuf<uint16_t>> hb;
-  DevBuf<uint16_t> X;
-  DevBuf<float> Xf, Gi, Gh, Y;
-  // fine-level vectors (FP64)
-  std::vector<DevBuf<double>> xt;              // prolongation chain, index l - L
-  DevBuf<double> vprev, vc, bF, dcorr;
-  std::vector<DevBuf<double>> rchain;          // restriction chain
-  // patch tables
-  DevBuf<int> grid, nadj_ptr, nadj;
-  DevBuf<double> inv_mass, feat;
-  bool has_vprev = false;
-  PatchView view() const {
-    const DevLevel &LF = *ctx->levels[F];
-    return PatchView{B, S2, LF.h.N, grid.p, nadj_ptr.p, nadj.p, inv_mass.p, feat.p, LF.flag.p};
-  }
-};
 
 namespace {
 
@@ -145,7 +113,9 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const 
   check(hipGetLastError(), "k_gemm_nt_bf16");
 }
 
-void repack(Net &n) {
+}  // namespace
+
+void net_repack(Net &n) {
   hipStream_t s = n.ctx->stream;
   for (int l = 0; l < n.layers; ++l) {
     const int il = l == 0 ? n.I : n.H, kl = l == 0 ? n.K0 : n.H;
@@ -159,6 +129,8 @@ void repack(Net &n) {
                      n.H, n.w32.p + n.off_out, n.H, n.wout_b.p);
   check(hipGetLastError(), "repack");
 }
+
+namespace {
 
 // One GRU time step of all patches on the BF16 input rows in n.X.
 void net_forward(Net &n) {
@@ -214,9 +186,6 @@ void prolong_chain(Net &n, const double *xL) {
 }  // namespace
 }  // namespace dnnmg
 
-struct dnnmg_net {
-  dnnmg::Net impl;
-};
 
 extern "C" {
 
@@ -293,7 +262,7 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
     n.vc.alloc(nf);
     n.bF.alloc(nf);
     n.dcorr.alloc(2 * static_cast<size_t>(c.levels[n.F]->h.N));
-    repack(n);
+    net_repack(n);
     zero_state(n);
     check(hipStreamSynchronize(c.stream), "net create");
   } catch (const DnnmgError &e) {
@@ -342,7 +311,7 @@ int dnnmg_net_set_weights(dnnmg_net *net, const float *w, const float *mu, const
     if (sigma) check(hipMemcpyAsync(n.sg.p, sigma, sizeof(float) * 10, hipMemcpyHostToDevice, c.stream), "sg");
     if (out_scale)
       check(hipMemcpyAsync(n.oscale.p, out_scale, sizeof(float) * 2, hipMemcpyHostToDevice, c.stream), "os");
-    repack(n);
+    net_repack(n);
     check(hipStreamSynchronize(c.stream), "set weights");
   } catch (const DnnmgError &e) {
     c.last_error = e.msg;

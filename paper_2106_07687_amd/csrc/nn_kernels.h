@@ -213,6 +213,160 @@ __global__ void k_patch_scatter(PatchView pv, const float *__restrict__ Y, int l
   }
 }
 
+// General-stride BF16 GEMM for the backward pass:
+// C_z[m][n] = sum_{k in slice z} A(m, k) B(n, k), A(m, k) = A[m sAm + k sAk],
+// B(n, k) = B[n sBn + k sBk]; any M, N, K (guarded).  Split-K over
+// gridDim.z: slice z covers k in [z kz, min(K, (z + 1) kz)) and writes (or,
+// with accumulate and gridDim.z == 1, adds to) C + z * zstride.
+__global__ void __launch_bounds__(256) k_gemm_bf16_strided(int M, int N, int K, int kz,
+                                                           const uint16_t *__restrict__ A, long sAm, long sAk,
+                                                           const uint16_t *__restrict__ Bm, long sBn, long sBk,
+                                                           float *__restrict__ Cm, int ldc, long zstride,
+                                                           int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+  const int kb = blockIdx.z * kz, ke = min(K, kb + kz);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    uint16_t va[8], vb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid * 8 + e;   // 0..2047 over a 64 x 32 tile
+      const int r = idx >> 5, cc = idx & 31;
+      const int k = k0 + cc;
+      va[e] = (bm + r < M && k < ke) ? A[(bm + r) * sAm + k * sAk] : uint16_t(0);
+      vb[e] = (bn + r < N && k < ke) ? Bm[(bn + r) * sBn + k * sBk] : uint16_t(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid * 8 + e;
+      As[idx >> 5][idx & 31] = va[e];
+      Bs[idx >> 5][idx & 31] = vb[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      bf16x4 a[2], b[2];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
+        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
+        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
+                      static_cast<short>(pa[3])};
+        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
+                      static_cast<short>(pb[3])};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  float *Cz = Cm + blockIdx.z * zstride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = bn + wn * 32 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M) {
+          float *c = Cz + static_cast<size_t>(row) * ldc + col;
+          *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+    }
+}
+
+// dst[i] (+)= sum_z part[z * zstride + i] for an M x N block with leading
+// dimension ld (fixed z order: deterministic).
+__global__ void k_reduce_split(int M, int N, int ld, int Z, long zstride, const float *__restrict__ part,
+                               float *__restrict__ dst, int ldd, int accumulate) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(M) * N) return;
+  const int m = static_cast<int>(t / N), n = static_cast<int>(t % N);
+  float s = 0.0f;
+  for (int z = 0; z < Z; ++z) s += part[z * zstride + static_cast<size_t>(m) * ld + n];
+  float *d = dst + static_cast<size_t>(m) * ldd + n;
+  *d = accumulate ? *d + s : s;
+}
+
+// Backward of one GRU gate update.  In: g = dL/dh_t (total), saved gates
+// (r, z, n, gh_n) and h_{t-1}.  Out: dgi = dL/d(W_ih x) (3H), dgh =
+// dL/d(W_hh h_{t-1}) (3H) as FP32 and BF16, dhp = g * z (the direct part of
+// dL/dh_{t-1}; the GEMM dgh W_hh is added to it afterwards).
+__global__ void k_gru_gates_bwd(int B, int H, const float *__restrict__ g, const float *__restrict__ save,
+                                const float *__restrict__ hprev, uint16_t *__restrict__ dgi_b,
+                                uint16_t *__restrict__ dgh_b, float *__restrict__ dhp) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(B) * H) return;
+  const int b = static_cast<int>(t / H), j = static_cast<int>(t % H);
+  const float *s = save + static_cast<size_t>(b) * 4 * H;
+  const float r = s[j], z = s[H + j], n = s[2 * H + j], ghn = s[3 * H + j];
+  const float gg = g[t], hp = hprev[t];
+  const float dz = gg * (hp - n);
+  const float dn = gg * (1.0f - z);
+  const float dan = dn * (1.0f - n * n);
+  const float dr = dan * ghn;
+  const float dar = dr * r * (1.0f - r);
+  const float daz = dz * z * (1.0f - z);
+  const size_t o = static_cast<size_t>(b) * 3 * H;
+  dgi_b[o + j] = f2bf(dar);
+  dgi_b[o + H + j] = f2bf(daz);
+  dgi_b[o + 2 * H + j] = f2bf(dan);
+  dgh_b[o + j] = f2bf(dar);
+  dgh_b[o + H + j] = f2bf(daz);
+  dgh_b[o + 2 * H + j] = f2bf(dan * r);
+  dhp[t] = gg * z;
+}
+
+// dY = 2 (Y - D) / B (BF16 copy) and per-block partial sums of (Y - D)^2.
+__global__ void k_loss_grad(int B, int O, const float *__restrict__ Y, const float *__restrict__ D,
+                            uint16_t *__restrict__ dYb, double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const size_t n = static_cast<size_t>(B) * O;
+  double s = 0.0;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float d = Y[i] - D[i];
+    s += static_cast<double>(d) * d;
+    dYb[i] = f2bf(2.0f * d / static_cast<float>(B));
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Adam on the FP32 masters (bias-corrected, step t >= 1).
+__global__ void k_adam(size_t n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
 __global__ void k_f32_to_bf16(size_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = f2bf(a[i]);

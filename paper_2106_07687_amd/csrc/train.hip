@@ -1,0 +1,308 @@
+// BPTT training of the patch GRU network (loss of eq. loss, Sec. 2.2) with
+// gradient checkpointing, BF16 MFMA GEMMs (FP32 accumulation) and Adam on
+// FP32 master weights.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "net.h"
+
+using namespace dnnmg;
+
+namespace {
+
+void gemm_nt(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+             float *C, int ldc) {
+  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
+  hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0);
+  check(hipGetLastError(), "k_gemm_nt_bf16");
+}
+
+// C (+)= A(m,k) B(n,k) with general strides; split-K through `part`.
+void gemm_strided(hipStream_t s, int M, int N, int K, const uint16_t *A, long sAm, long sAk,
+                  const uint16_t *B, long sBn, long sBk, float *C, int ldc, bool acc, DevBuf<float> &part) {
+  const long tiles = static_cast<long>((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  int Z = 1;
+  while (tiles * Z < 512 && K / (Z * 2) >= 1024) Z *= 2;
+  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, Z);
+  if (Z == 1) {
+    hipLaunchKernelGGL(k_gemm_bf16_strided, grid, dim3(256), 0, s, M, N, K, K, A, sAm, sAk, B, sBn, sBk, C, ldc,
+                       0L, acc ? 1 : 0);
+    check(hipGetLastError(), "k_gemm_bf16_strided");
+    return;
+  }
+  const int kz = ((K + Z - 1) / Z + GBK - 1) / GBK * GBK;
+  const size_t need = static_cast<size_t>(Z) * M * N;
+  if (part.n < need) part.alloc(need);
+  hipLaunchKernelGGL(k_gemm_bf16_strided, grid, dim3(256), 0, s, M, N, K, kz, A, sAm, sAk, B, sBn, sBk, part.p,
+                     N, static_cast<long>(M) * N, 0);
+  hipLaunchKernelGGL(k_reduce_split, dim3(blocks(static_cast<size_t>(M) * N, 256)), dim3(256), 0, s, M, N, N, Z,
+                     static_cast<long>(M) * N, part.p, C, ldc, acc ? 1 : 0);
+  check(hipGetLastError(), "split-K GEMM");
+}
+
+struct Trainer {
+  int T = 0, Bt = 0, seg = 0, nseg = 0;
+  DevBuf<uint16_t> Xb;                       // T x Bt x K0
+  std::vector<DevBuf<float>> hck;            // per layer: (nseg) x Bt x H checkpoints
+  std::vector<DevBuf<float>> hs32;           // per layer: (seg + 1) x Bt x H
+  std::vector<DevBuf<uint16_t>> hs16;        // per layer: (seg + 1) x Bt x H
+  std::vector<DevBuf<float>> sv;             // per layer: seg x Bt x 4H saved gates
+  std::vector<DevBuf<uint16_t>> dgi, dgh;    // per layer: seg x Bt x 3H
+  std::vector<DevBuf<float>> dh;             // per layer: Bt x H
+  DevBuf<float> dhp, Gi, Gh, Yseg;           // Yseg: seg x Bt x O
+  DevBuf<uint16_t> dYb;                      // seg x Bt x O
+  DevBuf<float> grad, part;
+  DevBuf<double> lpart;
+};
+
+void ensure(Net &n, Trainer &tr, int T, int Bt, int seg) {
+  if (tr.T == T && tr.Bt == Bt && tr.seg == seg) return;
+  tr.T = T;
+  tr.Bt = Bt;
+  tr.seg = seg;
+  tr.nseg = (T + seg - 1) / seg;
+  const size_t bh = static_cast<size_t>(Bt) * n.H;
+  tr.Xb.alloc(static_cast<size_t>(T) * Bt * n.K0);
+  tr.hck.resize(n.layers);
+  tr.hs32.resize(n.layers);
+  tr.hs16.resize(n.layers);
+  tr.sv.resize(n.layers);
+  tr.dgi.resize(n.layers);
+  tr.dgh.resize(n.layers);
+  tr.dh.resize(n.layers);
+  for (int l = 0; l < n.layers; ++l) {
+    tr.hck[l].alloc(static_cast<size_t>(tr.nseg) * bh);
+    tr.hs32[l].alloc(static_cast<size_t>(seg + 1) * bh);
+    tr.hs16[l].alloc(static_cast<size_t>(seg + 1) * bh);
+    tr.sv[l].alloc(static_cast<size_t>(seg) * 4 * bh);
+    tr.dgi[l].alloc(static_cast<size_t>(seg) * 3 * bh);
+    tr.dgh[l].alloc(static_cast<size_t>(seg) * 3 * bh);
+    tr.dh[l].alloc(bh);
+  }
+  tr.dhp.alloc(bh);
+  tr.Gi.alloc(3 * bh);
+  tr.Gh.alloc(3 * bh);
+  tr.Yseg.alloc(static_cast<size_t>(seg) * Bt * n.O);
+  tr.dYb.alloc(static_cast<size_t>(seg) * Bt * n.O);
+  tr.grad.alloc(static_cast<size_t>(n.nparam));
+  tr.lpart.alloc(1024);
+}
+
+// One forward GRU step for all layers.  hin32/hin16: state before the step
+// (per layer), hout32/hout16: state after (may alias hin for in-place);
+// save: gate storage per layer (or null); Y: head output (or null).
+void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector<float *> &h32,
+              std::vector<uint16_t *> &h16_in, std::vector<uint16_t *> &h16_out, std::vector<float *> &save,
+              float *Y) {
+  const int H3 = 3 * n.H;
+  for (int l = 0; l < n.layers; ++l) {
+    const uint16_t *in = l == 0 ? x : h16_out[l - 1];
+    const int K = l == 0 ? n.K0 : n.H;
+    gemm_nt(s, tr.Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
+    gemm_nt(s, tr.Bt, H3, n.H, h16_in[l], n.H, n.whh_b[l].p, n.H, tr.Gh.p, H3);
+    hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(tr.Bt) * n.H, 256)), dim3(256), 0, s, tr.Bt,
+                       n.H, tr.Gi.p, tr.Gh.p, h32[l], h16_out[l], n.H, save[l]);
+  }
+  if (Y) gemm_nt(s, tr.Bt, n.O, n.H, h16_out[n.layers - 1], n.H, n.wout_b.p, n.H, Y, n.O);
+  check(hipGetLastError(), "fwd_step");
+}
+
+// Loss and gradient (into tr.grad) by BPTT with checkpoints every `seg` steps.
+double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
+  Ctx &c = *n.ctx;
+  hipStream_t s = c.stream;
+  const int T = tr.T, Bt = tr.Bt, seg = tr.seg, L = n.layers, H = n.H;
+  const size_t bh = static_cast<size_t>(Bt) * H;
+  hipLaunchKernelGGL(k_pack_bf16, dim3(blocks(static_cast<size_t>(T) * Bt * n.K0, 256)), dim3(256), 0, s,
+                     T * Bt, n.I, X, n.K0, tr.Xb.p);
+  hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.grad.p, tr.grad.n, 0.0f);
+  // forward sweep storing checkpoints (running state in hs32[.][0] / hs16[.][0])
+  std::vector<float *> h32(L), sv_null(L, nullptr);
+  std::vector<uint16_t *> h16(L);
+  for (int l = 0; l < L; ++l) {
+    h32[l] = tr.hs32[l].p;
+    h16[l] = tr.hs16[l].p;
+    hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, h32[l], bh, 0.0f);
+    hipLaunchKernelGGL(k_fill<uint16_t>, dim3(1024), dim3(256), 0, s, h16[l], bh, uint16_t(0));
+  }
+  for (int t = 0; t < T; ++t) {
+    if (t % seg == 0)
+      for (int l = 0; l < L; ++l)
+        check(hipMemcpyAsync(tr.hck[l].p + static_cast<size_t>(t / seg) * bh, h32[l], bh * sizeof(float),
+                             hipMemcpyDeviceToDevice, s),
+              "checkpoint");
+    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h16, h16, sv_null, nullptr);
+  }
+  for (int l = 0; l < L; ++l)
+    hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.dh[l].p, bh, 0.0f);
+  double loss = 0.0;
+  std::vector<double> lp(1024);
+  const int lblocks = std::min(1024, blocks(static_cast<size_t>(Bt) * n.O, 256));
+  for (int sg = tr.nseg - 1; sg >= 0; --sg) {
+    const int t0 = sg * seg, ns = std::min(seg, T - t0);
+    // recompute the segment from its checkpoint, keeping every state
+    for (int l = 0; l < L; ++l) {
+      check(hipMemcpyAsync(tr.hs32[l].p, tr.hck[l].p + static_cast<size_t>(sg) * bh, bh * sizeof(float),
+                           hipMemcpyDeviceToDevice, s),
+            "restore");
+      hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks(bh, 256)), dim3(256), 0, s, bh, tr.hs32[l].p, tr.hs16[l].p);
+    }
+    for (int k = 0; k < ns; ++k) {
+      std::vector<float *> hk(L), svk(L);
+      std::vector<uint16_t *> hin(L), hout(L);
+      for (int l = 0; l < L; ++l) {
+        check(hipMemcpyAsync(tr.hs32[l].p + (k + 1) * bh, tr.hs32[l].p + k * bh, bh * sizeof(float),
+                             hipMemcpyDeviceToDevice, s),
+              "state copy");
+        hk[l] = tr.hs32[l].p + (k + 1) * bh;
+        hin[l] = tr.hs16[l].p + k * bh;
+        hout[l] = tr.hs16[l].p + (k + 1) * bh;
+        svk[l] = tr.sv[l].p + static_cast<size_t>(k) * 4 * bh;
+      }
+      fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t0 + k) * Bt * n.K0, hk, hin, hout, svk,
+               tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O);
+    }
+    // backward through the segment
+    for (int k = ns - 1; k >= 0; --k) {
+      const int t = t0 + k;
+      uint16_t *dY = tr.dYb.p + static_cast<size_t>(k) * Bt * n.O;
+      hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, s, Bt, n.O,
+                         tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O, D + static_cast<size_t>(t) * Bt * n.O, dY,
+                         tr.lpart.p);
+      check(hipMemcpyAsync(lp.data(), tr.lpart.p, sizeof(double) * lblocks, hipMemcpyDeviceToHost, s), "loss");
+      check(hipStreamSynchronize(s), "loss sync");
+      for (int b = 0; b < lblocks; ++b) loss += lp[b];
+      // dh_top += dY W_out
+      gemm_strided(s, Bt, H, n.O, dY, n.O, 1, n.wout_b.p, 1, H, tr.dh[L - 1].p, H, true, tr.part);
+      for (int l = L - 1; l >= 0; --l) {
+        uint16_t *dgi = tr.dgi[l].p + static_cast<size_t>(k) * 3 * bh;
+        uint16_t *dgh = tr.dgh[l].p + static_cast<size_t>(k) * 3 * bh;
+        hipLaunchKernelGGL(k_gru_gates_bwd, dim3(blocks(bh, 256)), dim3(256), 0, s, Bt, H, tr.dh[l].p,
+                           tr.sv[l].p + static_cast<size_t>(k) * 4 * bh, tr.hs32[l].p + k * bh, dgi, dgh,
+                           tr.dhp.p);
+        check(hipMemcpyAsync(tr.dh[l].p, tr.dhp.p, bh * sizeof(float), hipMemcpyDeviceToDevice, s), "dh");
+        // dh_{t-1} = g z + dgh W_hh
+        gemm_strided(s, Bt, H, 3 * H, dgh, 3 * H, 1, n.whh_b[l].p, 1, H, tr.dh[l].p, H, true, tr.part);
+        if (l > 0)   // gradient into the layer below: dgi W_ih
+          gemm_strided(s, Bt, H, 3 * H, dgi, 3 * H, 1, n.wih_b[l].p, 1, H, tr.dh[l - 1].p, H, true, tr.part);
+      }
+    }
+    // weight gradients of the segment: K = ns * Bt rows at once
+    const int Ks = ns * Bt;
+    float *g = tr.grad.p;
+    gemm_strided(s, n.O, H, Ks, tr.dYb.p, 1, n.O, tr.hs16[L - 1].p + bh, 1, H, g + n.off_out, H, true, tr.part);
+    for (int l = 0; l < L; ++l) {
+      const int Il = l == 0 ? n.I : H;
+      const uint16_t *in = l == 0 ? tr.Xb.p + static_cast<size_t>(t0) * Bt * n.K0 : tr.hs16[l - 1].p + bh;
+      const long ldin = l == 0 ? n.K0 : H;
+      gemm_strided(s, 3 * H, Il, Ks, tr.dgi[l].p, 1, 3 * H, in, 1, ldin, g + n.off_ih[l], Il, true, tr.part);
+      gemm_strided(s, 3 * H, H, Ks, tr.dgh[l].p, 1, 3 * H, tr.hs16[l].p, 1, H, g + n.off_hh[l], H, true, tr.part);
+    }
+  }
+  return loss / Bt;
+}
+
+struct TrainState {
+  Trainer tr;
+  DevBuf<float> m, v, Xd, Dd;
+  long step = 0;
+};
+
+}  // namespace
+
+namespace dnnmg {
+TrainStateHolder::~TrainStateHolder() { delete static_cast<TrainState *>(p); }
+}  // namespace dnnmg
+
+namespace {
+TrainState &tstate(Net &n) {
+  if (!n.train.p) n.train.p = new TrainState();
+  return *static_cast<TrainState *>(n.train.p);
+}
+
+int check_batch(Net &n, int T, int Bt, int ckpt) {
+  if (T < 1 || Bt < 1 || ckpt < 1 || T > 4096 || Bt > (1 << 22)) {
+    n.ctx->last_error = "invalid batch shape";
+    return DNNMG_EINVAL;
+  }
+  return DNNMG_OK;
+}
+
+int run_grad(Net &n, const float *X, const float *D, int T, int Bt, int ckpt, bool host, float *grad_out,
+             float *loss_out, float lr, bool update) {
+  Ctx &c = *n.ctx;
+  try {
+    TrainState &ts = tstate(n);
+    ensure(n, ts.tr, T, Bt, std::min(ckpt, T));
+    const float *Xd = X, *Dd = D;
+    if (host) {
+      const size_t nx = static_cast<size_t>(T) * Bt * n.I, nd = static_cast<size_t>(T) * Bt * n.O;
+      if (ts.Xd.n < nx) ts.Xd.alloc(nx);
+      if (ts.Dd.n < nd) ts.Dd.alloc(nd);
+      check(hipMemcpyAsync(ts.Xd.p, X, nx * sizeof(float), hipMemcpyHostToDevice, c.stream), "X H2D");
+      check(hipMemcpyAsync(ts.Dd.p, D, nd * sizeof(float), hipMemcpyHostToDevice, c.stream), "D H2D");
+      Xd = ts.Xd.p;
+      Dd = ts.Dd.p;
+    }
+    const double loss = loss_and_grad(n, ts.tr, Xd, Dd);
+    if (update) {
+      if (!ts.m.p) {
+        ts.m.alloc(n.nparam);
+        ts.v.alloc(n.nparam);
+        hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, c.stream, ts.m.p, ts.m.n, 0.0f);
+        hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, c.stream, ts.v.p, ts.v.n, 0.0f);
+      }
+      ts.step += 1;
+      const float b1 = 0.9f, b2 = 0.999f;
+      const float c1 = 1.0f - std::pow(b1, static_cast<float>(ts.step));
+      const float c2 = 1.0f - std::pow(b2, static_cast<float>(ts.step));
+      hipLaunchKernelGGL(k_adam, dim3(blocks(n.nparam, 256)), dim3(256), 0, c.stream, static_cast<size_t>(n.nparam),
+                         n.w32.p, ts.tr.grad.p, ts.m.p, ts.v.p, lr, b1, b2, 1e-8f, c1, c2);
+      check(hipGetLastError(), "k_adam");
+      net_repack(n);
+    }
+    if (grad_out)
+      check(hipMemcpyAsync(grad_out, ts.tr.grad.p, sizeof(float) * n.nparam, hipMemcpyDeviceToHost, c.stream),
+            "grad D2H");
+    check(hipStreamSynchronize(c.stream), "train sync");
+    if (loss_out) *loss_out = static_cast<float>(loss);
+  } catch (const DnnmgError &e) {
+    c.last_error = e.msg;
+    return e.code;
+  }
+  return DNNMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dnnmg_net_gradient(dnnmg_net *net, const float *X, const float *D, int T, int B, int ckpt,
+                       float *grad, float *loss) {
+  if (!net || !X || !D) return DNNMG_EINVAL;
+  Net &n = net_of(net);
+  const int e = check_batch(n, T, B, ckpt);
+  if (e) return e;
+  return run_grad(n, X, D, T, B, ckpt, true, grad, loss, 0.0f, false);
+}
+
+int dnnmg_train_step(dnnmg_net *net, const float *X, const float *D, int T, int B, int ckpt, float lr,
+                     float *loss) {
+  if (!net || !X || !D || !(lr > 0)) return DNNMG_EINVAL;
+  Net &n = net_of(net);
+  const int e = check_batch(n, T, B, ckpt);
+  if (e) return e;
+  return run_grad(n, X, D, T, B, ckpt, true, nullptr, loss, lr, true);
+}
+
+int dnnmg_train_step_dev(dnnmg_net *net, const float *X_dev, const float *D_dev, int T, int B, int ckpt,
+                         float lr, float *loss) {
+  if (!net || !X_dev || !D_dev || !(lr > 0)) return DNNMG_EINVAL;
+  Net &n = net_of(net);
+  const int e = check_batch(n, T, B, ckpt);
+  if (e) return e;
+  return run_grad(n, X_dev, D_dev, T, B, ckpt, false, nullptr, loss, lr, true);
+}
+
+}  // extern "C"
