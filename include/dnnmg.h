@@ -226,6 +226,14 @@ typedef struct {
 int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt,
                   dnnmg_correct_out *dbg);
 
+/* Algorithm 1, lines 8-9 for a given fine velocity (teacher forcing when
+ * generating training data from fine solutions): b^F = Rhs(v_fine) on level
+ * F, b^L = (P^m)^T b^F stored as the coarse state's pending right-hand side,
+ * and v_prev <- v_fine.  v_fine: host, 3 doubles per fine node (pressure
+ * ignored). */
+int dnnmg_rhs_from_fine(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
+                        double dt);
+
 /* Training (loss of eq. loss): X holds T x B standardised input rows
  * (T time steps of B patch sequences, n_in floats each, step-major), D the
  * T x B x n_out target rows in network output units.  Loss =

@@ -96,6 +96,7 @@ _SIGS = {
     "dnnmg_net_reset": (C.c_int, [_P, _P]),
     "dnnmg_net_forward": (C.c_int, [_P, _FP, _FP]),
     "dnnmg_correct": (C.c_int, [_P, _P, _P, C.c_double, C.POINTER(CorrectOut)]),
+    "dnnmg_rhs_from_fine": (C.c_int, [_P, _P, _P, _DP, C.c_double]),
     "dnnmg_net_gradient": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, _FP, _FP]),
     "dnnmg_train_step": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_train_step_dev": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
@@ -323,6 +324,10 @@ class Net:
         Y = np.empty((self.n_patches, self.n_out), dtype=np.float32)
         self.ctx._check(self.ctx.lib.dnnmg_net_forward(self.h, _fp(X), _fp(Y)))
         return Y
+
+    def rhs_from_fine(self, state, v_fine, dt):
+        v = _f64(v_fine)
+        self.ctx._check(self.ctx.lib.dnnmg_rhs_from_fine(self.ctx.h, state.h, self.h, _dp(v), dt))
 
     def gradient(self, X, D, ckpt=8):
         """X: (T, B, n_in), D: (T, B, n_out) host arrays -> (loss, grad)."""

@@ -183,11 +183,59 @@ void prolong_chain(Net &n, const double *xL) {
   check(hipGetLastError(), "prolong_chain");
 }
 
+// b^F = Rhs(n.vc) on level F (Algorithm 1, l. 8), b^L = (P^m)^T b^F into the
+// coarse state's pending right-hand side (l. 9), then v_prev <- n.vc.
+void rhs_and_restrict(Net &n, State &st, double dt) {
+  Ctx &c = *n.ctx;
+  hipStream_t s = c.stream;
+  const DevLevel &LF = *c.levels[n.F];
+  {
+    ProfScope ps(c.prof, s, "dnnmg_rhs", n.F);
+    c.ensure_lps(n.F, dt);
+    hipLaunchKernelGGL(k_rhs, dim3(blocks(LF.h.N, 128)), dim3(128), 0, s, LF.view(), c.phys(dt, st.t + dt),
+                       n.vc.p, n.bF.p);
+    check(hipGetLastError(), "k_rhs");
+  }
+  const double *src = n.bF.p;
+  for (int l = n.F; l > n.L; --l) {
+    DevLevel &Fl = *c.levels[l];
+    DevLevel &Cl = *c.levels[l - 1];
+    TransferView tv{Fl.h.Nc, Fl.h.Ec, Fl.h.N, Fl.edge_ends.p, Cl.cells.p, Fl.rptr.p, Fl.ridx.p, Cl.flag.p};
+    double *dst = (l - 1 == n.L) ? st.pending_rhs.p : n.rchain[l - 1 - n.L].p;
+    hipLaunchKernelGGL(k_restrict<double>, dim3(blocks(Fl.h.Nc, 256)), dim3(256), 0, s, tv, src, dst);
+    src = dst;
+  }
+  check(hipGetLastError(), "restrict chain");
+  std::swap(n.vprev, n.vc);
+  st.has_pending = true;
+}
+
 }  // namespace
 }  // namespace dnnmg
 
-
 extern "C" {
+
+int dnnmg_rhs_from_fine(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
+                        double dt) {
+  if (!ctx || !coarse || !net || !v_fine || !(dt > 0)) return DNNMG_EINVAL;
+  Net &n = net->impl;
+  Ctx &c = ctx->impl;
+  if (n.ctx != &c || coarse->impl.ctx != &c || coarse->impl.level != n.L) {
+    c.last_error = "state / network do not belong to this context and coarse level";
+    return DNNMG_EINVAL;
+  }
+  try {
+    const size_t nf = 3 * static_cast<size_t>(c.levels[n.F]->h.N);
+    check(hipMemcpyAsync(n.vc.p, v_fine, nf * sizeof(double), hipMemcpyHostToDevice, c.stream), "v H2D");
+    rhs_and_restrict(n, coarse->impl, dt);
+    n.has_vprev = true;
+    check(hipStreamSynchronize(c.stream), "rhs_from_fine");
+  } catch (const DnnmgError &e) {
+    c.last_error = e.msg;
+    return e.code;
+  }
+  return DNNMG_OK;
+}
 
 int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers,
                      dnnmg_net **out) {
@@ -413,26 +461,7 @@ int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt
                          n.vc.p, n.dcorr.p);
       check(hipGetLastError(), "k_patch_scatter");
     }
-    {
-      ProfScope ps(c.prof, s, "dnnmg_rhs", n.F);
-      c.ensure_lps(n.F, dt);
-      hipLaunchKernelGGL(k_rhs, dim3(blocks(NF, 128)), dim3(128), 0, s, LF.view(), c.phys(dt, st.t + dt),
-                         n.vc.p, n.bF.p);
-      check(hipGetLastError(), "k_rhs");
-    }
-    // b^L = (P^m)^T b^F
-    const double *src = n.bF.p;
-    for (int l = n.F; l > n.L; --l) {
-      DevLevel &Fl = *c.levels[l];
-      DevLevel &Cl = *c.levels[l - 1];
-      TransferView tv{Fl.h.Nc, Fl.h.Ec, Fl.h.N, Fl.edge_ends.p, Cl.cells.p, Fl.rptr.p, Fl.ridx.p, Cl.flag.p};
-      double *dst = (l - 1 == n.L) ? st.pending_rhs.p : n.rchain[l - 1 - n.L].p;
-      hipLaunchKernelGGL(k_restrict<double>, dim3(blocks(Fl.h.Nc, 256)), dim3(256), 0, s, tv, src, dst);
-      src = dst;
-    }
-    check(hipGetLastError(), "restrict chain");
-    std::swap(n.vprev, n.vc);   // v_prev <- v~ + d
-    st.has_pending = true;
+    rhs_and_restrict(n, st, dt);
     if (dbg) {
       if (dbg->inputs) {
         std::vector<float> tmp(static_cast<size_t>(n.B) * n.K0);
