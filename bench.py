@@ -1,10 +1,16 @@
-"""Benchmark: time steps/s of the hot path on one MI355X.
+"""Benchmark: time steps/s of DNN-MG against full-depth GMG on one MI355X.
 
-Workload (default): the mixed-precision plain method at scale -- channel with
-one seeded circular obstacle (seed 0), Re = 100, macro mesh refined to level 7
-(1.38M cells, ~1.38M nodes, ~4.1M DoFs), dt = 0.005, FP32 smoother, transfers
-and Krylov vectors with FP64 Newton residual, update, coarse solve and
-Gram-Schmidt dots.  W untimed steps from rest, then K timed steps.
+Workload: channel with one seeded circular obstacle (seed 0), Re = 100,
+dt = 0.005, mixed precision (FP32 smoother, transfers and Krylov vectors;
+FP64 Newton residual, update, coarse solve and Gram-Schmidt dots).
+  * full-depth GMG: Newton-GMRES-multigrid on level 7 (1.38M cells, ~4.1M
+    DoFs), W untimed steps from rest, then K timed steps;
+  * DNN-MG: Newton-GMRES-multigrid on level 5 plus the patch GRU (hidden 128,
+    2 layers, BF16 MFMA) correcting level 7 (Algorithm 1), W + K steps;
+`value` is the DNN-MG rate; the GMG rate, the speed-up and the velocity
+errors of DNN-MG and of the plain level-5 method against the level-7
+solution are reported in `config`.  `train` times BPTT iterations at the
+training batch shape (8192 sequences x 32 steps).
 
 Prints one JSON line (see the field list at the bottom).  `roofline` is
 computed from per-kernel HIP-event timings recorded by the library on its
@@ -70,25 +76,78 @@ def cpu_baseline(seed: int, level: int, fine_level: int, dt: float):
                        f"{scale:.0f} to the level-{fine_level} step")}
 
 
+def run_steps(ctx, st, steps, dt, net=None):
+    """`steps` time steps (plain, or DNN-MG: coarse step + correction)."""
+    stats = []
+    for _ in range(steps):
+        stats.append(ctx.step(st, dt))
+        if net is not None:
+            net.correct(st, dt)
+    return stats
+
+
+def velocity_error(ctx, xl, level, fine_level, x_fine, corr=None):
+    """Relative l2 error of the fine-level velocity (P^m v^L [+ d]) against
+    the fine solution."""
+    import numpy as np
+    x = xl
+    for l in range(level + 1, fine_level + 1):
+        x = ctx.prolong(l, x)
+    v = x.reshape(-1, 3)[:, :2]
+    if corr is not None:
+        v = v + corr
+    ref = x_fine.reshape(-1, 3)[:, :2]
+    return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+
+
+def roofline_from(prof, ctx, level, kernels_with_bytes):
+    best = None
+    for key, (cnt, ms) in prof.items():
+        name, lv = key.split("@L")
+        if int(lv) != level or name not in kernels_with_bytes:
+            continue
+        b = kernel_bytes(ctx, name, level)
+        if b is None:
+            continue
+        if best is None or ms > best[2]:
+            best = (name, cnt, ms, b)
+    if not best:
+        return None
+    name, cnt, ms, b = best
+    avg_s = ms / cnt / 1e3
+    ach = b / avg_s / 1e9
+    return {"bound": "hbm", "kernel": f"{name}@L{level}", "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_us": round(avg_s * 1e6, 2), "launches": cnt,
+            "bytes_per_launch": b}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--level", type=int, default=7)
+    ap.add_argument("--coarse-level", type=int, default=5)
+    ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--layers", type=int, default=2)
     ap.add_argument("--dt", type=float, default=0.005)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-level", type=int, default=4)
+    ap.add_argument("--train-iters", type=int, default=3)
+    ap.add_argument("--train-seq", type=int, default=32)
+    ap.add_argument("--train-batch", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import paper_2106_07687_amd as P
-    from synthetic import channel_obstacle
+    from synthetic import channel_obstacle, gru_weights
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -97,59 +156,100 @@ def main():
     t0 = time.perf_counter()
     ctx.setup_mesh(macro, args.level)
     setup_s = time.perf_counter() - t0
-    n_nodes, n_cells, _ = ctx.level_info(args.level)
-    st = ctx.state(args.level)
-    print(f"[bench] setup level {args.level}: {n_nodes} nodes, {n_cells} cells, "
-          f"{setup_s:.1f} s", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        info = ctx.step(st, args.dt)
-        print(f"[bench] warmup step {k}: {info}", file=sys.stderr, flush=True)
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        stats.append(ctx.step(st, args.dt))
-    stream.synchronize()
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    prof = ctx.profile_report()
-    ctx.profile_enable(False)
-    for k, s in enumerate(stats):
-        print(f"[bench] step {k}: {s}", file=sys.stderr, flush=True)
+    nF, cF, _ = ctx.level_info(args.level)
+    nL = ctx.level_info(args.coarse_level)[0]
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    log(f"setup levels 0..{args.level}: fine {nF} nodes / {cF} cells, {setup_s:.1f} s")
 
-    # dominant kernel on the finest level with a traffic model
-    best = None
-    for key, (cnt, ms) in prof.items():
-        name, lv = key.split("@L")
-        if int(lv) != args.level:
-            continue
-        b = kernel_bytes(ctx, name, args.level)
-        if b is None:
-            continue
-        if best is None or ms > best[2]:
-            best = (name, cnt, ms, b)
-    roof = None
-    if best:
-        name, cnt, ms, b = best
-        avg_s = ms / cnt / 1e3
-        ach = b / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": f"{name}@L{args.level}", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_us": round(avg_s * 1e6, 2), "launches": cnt,
-                "bytes_per_launch": b}
-    for key in sorted(prof, key=lambda k: -prof[k][1])[:12]:
-        cnt, ms = prof[key]
-        print(f"[bench] kernel {key}: {cnt} launches, {ms:.2f} ms total, "
-              f"{1e3 * ms / cnt:.1f} us avg", file=sys.stderr, flush=True)
+    # ---- full-depth GMG on the fine level (reference and baseline)
+    sf = ctx.state(args.level)
+    for k, s_ in enumerate(run_steps(ctx, sf, args.warmup, args.dt)):
+        log(f"gmg warmup {k}: {s_}")
+    ctx.profile_enable(True)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    g_stats = run_steps(ctx, sf, args.steps, args.dt)
+    stream.synchronize()
+    g_sec = time.perf_counter() - t0
+    g_prof = ctx.profile_report()
+    ctx.profile_enable(False)
+    for k, s_ in enumerate(g_stats):
+        log(f"gmg step {k}: {s_}")
+    x_fine, _ = sf.get()
+
+    # ---- DNN-MG: Newton-GMRES-MG on the coarse level + patch GRU on the fine level
+    m = args.level - args.coarse_level
+    net = P.Net(ctx, args.coarse_level, m, args.hidden, args.layers)
+    w = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
+    net.set_weights(w, mu=np.zeros(10), sigma=np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
+                    out_scale=np.array([1e-3, 1e-3]))
+    sc = ctx.state(args.coarse_level)
+    net.reset(sc)
+    for k, s_ in enumerate(run_steps(ctx, sc, args.warmup, args.dt, net)):
+        log(f"dnnmg warmup {k}: {s_}")
+    ctx.profile_enable(True)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    d_stats = run_steps(ctx, sc, args.steps, args.dt, net)
+    stream.synchronize()
+    d_sec = time.perf_counter() - t0
+    d_prof = ctx.profile_report()
+    ctx.profile_enable(False)
+    for k, s_ in enumerate(d_stats):
+        log(f"dnnmg step {k}: {s_}")
+    out = net.correct(sc, args.dt, debug=True)   # correction of the last state (untimed)
+    xl, _ = sc.get()
+    err_dnn = velocity_error(ctx, xl, args.coarse_level, args.level, x_fine, out["correction"])
+    err_mgl = None
+    # plain MG(L) for the error comparison (untimed)
+    sp = ctx.state(args.coarse_level)
+    run_steps(ctx, sp, args.warmup + args.steps, args.dt)
+    xp, _ = sp.get()
+    err_mgl = velocity_error(ctx, xp, args.coarse_level, args.level, x_fine)
+
+    for name, prof in (("gmg", g_prof), ("dnnmg", d_prof)):
+        for key in sorted(prof, key=lambda k: -prof[k][1])[:14]:
+            cnt, ms = prof[key]
+            log(f"{name} kernel {key}: {cnt} launches, {ms:.2f} ms total, {1e3 * ms / cnt:.1f} us avg")
+    roof = roofline_from(g_prof, ctx, args.level, ("spmv", "residual_spmv", "vanka_apply", "vanka_update"))
+    # MFMA utilisation of the network's input GEMM (layer 0)
+    mfma = None
+    if "gru_gemm_in@L0" in d_prof:
+        cnt, ms = d_prof["gru_gemm_in@L0"]
+        flop = 2.0 * net.n_patches * 3 * args.hidden * ((net.n_in + 31) // 32 * 32)
+        tf = flop / (ms / cnt / 1e3) / 1e12
+        mfma = {"kernel": "gru_gemm_in@L0", "achieved": round(tf, 2), "peak": 2500.0,
+                "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5), "avg_us": round(1e3 * ms / cnt, 2)}
+    # ---- BPTT training throughput at the training batch shape (synthetic rows)
+    train = None
+    if args.train_iters > 0:
+        T, B = args.train_seq, args.train_batch
+        gX = torch.randn(T, B, net.n_in, device="cuda", dtype=torch.float32)
+        gD = 0.1 * torch.randn(T, B, net.n_out, device="cuda", dtype=torch.float32)
+        torch.cuda.synchronize()
+        net.train_step_dev(gX.data_ptr(), gD.data_ptr(), T, B, lr=1e-4, ckpt=8)   # warm-up / allocation
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.train_iters):
+            net.train_step_dev(gX.data_ptr(), gD.data_ptr(), T, B, lr=1e-4, ckpt=8)
+        stream.synchronize()
+        tsec = (time.perf_counter() - t0) / args.train_iters
+        H, I, O, Lr = args.hidden, net.n_in, net.n_out, args.layers
+        fwd = 2.0 * (3 * H * ((I + 31) // 32 * 32) + 3 * H * H + (Lr - 1) * 6 * H * H + O * H)
+        flop = T * B * fwd * (1 + 1 + 2)      # forward, recompute, backward (2x forward)
+        train = {"seq": T, "batch": B, "hidden": H, "layers": Lr, "ms_per_iter": round(1e3 * tsec, 2),
+                 "model_tflop_per_iter": round(flop / 1e12, 4),
+                 "tflops": round(flop / tsec / 1e12, 2), "mfma_frac": round(flop / tsec / 2.5e15, 5)}
+        log(f"train: {train}")
+        del gX, gD
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.seed, args.cpu_level, args.level, args.dt)
-    ms_step = 1e3 * sec / args.steps
-    out = {
+    ms_step = 1e3 * d_sec / args.steps
+    result = {
         "metric": METRIC,
-        "value": round(args.steps / sec, 4),
+        "value": round(args.steps / d_sec, 4),
         "unit": "time steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -158,18 +258,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64+bf16",
         "data": "synthetic",
-        "config": {"workload": f"plain full-depth GMG, channel+obstacle seed {args.seed}, "
-                               f"level {args.level}, Re 100, dt {args.dt}, mixed precision",
-                   "level": args.level, "nodes": n_nodes, "dofs": 3 * n_nodes,
-                   "newton_iters": sum(s["newton_iters"] for s in stats),
-                   "gmres_iters": sum(s["gmres_iters"] for s in stats),
-                   "dof_updates_per_s": round(3 * n_nodes * args.steps / sec, 1)},
+        "config": {"workload": (f"DNN-MG: Newton-GMRES-GMG on level {args.coarse_level} + GRU "
+                                f"{args.hidden}x{args.layers} patch net correcting level {args.level}; "
+                                f"channel+obstacle seed {args.seed}, Re 100, dt {args.dt}, mixed precision, "
+                                f"random-init net"),
+                   "coarse_level": args.coarse_level, "fine_level": args.level,
+                   "fine_dofs": 3 * nF, "coarse_dofs": 3 * nL, "patches": net.n_patches,
+                   "gmg_steps_per_s": round(args.steps / g_sec, 4),
+                   "gmg_ms_per_step": round(1e3 * g_sec / args.steps, 3),
+                   "dnnmg_speedup_vs_gmg": round(g_sec / d_sec, 3),
+                   "velocity_rel_l2_err_dnnmg": round(err_dnn, 6),
+                   "velocity_rel_l2_err_mg_coarse": round(err_mgl, 6),
+                   "gmg_dof_updates_per_s": round(3 * nF * args.steps / g_sec, 1),
+                   "gmg_newton_iters": sum(s_["newton_iters"] for s_ in g_stats),
+                   "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
+                   "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
+                   "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats)},
         "roofline": roof,
+        "mfma": mfma,
+        "train": train,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":
