@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--train-iters", type=int, default=3)
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="device copy of this many MiB before the run (calibrates "
+                         "hardware traffic counters against a known byte count)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -151,6 +154,12 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb * (1 << 18), device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream)
     t0 = time.perf_counter()

@@ -52,7 +52,7 @@ typedef struct dnnmg_net dnnmg_net;
  * LPS parameter alpha_T = alpha0 / (nu / h_T^2 + 1/k) with alpha0 = 0.5,
  * Newton with full steps and absolute tolerance 1e-10 on the l2 norm of the
  * nonlinear residual, GMRES(30) with relative tolerance 1e-2 and at most 100
- * iterations, V(2,2) cycles with additive cell-Vanka (omega = 0.8). */
+ * iterations, V(2,2) cycles with additive cell-Vanka (omega = 0.6). */
 typedef struct {
   double nu;              /* kinematic viscosity (the paper's 1/Re)              */
   double alpha0;          /* LPS scale                                           */

@@ -9,7 +9,7 @@
 * The iterative components the paper names for the linear solves (Sec. 2.2:
   GMRES with a geometric multigrid preconditioner, one V-cycle per
   application), in the paper's terms plus the readings N3 (V(2,2), additive
-  averaged cell-Vanka, omega = 0.8, coarse operators re-discretised at the
+  averaged cell-Vanka, omega = 0.6, coarse operators re-discretised at the
   injected iterate, dense LU on level 0):
   `vanka_sweep`, `vcycle`, `gmres`.
 """
@@ -63,7 +63,7 @@ def cell_blocks(J: sp.csr_matrix, cells) -> np.ndarray:
     return out.reshape(-1, 12, 12)
 
 
-def vanka_sweep(J, blocks, cells, x, b, omega=0.8):
+def vanka_sweep(J, blocks, cells, x, b, omega=0.6):
     """Additive averaged cell-Vanka: r = b - J x; for every cell solve the local
     12x12 system (LU with partial pivoting); each node receives omega times the
     mean of the corrections of the cells that contain it."""
@@ -82,7 +82,7 @@ class MGHierarchy:
     injected to each level: coarse vertices keep their ids, so injection is
     the prefix of the fine vector)."""
 
-    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.8):
+    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6):
         self.levels = levels
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
@@ -181,7 +181,7 @@ def gmres(A, b, precond, rtol=1e-2, restart=30, maxit=100):
 
 
 def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1e-2,
-                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.8):
+                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6):
     """Newton's method (eq. newton) with GMRES + V-cycle linear solves, as in
     Algorithm 1, lines 2-4 (full steps, reading N1)."""
     fine = levels[-1]

@@ -194,7 +194,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->gmres_max = 100;
   p->nu_pre = 2;
   p->nu_post = 2;
-  p->vanka_omega = 0.8;
+  p->vanka_omega = 0.6;
   p->precision = 1;
   p->stream = nullptr;
   return DNNMG_OK;

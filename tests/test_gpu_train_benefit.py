@@ -73,35 +73,59 @@ def test_trained_network_beats_plain_coarse_method():
     sg_full = np.concatenate([np.repeat(sg[:6], S2), sg[6:]])
     X = ((Xraw - mu_full) / sg_full).astype(np.float32)
     D = np.concatenate([Dstar[..., :S2] / osc[0], Dstar[..., S2:] / osc[1]], axis=-1).astype(np.float32)
-    # 3. BPTT training from a small random initialisation
+    # 3. BPTT training from a small random initialisation, then DAgger rounds:
+    #    the network is run free (its own corrections feed the next coarse
+    #    step), the states it visits are labelled with the true correction
+    #    d* = v^F_n - P^2 v^L_n and added as new sequences (exposure bias).
     from synthetic import gru_weights
     w0 = gru_weights(net.n_in, 64, 2, net.n_out, seed=1, scale=0.5)
     net.set_weights(w0, mu.astype(np.float32), sg.astype(np.float32), osc.astype(np.float32))
-    losses = []
-    for it in range(400):
-        lr = 3e-3 if it < 300 else 1e-3
-        losses.append(net.train_step(X, D, lr=lr, ckpt=8))
-    print(f"[train] loss {losses[0]:.3f} -> {losses[-1]:.3f} (per sequence, {N} steps)", flush=True)
-    assert losses[-1] < 0.5 * losses[0]
 
-    # 4. free-running DNN-MG vs plain MG(L)
-    def run(with_net):
+    def standardise(Xr, Ds):
+        Xs = ((Xr - mu_full) / sg_full).astype(np.float32)
+        Dn = np.concatenate([Ds[..., :S2] / osc[0], Ds[..., S2:] / osc[1]], axis=-1).astype(np.float32)
+        return Xs, Dn
+
+    def run(with_net, collect=False):
         st = ctx.state(L)
         if with_net:
             net.reset(st)
-        errs = []
+        errs, Xc, Dc = [], [], []
         for n in range(1, N + 1):
-            info = ctx.step(st, DT)
+            ctx.step(st, DT)
             xl, _ = st.get()
             v = _prolong(ctx, xl, L, F).reshape(-1, 3)[:, :2]
+            ref = xF[n].reshape(-1, 3)[:, :2]
             if with_net:
                 out = net.correct(st, DT, debug=True)
+                if collect:
+                    d = ref - v
+                    Xc.append(out["inputs"].astype(np.float64))
+                    Dc.append(np.concatenate([d[grid, 0], d[grid, 1]], axis=1))
                 v = v + out["correction"]
-            ref = xF[n].reshape(-1, 3)[:, :2]
             errs.append(np.linalg.norm(v - ref) / np.linalg.norm(ref))
         st.close()
+        if collect:
+            # the net standardises internally: undo it to store raw inputs
+            Xr = np.stack(Xc) * sg_full + mu_full
+            return np.array(errs), Xr, np.stack(Dc)
         return np.array(errs)
 
+    X, D = standardise(Xraw, Dstar)
+    losses = [net.train_step(X, D, lr=3e-3, ckpt=8) for _ in range(300)]
+    print(f"[train] teacher forcing: loss {losses[0]:.3f} -> {losses[-1]:.3f}", flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    for rnd in range(3):
+        e, Xr, Ds = run(True, collect=True)
+        print(f"[train] DAgger round {rnd}: free-run error 2nd half {e[N // 2:].mean():.4f}", flush=True)
+        Xn, Dn = standardise(Xr, Ds)
+        X = np.concatenate([X, Xn], axis=1)
+        D = np.concatenate([D, Dn], axis=1)
+        for it in range(200):
+            loss = net.train_step(X, D, lr=2e-3 if it < 150 else 5e-4, ckpt=8)
+        print(f"[train] round {rnd}: {X.shape[1]} sequences, loss {loss:.3f}", flush=True)
+
+    # 4. free-running DNN-MG vs plain MG(L)
     e_plain = run(False)
     e_dnn = run(True)
     half = slice(N // 2, N)
