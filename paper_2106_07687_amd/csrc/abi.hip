@@ -112,7 +112,9 @@ retry:
       break;
     }
     if (it == c.prm.newton_max) break;
-    S.linearize(st.x.p, l, dt);
+    // the multigrid preconditioner is refreshed at the first Newton iteration
+    // of a step; later iterations re-assemble only the finest Jacobian
+    S.linearize(st.x.p, l, dt, it == 0);
     hipLaunchKernelGGL((k_convert<double, T>), dim3(blocks(n, 256)), dim3(256), 0, s, n, c.R.p, o.b.p);
     double r0, r1;
     const int k = S.gmres(l, o.b.p, o.x.p, c.prm.gmres_rtol, c.prm.gmres_restart, c.prm.gmres_max,

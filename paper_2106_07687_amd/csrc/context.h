@@ -119,7 +119,9 @@ class Solver {
  public:
   explicit Solver(Ctx *c) : ctx_(c) {}
   void setup(int finest);
-  void linearize(const double *x_dev, int level, double dt);   // J, Vanka, coarse inverse
+  // J on `level` (and, if full, on all coarser levels with the Vanka inverses
+  // and the level-0 inverse: the multigrid preconditioner)
+  void linearize(const double *x_dev, int level, double dt, bool full = true);
   void vanka_sweep(int l, T *x, const T *b, bool zero_start);
   void vcycle(int l, const T *b, T *x);                         // x = V(b), zero start
   int gmres(int level, const T *b, T *x, double rtol, int restart, int maxit, double *res0,
@@ -133,7 +135,7 @@ class Solver {
   Ctx *ctx_;
   int lin_level_ = -1;
   std::vector<OpLevel<T>> ops_;
-  DevBuf<double> W_, invT_;
+  DevBuf<double> W_, prow_, colk_;
   int n0_ = 0;
   // GMRES workspace
   int gm_level_ = -1, gm_m_ = 0;

@@ -644,88 +644,85 @@ __global__ void k_dense_from_sell(LevelView L, const T *__restrict__ JQ, const T
   }
 }
 
-// In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix
-// held in the left half of W (n x 2n, row-major; the right half must hold the
-// identity).  One workgroup; the inverse is written transposed into invT
-// (invT[k * n + i] = A^{-1}[i][k]) so that the solve reads it coalesced.
-__global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict__ W,
-                                                       double *__restrict__ invT) {
-  __shared__ double sval[1024];
-  __shared__ int sidx[1024];
-  __shared__ int piv;
-  const int tid = threadIdx.x, nt = blockDim.x, w = 2 * n;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += nt) {
-      const double v = fabs(W[static_cast<size_t>(i) * w + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
+// Multi-workgroup Gauss-Jordan, one pivot column k per pair of launches.
+// Pivot step (one workgroup): partial pivoting on column k, row swap,
+// normalisation of the pivot row, copies of the pivot row (prow) and of
+// column k (colk, 0 at the pivot row).
+__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k, double *__restrict__ W,
+                                                  double *__restrict__ prow, double *__restrict__ colk) {
+  __shared__ double sval[256];
+  __shared__ int sidx[256];
+  const int tid = threadIdx.x, w = 2 * n;
+  double best = -1.0;
+  int bi = k;
+  for (int i = k + tid; i < n; i += 256) {
+    const double v = fabs(W[static_cast<size_t>(i) * w + k]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  sval[tid] = best;
+  sidx[tid] = bi;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      const double ov = sval[tid + off];
+      const int oi = sidx[tid + off];
+      if (ov > sval[tid] || (ov == sval[tid] && oi < sidx[tid])) {
+        sval[tid] = ov;
+        sidx[tid] = oi;
       }
     }
-    sval[tid] = best;
-    sidx[tid] = bi;
-    __syncthreads();
-    for (int off = nt / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        const double ov = sval[tid + off];
-        const int oi = sidx[tid + off];
-        if (ov > sval[tid] || (ov == sval[tid] && oi < sidx[tid])) {
-          sval[tid] = ov;
-          sidx[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) piv = sidx[0];
-    __syncthreads();
-    const int p = piv;
-    if (p != k)
-      for (int j = tid; j < w; j += nt) {
-        const double t = W[static_cast<size_t>(k) * w + j];
-        W[static_cast<size_t>(k) * w + j] = W[static_cast<size_t>(p) * w + j];
-        W[static_cast<size_t>(p) * w + j] = t;
-      }
-    __syncthreads();
-    const double ip = 1.0 / W[static_cast<size_t>(k) * w + k];
-    __syncthreads();
-    for (int j = tid; j < w; j += nt) W[static_cast<size_t>(k) * w + j] *= ip;
-    __syncthreads();
-    // eliminate column k from all other rows
-    for (int t = tid; t < n * w; t += nt) {
-      const int i = t / w, j = t % w;
-      if (i == k || j < k) continue;
-      const double fct = W[static_cast<size_t>(i) * w + k];
-      if (j == k) continue;
-      W[static_cast<size_t>(i) * w + j] -= fct * W[static_cast<size_t>(k) * w + j];
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += nt)
-      if (i != k) W[static_cast<size_t>(i) * w + k] = 0.0;
     __syncthreads();
   }
-  for (int t = tid; t < n * n; t += nt) {
-    const int i = t / n, k = t % n;
-    invT[static_cast<size_t>(k) * n + i] = W[static_cast<size_t>(i) * w + n + k];
+  const int p = sidx[0];
+  const double piv = W[static_cast<size_t>(p) * w + k];
+  const double ip = 1.0 / piv;
+  for (int j = tid; j < w; j += 256) {
+    const double a = W[static_cast<size_t>(k) * w + j];
+    const double b = W[static_cast<size_t>(p) * w + j];
+    const double nb = b * ip;
+    W[static_cast<size_t>(p) * w + j] = a;
+    W[static_cast<size_t>(k) * w + j] = nb;
+    prow[j] = nb;
   }
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) colk[i] = (i == k) ? 0.0 : W[static_cast<size_t>(i) * w + k];
+}
+
+// Elimination step: W[i][j] -= colk[i] * prow[j] for all rows i != k.
+__global__ void k_gj_elim(int n, int k, double *__restrict__ W, const double *__restrict__ prow,
+                          const double *__restrict__ colk) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int w = 2 * n;
+  if (j >= w || i == k) return;
+  const double f = colk[i];
+  if (f != 0.0) W[static_cast<size_t>(i) * w + j] -= f * prow[j];
+}
+
+// x = A^{-1} b with the inverse held in the right half of the Gauss-Jordan
+// workspace (row-major, stride 2n): 32 lanes per row split the dot product.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__restrict__ W,
+                                                       const T *__restrict__ b, T *__restrict__ x) {
+  const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int lane = threadIdx.x & 31;
+  double s = 0.0;
+  if (row < n) {
+    const double *r = W + static_cast<size_t>(row) * 2 * n + n;
+    for (int k = lane; k < n; k += 32) s += r[k] * static_cast<double>(b[k]);
+  }
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+  if (row < n && lane == 0) x[row] = static_cast<T>(s);
 }
 
 __global__ void k_identity_right(int n, double *__restrict__ W) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   W[static_cast<size_t>(i) * 2 * n + n + i] = 1.0;
-}
-
-// x = A^{-1} b with the stored transposed inverse (FP64 arithmetic).
-template <typename T>
-__global__ void k_dense_solve(int n, const double *__restrict__ invT, const T *__restrict__ b,
-                              T *__restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < n; ++k) s += invT[static_cast<size_t>(k) * n + i] * static_cast<double>(b[k]);
-  x[i] = static_cast<T>(s);
 }
 
 // -------------------------------------------------------------- BLAS-1

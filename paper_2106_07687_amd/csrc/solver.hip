@@ -150,14 +150,16 @@ void Solver<T>::setup(int finest) {
   }
   n0_ = 3 * ctx_->levels[0]->h.N;
   W_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
-  invT_.alloc(static_cast<size_t>(n0_) * n0_);
+  prow_.alloc(2 * static_cast<size_t>(n0_));
+  colk_.alloc(static_cast<size_t>(n0_));
   lin_level_ = -1;
 }
 
 template <typename T>
-void Solver<T>::linearize(const double *x_dev, int level, double dt) {
+void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) {
   hipStream_t s = ctx_->stream;
-  for (int l = 0; l <= level; ++l) {
+  if (lin_level_ < level) full = true;   // never factorised at this depth
+  for (int l = full ? 0 : level; l <= level; ++l) {
     ctx_->ensure_lps(l, dt);
     DevLevel &L = *ctx_->levels[l];
     OpLevel<T> &o = ops_[l];
@@ -169,14 +171,16 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt) {
                          ctx_->phys(dt, 0.0), x_dev, L.sP.p, o.JQ.p, o.JX.p);
     }
     LAUNCH_CHECK("k_assemble");
-    if (l > 0) {
+    if (full && l > 0) {
       ProfScope ps(ctx_->prof, s, "vanka_factor", l);
       hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 16, 256)),
                          dim3(256), 0, s, L.view(), o.JQ.p, o.inv.p);
       LAUNCH_CHECK("k_vanka_factor");
     }
   }
-  // level-0 dense inverse (FP64)
+  if (!full) return;
+  // level-0 dense inverse (FP64): Gauss-Jordan with partial pivoting on
+  // [J_0 | I], one pivot kernel and one elimination kernel per column
   DevLevel &L0 = *ctx_->levels[0];
   hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, W_.p, W_.n, 0.0);
   hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
@@ -184,7 +188,11 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt) {
   hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
   {
     ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, n0_, W_.p, invT_.p);
+    const dim3 eg(blocks(2 * n0_, 256), n0_);
+    for (int k = 0; k < n0_; ++k) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
+      hipLaunchKernelGGL(k_gj_elim, eg, dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
+    }
   }
   LAUNCH_CHECK("coarse inverse");
   lin_level_ = level;
@@ -250,7 +258,7 @@ void Solver<T>::vcycle(int l, const T *b, T *x) {
   hipStream_t s = ctx_->stream;
   if (l == 0) {
     ProfScope ps(ctx_->prof, s, "coarse_solve", 0);
-    hipLaunchKernelGGL(k_dense_solve<T>, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, invT_.p, b, x);
+    hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, W_.p, b, x);
     LAUNCH_CHECK("k_dense_solve");
     return;
   }
