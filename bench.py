@@ -122,6 +122,76 @@ def roofline_from(prof, ctx, level, kernels_with_bytes):
             "bytes_per_launch": b}
 
 
+def train_dnnmg(ctx, net, xF, args, log):
+    """Trains the patch network on the GPU (untimed): teacher-forced coarse
+    steps (the coarse right-hand side restricted from the fine velocity of
+    the previous step) give inputs and targets d* = v^F_n - P^m v^L_n; BPTT
+    with Adam; then DAgger rounds add the states of free DNN-MG runs."""
+    import numpy as np
+    import torch
+
+    from synthetic import gru_weights
+    L, dt = args.coarse_level, args.dt
+    nL = ctx.level_info(L)[0]
+    N = len(xF) - 1
+    S2 = net.n_out // 2
+    net.set_weights(None, mu=np.zeros(10), sigma=np.ones(10), out_scale=np.ones(2))
+    sl = ctx.state(L)
+    Xr, Dr = [], []
+    for n in range(1, N + 1):
+        sl.set(xF[n - 1][:3 * nL], (n - 1) * dt)
+        net.rhs_from_fine(sl, xF[n - 1], dt)
+        ctx.step(sl, dt)
+        Xr.append(net.correct(sl, dt, debug=True)["inputs"])
+        Dr.append(net.targets(sl, xF[n]))
+    sl.close()
+    Xr, Dr = np.stack(Xr), np.stack(Dr)
+    mu = np.array([Xr[..., c * S2:(c + 1) * S2].mean() for c in range(6)] +
+                  [Xr[..., 6 * S2 + k].mean() for k in range(4)])
+    sg = np.array([Xr[..., c * S2:(c + 1) * S2].std() for c in range(6)] +
+                  [Xr[..., 6 * S2 + k].std() for k in range(4)])
+    sg = np.where(sg > 1e-30, sg, 1.0)
+    osc = np.array([Dr[..., :S2].std(), Dr[..., S2:].std()])
+    osc = np.where(osc > 1e-30, osc, 1.0)
+    mu_f = np.concatenate([np.repeat(mu[:6], S2), mu[6:]]).astype(np.float32)
+    sg_f = np.concatenate([np.repeat(sg[:6], S2), sg[6:]]).astype(np.float32)
+    os_f = np.concatenate([np.repeat(osc[0], S2), np.repeat(osc[1], S2)]).astype(np.float32)
+    w0 = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
+    net.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
+    X = torch.from_numpy((Xr - mu_f) / sg_f).cuda()
+    D = torch.from_numpy(Dr / os_f).cuda()
+    del Xr, Dr
+    ck = min(8, N)
+
+    def fit(iters, lr):
+        loss = None
+        for it in range(iters):
+            loss = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1],
+                                      lr=lr if it < 0.75 * iters else 0.3 * lr, ckpt=ck)
+        return loss
+
+    first = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1], lr=2e-3, ckpt=ck)
+    loss = fit(args.train_net_iters, 2e-3)
+    log(f"net training (teacher forcing): loss {first:.1f} -> {loss:.1f}, {X.shape[1]} sequences")
+    for rnd in range(args.dagger):
+        st = ctx.state(L)
+        net.reset(st)
+        Xc, Dc = [], []
+        for n in range(1, N + 1):
+            ctx.step(st, dt)
+            Xc.append(net.correct(st, dt, debug=True)["inputs"])
+            Dc.append(net.targets(st, xF[n]))
+        st.close()
+        X = torch.cat([X, torch.from_numpy(np.stack(Xc)).cuda()], dim=1).contiguous()
+        D = torch.cat([D, torch.from_numpy(np.stack(Dc)).cuda()], dim=1).contiguous()
+        loss = fit(args.train_net_iters // 2, 1e-3)
+        log(f"net training (DAgger round {rnd}): loss {loss:.1f}, {X.shape[1]} sequences")
+    del X, D
+    torch.cuda.empty_cache()
+    return {"sequences_per_round": net.n_patches, "steps": N, "rounds": 1 + args.dagger,
+            "final_loss": round(float(loss), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +208,10 @@ def main():
     ap.add_argument("--train-iters", type=int, default=3)
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
+    ap.add_argument("--train-net", type=int, default=1,
+                    help="train the patch network on the GPU before the DNN-MG run (untimed)")
+    ap.add_argument("--train-net-iters", type=int, default=150)
+    ap.add_argument("--dagger", type=int, default=2)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="device copy of this many MiB before the run (calibrates "
                          "hardware traffic counters against a known byte count)")
@@ -189,9 +263,21 @@ def main():
     # ---- DNN-MG: Newton-GMRES-MG on the coarse level + patch GRU on the fine level
     m = args.level - args.coarse_level
     net = P.Net(ctx, args.coarse_level, m, args.hidden, args.layers)
-    w = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
-    net.set_weights(w, mu=np.zeros(10), sigma=np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
-                    out_scale=np.array([1e-3, 1e-3]))
+    nsteps = args.warmup + args.steps
+    # fine reference at every step (untimed replay of the GMG run above)
+    sfr = ctx.state(args.level)
+    xF = [sfr.get()[0]]
+    for _ in range(nsteps):
+        ctx.step(sfr, args.dt)
+        xF.append(sfr.get()[0])
+    sfr.close()
+    train_info = None
+    if args.train_net:
+        train_info = train_dnnmg(ctx, net, xF, args, log)
+    else:
+        w = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
+        net.set_weights(w, mu=np.zeros(10), sigma=np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
+                        out_scale=np.array([1e-3, 1e-3]))
     sc = ctx.state(args.coarse_level)
     net.reset(sc)
     for k, s_ in enumerate(run_steps(ctx, sc, args.warmup, args.dt, net)):
@@ -206,15 +292,24 @@ def main():
     ctx.profile_enable(False)
     for k, s_ in enumerate(d_stats):
         log(f"dnnmg step {k}: {s_}")
-    out = net.correct(sc, args.dt, debug=True)   # correction of the last state (untimed)
-    xl, _ = sc.get()
-    err_dnn = velocity_error(ctx, xl, args.coarse_level, args.level, x_fine, out["correction"])
-    err_mgl = None
-    # plain MG(L) for the error comparison (untimed)
-    sp = ctx.state(args.coarse_level)
-    run_steps(ctx, sp, args.warmup + args.steps, args.dt)
-    xp, _ = sp.get()
-    err_mgl = velocity_error(ctx, xp, args.coarse_level, args.level, x_fine)
+    sc.close()
+    # velocity errors against the fine solution at every timed step (untimed
+    # replays of the same deterministic runs)
+    err_dnn, err_mgl = [], []
+    for with_net in (True, False):
+        st = ctx.state(args.coarse_level)
+        if with_net:
+            net.reset(st)
+        for n in range(1, nsteps + 1):
+            ctx.step(st, args.dt)
+            xl, _ = st.get()
+            corr = net.correct(st, args.dt, debug=True)["correction"] if with_net else None
+            if n > args.warmup:
+                e = velocity_error(ctx, xl, args.coarse_level, args.level, xF[n], corr)
+                (err_dnn if with_net else err_mgl).append(e)
+        st.close()
+    err_dnn, err_mgl = float(np.mean(err_dnn)), float(np.mean(err_mgl))
+    log(f"velocity error (mean over timed steps): DNN-MG {err_dnn:.3e}, MG(L) {err_mgl:.3e}")
 
     for name, prof in (("gmg", g_prof), ("dnnmg", d_prof)):
         for key in sorted(prof, key=lambda k: -prof[k][1])[:14]:
@@ -271,8 +366,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"DNN-MG: Newton-GMRES-GMG on level {args.coarse_level} + GRU "
                                 f"{args.hidden}x{args.layers} patch net correcting level {args.level}; "
-                                f"channel+obstacle seed {args.seed}, Re 100, dt {args.dt}, mixed precision, "
-                                f"random-init net"),
+                                f"channel+obstacle seed {args.seed}, Re 100, dt {args.dt}, mixed precision"),
                    "coarse_level": args.coarse_level, "fine_level": args.level,
                    "fine_dofs": 3 * nF, "coarse_dofs": 3 * nL, "patches": net.n_patches,
                    "gmg_steps_per_s": round(args.steps / g_sec, 4),
@@ -280,6 +374,8 @@ def main():
                    "dnnmg_speedup_vs_gmg": round(g_sec / d_sec, 3),
                    "velocity_rel_l2_err_dnnmg": round(err_dnn, 6),
                    "velocity_rel_l2_err_mg_coarse": round(err_mgl, 6),
+                   "net": "trained on the GPU (teacher forcing + DAgger)" if train_info else "random init",
+                   "net_training": train_info,
                    "gmg_dof_updates_per_s": round(3 * nF * args.steps / g_sec, 1),
                    "gmg_newton_iters": sum(s_["newton_iters"] for s_ in g_stats),
                    "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),

@@ -233,6 +233,13 @@ int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt
  * ignored). */
 int dnnmg_rhs_from_fine(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
                         double dt);
+/* Training targets of the loss (eq. loss) for the coarse state: the velocity
+ * correction d* = v_fine - P^m x (coarse) at every patch node, divided by the
+ * net's output scales, written as n_patches x n_out floats (host) in the
+ * network's output layout.  v_fine: host, 3 doubles per fine node.  The
+ * network's inference state is not changed. */
+int dnnmg_net_targets(dnnmg_ctx *ctx, const dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
+                      float *D);
 
 /* Training (loss of eq. loss): X holds T x B standardised input rows
  * (T time steps of B patch sequences, n_in floats each, step-major), D the

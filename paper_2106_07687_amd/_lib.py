@@ -97,6 +97,7 @@ _SIGS = {
     "dnnmg_net_forward": (C.c_int, [_P, _FP, _FP]),
     "dnnmg_correct": (C.c_int, [_P, _P, _P, C.c_double, C.POINTER(CorrectOut)]),
     "dnnmg_rhs_from_fine": (C.c_int, [_P, _P, _P, _DP, C.c_double]),
+    "dnnmg_net_targets": (C.c_int, [_P, _P, _P, _DP, _FP]),
     "dnnmg_net_gradient": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, _FP, _FP]),
     "dnnmg_train_step": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_train_step_dev": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
@@ -328,6 +329,13 @@ class Net:
     def rhs_from_fine(self, state, v_fine, dt):
         v = _f64(v_fine)
         self.ctx._check(self.ctx.lib.dnnmg_rhs_from_fine(self.ctx.h, state.h, self.h, _dp(v), dt))
+
+    def targets(self, state, v_fine):
+        """Scaled correction targets (n_patches, n_out) for the coarse state."""
+        v = _f64(v_fine)
+        D = np.empty((self.n_patches, self.n_out), dtype=np.float32)
+        self.ctx._check(self.ctx.lib.dnnmg_net_targets(self.ctx.h, state.h, self.h, _dp(v), _fp(D)))
+        return D
 
     def gradient(self, X, D, ckpt=8):
         """X: (T, B, n_in), D: (T, B, n_out) host arrays -> (loss, grad)."""

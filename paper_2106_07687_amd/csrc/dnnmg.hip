@@ -215,6 +215,33 @@ void rhs_and_restrict(Net &n, State &st, double dt) {
 
 extern "C" {
 
+int dnnmg_net_targets(dnnmg_ctx *ctx, const dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
+                      float *D) {
+  if (!ctx || !coarse || !net || !v_fine || !D) return DNNMG_EINVAL;
+  Net &n = net->impl;
+  Ctx &c = ctx->impl;
+  if (n.ctx != &c || coarse->impl.ctx != &c || coarse->impl.level != n.L) {
+    c.last_error = "state / network do not belong to this context and coarse level";
+    return DNNMG_EINVAL;
+  }
+  try {
+    hipStream_t s = c.stream;
+    const size_t nf = 3 * static_cast<size_t>(c.levels[n.F]->h.N);
+    check(hipMemcpyAsync(n.vc.p, v_fine, nf * sizeof(double), hipMemcpyHostToDevice, s), "v H2D");
+    prolong_chain(n, coarse->impl.x.p);
+    const size_t cnt = static_cast<size_t>(n.B) * n.S2;
+    hipLaunchKernelGGL(k_patch_targets, dim3(blocks(cnt, 256)), dim3(256), 0, s, n.view(), n.vc.p,
+                       n.xt[n.m].p, n.oscale.p, n.Y.p);
+    check(hipGetLastError(), "k_patch_targets");
+    check(hipMemcpyAsync(D, n.Y.p, sizeof(float) * n.B * n.O, hipMemcpyDeviceToHost, s), "D D2H");
+    check(hipStreamSynchronize(s), "targets");
+  } catch (const DnnmgError &e) {
+    c.last_error = e.msg;
+    return e.code;
+  }
+  return DNNMG_OK;
+}
+
 int dnnmg_rhs_from_fine(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, const double *v_fine,
                         double dt) {
   if (!ctx || !coarse || !net || !v_fine || !(dt > 0)) return DNNMG_EINVAL;

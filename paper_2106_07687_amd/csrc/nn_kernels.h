@@ -367,6 +367,19 @@ __global__ void k_adam(size_t n, float *__restrict__ w, const float *__restrict_
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Training targets (reading N9): D[p][f S2 + q] = (v_fine - x~)_f at the
+// patch node q of patch p, divided by the output scale of component f.
+__global__ void k_patch_targets(PatchView pv, const double *__restrict__ vf, const double *__restrict__ xt,
+                                const float *__restrict__ oscale, float *__restrict__ D) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(pv.B) * pv.S2) return;
+  const int p = static_cast<int>(t / pv.S2), q = static_cast<int>(t % pv.S2);
+  const int i = pv.grid[t];
+  float *row = D + static_cast<size_t>(p) * 2 * pv.S2;
+  row[q] = static_cast<float>((vf[3 * i] - xt[3 * i]) / oscale[0]);
+  row[pv.S2 + q] = static_cast<float>((vf[3 * i + 1] - xt[3 * i + 1]) / oscale[1]);
+}
+
 __global__ void k_f32_to_bf16(size_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = f2bf(a[i]);
