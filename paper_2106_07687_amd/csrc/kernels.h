@@ -112,7 +112,7 @@ __device__ __constant__ int kChildToPatch[4][4] = {{0, 1, 4, 3}, {1, 2, 5, 4}, {
 
 // Patch matrix s_P = K^T (sum_T alpha_T S_T) K of the LPS term, one thread per
 // patch, stored SoA: sP[(9 q + m) * NP + P].
-__global__ void k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
+__global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
   const int P = blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= L.NP) return;
   double S[9][9];
@@ -171,7 +171,7 @@ __global__ void k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
 // R = f_n - A_n(x) for every node (eqs. varform, varformv), gathered per node
 // over the node's cells (row a of each element) and patches; Dirichlet
 // velocity rows hold g(t_new) - x.  FP64 throughout.
-__global__ void k_residual(LevelView L, Phys ph, const double *__restrict__ x,
+__global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const double *__restrict__ x,
                            const double *__restrict__ xo, const double *__restrict__ rhs,
                            const double *__restrict__ sP, double *__restrict__ R) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,7 +254,7 @@ __global__ void k_residual(LevelView L, Phys ph, const double *__restrict__ x,
 // velocity field v: 1/k (v, phi) - (1 - theta)((v.grad) v, phi)
 // - (1 - theta) nu (grad v, grad phi); pressure rows 0.  This is Rhs() of
 // Algorithm 1 (line 7) without external force.
-__global__ void k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
+__global__ void __launch_bounds__(128) k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
   const double tho = 1.0 - ph.theta, nu = ph.nu, idt = ph.inv_dt;
@@ -322,7 +322,7 @@ __global__ void k_fill(T *__restrict__ a, size_t n, T v) {
 // Values are computed in FP64 and stored as T into the thread's own row
 // (zeroed beforehand), so there are no write conflicts.
 template <typename T>
-__global__ void k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
+__global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
                            const double *__restrict__ sP, T *__restrict__ JQ, T *__restrict__ JX) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
@@ -417,7 +417,7 @@ __global__ void k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
 // -------------------------------------------------------------- SpMV
 // y = b - J x (if b) or y = J x, T precision.
 template <typename T>
-__global__ void k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+__global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
                        const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
@@ -453,9 +453,10 @@ __global__ void k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restric
 // Gauss-Jordan elimination with partial pivoting.  A group of 16 lanes works
 // on one cell; lane r < 12 holds row r = 3 a + f.  Pivot search and pivot-row
 // broadcast use wavefront shuffles.  The inverse is stored SoA:
-// inv[(12 r + j) * C + c].
+// inv[((c / 64) * 144 + 12 r + j) * 64 + c % 64] (64-cell tiles: one
+// wavefront reads one contiguous 144 x 64 block).
 template <typename T>
-__global__ void k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restrict__ inv) {
+__global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restrict__ inv) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = gid >> 4;
   const int r = threadIdx.x & 15;
@@ -524,14 +525,15 @@ __global__ void k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restr
     }
   }
   if (live) {
+    T *dst = inv + (static_cast<size_t>(c / kS) * 144 + 12 * order) * kS + (c % kS);
 #pragma unroll
-    for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order + j) * L.C + c] = static_cast<T>(E[j]);
+    for (int j = 0; j < 12; ++j) dst[j * kS] = static_cast<T>(E[j]);
   }
 }
 
-// delta_c = inv_c r|_c, one thread per cell, stored SoA delta[(3a+f) * C + c].
+// delta_c = inv_c r|_c, one thread per cell; delta[12 c + 3 a + f].
 template <typename T>
-__global__ void k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
+__global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
                               T *__restrict__ delta) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= L.C) return;
@@ -542,27 +544,30 @@ __global__ void k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *_
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
+  const T *blk = inv + static_cast<size_t>(c / kS) * 144 * kS + (c % kS);
+  T *out = delta + 12 * static_cast<size_t>(c);
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
-    delta[static_cast<size_t>(i) * L.C + c] = s;
+    for (int j = 0; j < 12; ++j) s += blk[(12 * i + j) * kS] * rc[j];
+    out[i] = s;
   }
 }
 
 // x_j += omega / m_j * sum over the cells containing j of their corrections.
 template <typename T>
-__global__ void k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
+__global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
   for (int e = e0; e < e1; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
-    a0 += delta[static_cast<size_t>(3 * a) * L.C + c];
-    a1 += delta[static_cast<size_t>(3 * a + 1) * L.C + c];
-    a2 += delta[static_cast<size_t>(3 * a + 2) * L.C + c];
+    const T *d = delta + 12 * static_cast<size_t>(c) + 3 * a;
+    a0 += d[0];
+    a1 += d[1];
+    a2 += d[2];
   }
   const T w = omega / static_cast<T>(e1 - e0);
   x[3 * i] += w * a0;
@@ -625,7 +630,7 @@ __global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restr
 // Dense copy of the level-0 operator (FP64, row-major n x n, n = 3 N); padding
 // slots add zeros.
 template <typename T>
-__global__ void k_dense_from_sell(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+__global__ void __launch_bounds__(64) k_dense_from_sell(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
                                   double *__restrict__ A, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;   // row stride n (= 2 * 3 N for the Gauss-Jordan workspace)

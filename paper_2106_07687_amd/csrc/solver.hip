@@ -141,7 +141,7 @@ void Solver<T>::setup(int finest) {
     OpLevel<T> &o = ops_[l];
     o.JQ.alloc(static_cast<size_t>(h.totq) * 9 * kS);
     o.JX.alloc(static_cast<size_t>(std::max(h.totx, 1)) * kS);
-    o.inv.alloc(static_cast<size_t>(144) * h.C);
+    o.inv.alloc(static_cast<size_t>(144) * ((h.C + kS - 1) / kS) * kS);
     o.delta.alloc(static_cast<size_t>(12) * h.C);
     o.r.alloc(3 * static_cast<size_t>(h.N));
     o.b.alloc(3 * static_cast<size_t>(h.N));
