@@ -212,6 +212,12 @@ def main():
                     help="train the patch network on the GPU before the DNN-MG run (untimed)")
     ap.add_argument("--train-net-iters", type=int, default=150)
     ap.add_argument("--dagger", type=int, default=2)
+    ap.add_argument("--profile", choices=("roofline", "all"), default="roofline",
+                    help="roofline: HIP events only around the fine-level GMG kernels and "
+                         "the network kernels; all: every kernel of every level, launched "
+                         "directly (no graphs; events add launch overhead to the timings)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel directly instead of replaying captured graphs")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="device copy of this many MiB before the run (calibrates "
                          "hardware traffic counters against a known byte count)")
@@ -235,7 +241,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     macro = channel_obstacle(args.seed)
-    ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream)
+    ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
+                    use_graphs=0 if args.no_graphs else 1)
+    F = args.level
+    if args.profile == "all":
+        gmg_keys = dnn_keys = None
+    else:
+        gmg_keys = [f"{k}@L{F}" for k in ("spmv", "residual_spmv", "vanka_apply", "vanka_update",
+                                          "assemble", "vanka_factor", "residual", "gs_dots")]
+        dnn_keys = [f"{k}{l}@L{F}" for l in range(args.layers)
+                    for k in ("gru_gemm_in", "gru_gemm_hh", "gru_gates")]
+        dnn_keys += [f"{k}@L{F}" for k in ("gru_head", "dnnmg_rhs", "dnnmg_prolong",
+                                           "patch_gather", "patch_scatter")]
     t0 = time.perf_counter()
     ctx.setup_mesh(macro, args.level)
     setup_s = time.perf_counter() - t0
@@ -248,6 +265,7 @@ def main():
     sf = ctx.state(args.level)
     for k, s_ in enumerate(run_steps(ctx, sf, args.warmup, args.dt)):
         log(f"gmg warmup {k}: {s_}")
+    ctx.profile_select(gmg_keys)
     ctx.profile_enable(True)
     stream.synchronize()
     t0 = time.perf_counter()
@@ -282,6 +300,7 @@ def main():
     net.reset(sc)
     for k, s_ in enumerate(run_steps(ctx, sc, args.warmup, args.dt, net)):
         log(f"dnnmg warmup {k}: {s_}")
+    ctx.profile_select(dnn_keys)
     ctx.profile_enable(True)
     stream.synchronize()
     t0 = time.perf_counter()
@@ -318,11 +337,12 @@ def main():
     roof = roofline_from(g_prof, ctx, args.level, ("spmv", "residual_spmv", "vanka_apply", "vanka_update"))
     # MFMA utilisation of the network's input GEMM (layer 0)
     mfma = None
-    if "gru_gemm_in@L0" in d_prof:
-        cnt, ms = d_prof["gru_gemm_in@L0"]
+    mkey = f"gru_gemm_in0@L{F}"
+    if mkey in d_prof:
+        cnt, ms = d_prof[mkey]
         flop = 2.0 * net.n_patches * 3 * args.hidden * ((net.n_in + 31) // 32 * 32)
         tf = flop / (ms / cnt / 1e3) / 1e12
-        mfma = {"kernel": "gru_gemm_in@L0", "achieved": round(tf, 2), "peak": 2500.0,
+        mfma = {"kernel": mkey, "achieved": round(tf, 2), "peak": 2500.0,
                 "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5), "avg_us": round(1e3 * ms / cnt, 2)}
     # ---- BPTT training throughput at the training batch shape (synthetic rows)
     train = None
@@ -380,7 +400,8 @@ def main():
                    "gmg_newton_iters": sum(s_["newton_iters"] for s_ in g_stats),
                    "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
                    "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
-                   "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats)},
+                   "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats),
+                   "graphs": not args.no_graphs, "profile": args.profile},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

@@ -69,6 +69,10 @@ typedef struct {
   int precision;          /* 0: FP64 throughout; 1: mixed (FP32 smoother,
                              transfers, Krylov vectors; FP64 residual, Newton
                              update, coarse solve and Gram-Schmidt dots)        */
+  int use_graphs;         /* 1: replay V-cycles and the level-0 Gauss-Jordan
+                             sweep from HIP graphs captured on first use (same
+                             kernels, same order, bitwise the same results);
+                             0: launch every kernel directly                    */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 
@@ -264,8 +268,13 @@ int dnnmg_train_step_dev(dnnmg_net *net, const float *X_dev, const float *D_dev,
 /* Instrumentation (not part of the method).  When enabled, the library
  * records a pair of HIP events on its stream around every launch of its main
  * kernels and accumulates their durations per "kernel@Llevel" key; enabling
- * clears earlier totals. */
+ * clears earlier totals.  Levels that hold a profiled key are launched
+ * directly, not from graphs. */
 int dnnmg_profile_enable(dnnmg_ctx *ctx, int on);
+/* Restricts the timing to a comma-separated list of "kernel@Llevel" keys;
+ * NULL or "" times every key.  Kernels replayed from graphs (levels with no
+ * selected key) are not timed. */
+int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);

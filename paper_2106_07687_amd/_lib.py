@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("newton_tol", C.c_double), ("newton_max", C.c_int),
                 ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int), ("gmres_max", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vanka_omega", C.c_double),
-                ("precision", C.c_int), ("stream", C.c_void_p)]
+                ("precision", C.c_int), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
 
 
 class CoarseMesh(C.Structure):
@@ -102,6 +102,7 @@ _SIGS = {
     "dnnmg_train_step": (C.c_int, [_P, _FP, _FP, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_train_step_dev": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
+    "dnnmg_profile_select": (C.c_int, [_P, C.c_char_p]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
@@ -214,6 +215,11 @@ class Context:
 
     def profile_enable(self, on=True):
         self._check(self.lib.dnnmg_profile_enable(self.h, 1 if on else 0))
+
+    def profile_select(self, keys=None):
+        """Time only the given "kernel@Llevel" keys (None: all)."""
+        arg = None if not keys else ",".join(keys).encode()
+        self._check(self.lib.dnnmg_profile_select(self.h, arg))
 
     def profile_report(self):
         """{key: (launches, total_ms)} of the profiled kernel launches."""

@@ -38,7 +38,7 @@ bool params_ok(const dnnmg_params *p) {
          p->gmres_rtol > 0 && p->gmres_rtol < 1 && p->gmres_restart >= 1 &&
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
-         (p->precision == 0 || p->precision == 1);
+         (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1);
 }
 
 void upload_level(DevLevel &D, hipStream_t s) {
@@ -198,6 +198,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->nu_post = 2;
   p->vanka_omega = 0.6;
   p->precision = 1;
+  p->use_graphs = 1;
   p->stream = nullptr;
   return DNNMG_OK;
 }
@@ -231,6 +232,7 @@ int dnnmg_set_params(dnnmg_ctx *ctx, const dnnmg_params *p) {
   ctx->impl.prm = *p;
   ctx->impl.prm.precision = prec;
   ctx->impl.stream = static_cast<hipStream_t>(p->stream);
+  ++ctx->impl.graph_gen;   // captured graphs hold the old Vanka damping and sweep counts
   return DNNMG_OK;
 }
 
@@ -579,6 +581,26 @@ int dnnmg_profile_enable(dnnmg_ctx *ctx, int on) {
     Ctx &c = ctx->impl;
     if (on) c.prof.clear();
     c.prof.on = on != 0;
+    return DNNMG_OK;
+  });
+}
+
+int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys) {
+  if (!ctx) return DNNMG_EINVAL;
+  return guarded(ctx, [&]() {
+    std::vector<std::string> only;
+    if (keys) {
+      std::string all(keys), cur;
+      for (char ch : all + ",") {
+        if (ch == ',') {
+          if (!cur.empty()) only.push_back(cur);
+          cur.clear();
+        } else if (ch != ' ') {
+          cur += ch;
+        }
+      }
+    }
+    ctx->impl.prof.only = std::move(only);
     return DNNMG_OK;
   });
 }

@@ -7,6 +7,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dnnmg.h"
@@ -66,9 +67,13 @@ struct DevBuf {
 void check(hipError_t e, const char *what);
 
 // Optional per-kernel timing: HIP events recorded on the launch stream around
-// each profiled launch, resolved (synchronising) when queried.
+// each profiled launch, resolved (synchronising) when queried.  `only` limits
+// the timing to the listed "name@Llevel" keys (empty: every key).
 struct Profiler {
   bool on = false;
+  std::vector<std::string> only;
+  bool wants(const std::string &key) const;
+  bool wants_level(int level) const;   // some profiled key lives on `level`
   struct Rec {
     std::string key;
     hipEvent_t a, b;
@@ -130,13 +135,38 @@ class Solver {
   void prolong_add(int l, const T *ec, T *xf);
   void restrict_to(int l, const T *rf, T *rc);
   OpLevel<T> &op(int l) { return ops_[l]; }
+  ~Solver();
 
  private:
   Ctx *ctx_;
   int lin_level_ = -1;
+  // Launch-bound sequences (a V-cycle from a given level, the level-0
+  // Gauss-Jordan sweep) are captured once into HIP graphs and replayed; a
+  // slot is rebuilt when the context's graph generation changes.
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    long gen = -1;
+  };
+  std::map<std::tuple<int, const void *, const void *>, GraphSlot> vgraphs_;
+  GraphSlot ginv_;
+  bool capturing_ = false;
+  template <class F>
+  void graph_run(GraphSlot &g, F &&body);
+  bool use_graph(int level) const;
+  void clear_graphs();
+  void vcycle_body(int l, const T *b, T *x);
+  void coarse_inverse();
   std::vector<OpLevel<T>> ops_;
   DevBuf<double> W_, prow_, colk_;
   int n0_ = 0;
+  // blocked Gauss-Jordan: panel width (0: one pivot + one elimination launch
+  // per column), second workspace, panel transforms, pivot rows, used-row
+  // flags, and the compact inverse read by the coarse solve
+  int gj_b_ = 0;
+  DevBuf<double> W2_, Zp_, Ainv_;
+  DevBuf<int> piv_, used_;
+  const double *ainv_ = nullptr;   // A0^{-1}, row-major with leading dimension ainv_ld_
+  size_t ainv_ld_ = 0;
   // GMRES workspace
   int gm_level_ = -1, gm_m_ = 0;
   DevBuf<T> V_, Z_, w_;
@@ -152,6 +182,10 @@ class Ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   Profiler prof;
+  long graph_gen = 0;              // bumped when captured graphs go stale
+  hipStream_t cap_stream = nullptr;
+  hipStream_t capture_stream();    // private stream used only for graph capture
+  ~Ctx();
   std::vector<std::unique_ptr<DevLevel>> levels;
   int finest = -1;
   std::unique_ptr<Solver<float>> s32;

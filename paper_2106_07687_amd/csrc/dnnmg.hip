@@ -139,20 +139,22 @@ void net_forward(Net &n) {
   for (int l = 0; l < n.layers; ++l) {
     const uint16_t *in = l == 0 ? n.X.p : n.hb[l - 1].p;
     const int K = l == 0 ? n.K0 : n.H;
+    // keys "name<layer>@L<fine level>": the patches live on the fine level
+    const std::string lay = std::to_string(l);
     {
-      ProfScope ps(n.ctx->prof, s, "gru_gemm_in", l);
+      ProfScope ps(n.ctx->prof, s, ("gru_gemm_in" + lay).c_str(), n.F);
       gemm(s, n.B, H3, K, in, K, n.wih_b[l].p, K, n.Gi.p, H3, false);
     }
     {
-      ProfScope ps(n.ctx->prof, s, "gru_gemm_hh", l);
+      ProfScope ps(n.ctx->prof, s, ("gru_gemm_hh" + lay).c_str(), n.F);
       gemm(s, n.B, H3, n.H, n.hb[l].p, n.H, n.whh_b[l].p, n.H, n.Gh.p, H3, false);
     }
-    ProfScope ps(n.ctx->prof, s, "gru_gates", l);
+    ProfScope ps(n.ctx->prof, s, ("gru_gates" + lay).c_str(), n.F);
     hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(n.B) * n.H, 256)), dim3(256), 0, s, n.B,
                        n.H, n.Gi.p, n.Gh.p, n.h[l].p, n.hb[l].p, n.H, nullptr);
     check(hipGetLastError(), "k_gru_gates");
   }
-  ProfScope ps(n.ctx->prof, s, "gru_head", 0);
+  ProfScope ps(n.ctx->prof, s, "gru_head", n.F);
   gemm(s, n.B, n.O, n.H, n.hb[n.layers - 1].p, n.H, n.wout_b.p, n.H, n.Y.p, n.O, false);
 }
 

@@ -416,6 +416,7 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
 
 // -------------------------------------------------------------- SpMV
 // y = b - J x (if b) or y = J x, T precision.
+constexpr int kSpmvChunk = 16;
 template <typename T>
 __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
                        const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
@@ -426,17 +427,42 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
   const T *jq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
   const int *cq = L.colq + static_cast<size_t>(L.oq[s]) * kS + lane;
   T a0 = 0, a1 = 0, a2 = 0;
-  for (int k = 0; k < wq; ++k) {
-    const int j = cq[k * kS];
-    const T x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
-    const T *m = jq + static_cast<size_t>(k) * 9 * kS;
-    a0 += m[0] * x0 + m[kS] * x1 + m[2 * kS] * x2;
-    a1 += m[3 * kS] * x0 + m[4 * kS] * x1 + m[5 * kS] * x2;
-    a2 += m[6 * kS] * x0 + m[7 * kS] * x1 + m[8 * kS] * x2;
+  // Chunks of kSpmvChunk neighbours: all column indices of a chunk are loaded
+  // before the x values they select, so the dependent index -> x chain costs
+  // two memory latencies per chunk instead of two per neighbour (the same
+  // summation order as a plain loop).
+  for (int k0 = 0; k0 < wq; k0 += kSpmvChunk) {
+    int jv[kSpmvChunk];
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u) jv[u] = k0 + u < wq ? cq[(k0 + u) * kS] : -1;
+    T xv[kSpmvChunk][3];
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) xv[u][f] = jv[u] >= 0 ? x[3 * jv[u] + f] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u) {
+      if (jv[u] >= 0) {
+        const T *m = jq + static_cast<size_t>(k0 + u) * 9 * kS;
+        a0 += m[0] * xv[u][0] + m[kS] * xv[u][1] + m[2 * kS] * xv[u][2];
+        a1 += m[3 * kS] * xv[u][0] + m[4 * kS] * xv[u][1] + m[5 * kS] * xv[u][2];
+        a2 += m[6 * kS] * xv[u][0] + m[7 * kS] * xv[u][1] + m[8 * kS] * xv[u][2];
+      }
+    }
   }
   const T *jx = JX + static_cast<size_t>(L.ox[s]) * kS + lane;
   const int *cx = L.colx + static_cast<size_t>(L.ox[s]) * kS + lane;
-  for (int k = 0; k < wx; ++k) a2 += jx[k * kS] * x[3 * cx[k * kS] + 2];
+  for (int k0 = 0; k0 < wx; k0 += kSpmvChunk) {
+    int jv[kSpmvChunk];
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u) jv[u] = k0 + u < wx ? cx[(k0 + u) * kS] : -1;
+    T xv[kSpmvChunk];
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u) xv[u] = jv[u] >= 0 ? x[3 * jv[u] + 2] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSpmvChunk; ++u)
+      if (jv[u] >= 0) a2 += jx[(k0 + u) * kS] * xv[u];
+  }
   if (b) {
     y[3 * i] = b[3 * i] - a0;
     y[3 * i + 1] = b[3 * i + 1] - a1;
@@ -453,8 +479,8 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
 // Gauss-Jordan elimination with partial pivoting.  A group of 16 lanes works
 // on one cell; lane r < 12 holds row r = 3 a + f.  Pivot search and pivot-row
 // broadcast use wavefront shuffles.  The inverse is stored SoA:
-// inv[((c / 64) * 144 + 12 r + j) * 64 + c % 64] (64-cell tiles: one
-// wavefront reads one contiguous 144 x 64 block).
+// inv[(12 r + j) * C + c] (entry-major: each of the 144 loads of a wavefront
+// reads one contiguous 256-byte segment).
 template <typename T>
 __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restrict__ inv) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,13 +551,13 @@ __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__re
     }
   }
   if (live) {
-    T *dst = inv + (static_cast<size_t>(c / kS) * 144 + 12 * order) * kS + (c % kS);
 #pragma unroll
-    for (int j = 0; j < 12; ++j) dst[j * kS] = static_cast<T>(E[j]);
+    for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order + j) * L.C + c] = static_cast<T>(E[j]);
   }
 }
 
-// delta_c = inv_c r|_c, one thread per cell; delta[12 c + 3 a + f].
+// delta_c = inv_c r|_c, one thread per cell, stored entry-major
+// delta[(3 a + f) * C + c].
 template <typename T>
 __global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
                               T *__restrict__ delta) {
@@ -544,30 +570,50 @@ __global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__res
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
-  const T *blk = inv + static_cast<size_t>(c / kS) * 144 * kS + (c % kS);
-  T *out = delta + 12 * static_cast<size_t>(c);
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) s += blk[(12 * i + j) * kS] * rc[j];
-    out[i] = s;
+    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
+    delta[static_cast<size_t>(i) * L.C + c] = s;
   }
 }
 
 // x_j += omega / m_j * sum over the cells containing j of their corrections.
+// The first kCadj (cell, slot) entries of a node are loaded before any of
+// their corrections, so that a thread waits on two memory latencies, not on
+// two per cell (small levels have too few waves to hide a dependent chain).
+constexpr int kCadj = 8;
 template <typename T>
 __global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
-  for (int e = e0; e < e1; ++e) {
+  const size_t C = static_cast<size_t>(L.C);
+  int ce[kCadj];
+#pragma unroll
+  for (int u = 0; u < kCadj; ++u) ce[u] = e0 + u < e1 ? L.cadj[e0 + u] : -1;
+  T dv[kCadj][3];
+#pragma unroll
+  for (int u = 0; u < kCadj; ++u) {
+    const int c = ce[u] >> 2, a = ce[u] & 3;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) dv[u][f] = ce[u] >= 0 ? delta[static_cast<size_t>(3 * a + f) * C + c] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < kCadj; ++u) {
+    if (ce[u] >= 0) {
+      a0 += dv[u][0];
+      a1 += dv[u][1];
+      a2 += dv[u][2];
+    }
+  }
+  for (int e = e0 + kCadj; e < e1; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
-    const T *d = delta + 12 * static_cast<size_t>(c) + 3 * a;
-    a0 += d[0];
-    a1 += d[1];
-    a2 += d[2];
+    a0 += delta[static_cast<size_t>(3 * a) * C + c];
+    a1 += delta[static_cast<size_t>(3 * a + 1) * C + c];
+    a2 += delta[static_cast<size_t>(3 * a + 2) * C + c];
   }
   const T w = omega / static_cast<T>(e1 - e0);
   x[3 * i] += w * a0;
@@ -707,16 +753,146 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ W, const double *__
   if (f != 0.0) W[static_cast<size_t>(i) * w + j] -= f * prow[j];
 }
 
-// x = A^{-1} b with the inverse held in the right half of the Gauss-Jordan
-// workspace (row-major, stride 2n): 32 lanes per row split the dot product.
+// Blocked Gauss-Jordan on [A | I] (n x 2n, row-major) with implicit
+// pivoting: rows stay in place; column k's pivot is the not yet used row of
+// largest |value| (first such row on ties), recorded in piv[k].  After all
+// columns, row piv[k] of the right half is row k of A^{-1}.
+//
+// Panel step (one workgroup, n <= 512, thread i holds row i of the panel's
+// kGjB columns in registers): the panel's column steps are run on the panel
+// alone.  Their composite is G = I + sum_r (G e_{p_r} - e_{p_r}) e_{p_r}^T
+// (p_r the panel's pivot rows), and G e_{p_r} is obtained by carrying the
+// unit column e_{p_r} along from step r on (the steps before r leave it
+// unchanged): thread i also holds row i of Q = [G e_{p_0} .. G e_{p_{b-1}}].
+// Output Z = Q - [e_{p_0} .. e_{p_{b-1}}] and the pivot rows.
+constexpr int kGjB = 32;
+// a[c] for a runtime c without dynamic register indexing
+__device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
+  double v = 0.0;
+#pragma unroll
+  for (int t = 0; t < kGjB; ++t) v = (t == c) ? a[t] : v;
+  return v;
+}
+
+__global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const double *__restrict__ W,
+                                                   int *__restrict__ used_g, int *__restrict__ piv,
+                                                   double *__restrict__ Z) {
+  __shared__ double prow[2][2 * kGjB];
+  __shared__ double rv[2][8];
+  __shared__ int ri[2][8];
+  __shared__ int spiv[kGjB];
+  const int i = threadIdx.x;
+  const int nw = (blockDim.x + 63) / 64;
+  const bool live = i < n;
+  const size_t w2 = 2 * static_cast<size_t>(n);
+  double P[kGjB], Q[kGjB];
+#pragma unroll
+  for (int c = 0; c < kGjB; ++c) {
+    P[c] = (live && c < b) ? W[i * w2 + k0 + c] : 0.0;
+    Q[c] = 0.0;
+  }
+  bool used = !live || (k0 > 0 && used_g[i] != 0);
+  for (int c = 0; c < b; ++c) {
+    const int q = c & 1;
+    const double pc = gj_pick(P, c);
+    double best = used ? -1.0 : fabs(pc);
+    int bi = i;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if ((i & 63) == 0) {
+      rv[q][i >> 6] = best;
+      ri[q][i >> 6] = bi;
+    }
+    __syncthreads();
+    best = rv[q][0];
+    bi = ri[q][0];
+    for (int w = 1; w < nw; ++w)
+      if (rv[q][w] > best || (rv[q][w] == best && ri[q][w] < bi)) {
+        best = rv[q][w];
+        bi = ri[q][w];
+      }
+    const int p = bi;
+    if (i == p) {   // scaled pivot row [P | Q + e_c]
+      const double ip = 1.0 / pc;
+#pragma unroll
+      for (int cc = 0; cc < kGjB; ++cc) {
+        P[cc] = cc > c ? P[cc] * ip : 0.0;
+        Q[cc] = (cc == c ? 1.0 : Q[cc]) * ip;
+        prow[q][cc] = P[cc];
+        prow[q][kGjB + cc] = Q[cc];
+      }
+      used = true;
+      piv[k0 + c] = p;
+      spiv[c] = p;
+    }
+    __syncthreads();
+    if (i != p && live) {
+#pragma unroll
+      for (int cc = 0; cc < kGjB; ++cc) {
+        if (cc > c) P[cc] -= pc * prow[q][cc];
+        Q[cc] -= pc * prow[q][kGjB + cc];
+      }
+    }
+  }
+  if (live) used_g[i] = used ? 1 : 0;
+  __syncthreads();   // spiv[] of the last step is visible
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < kGjB; ++r)
+      if (r < b) Z[static_cast<size_t>(i) * b + r] = Q[r] - ((i == spiv[r]) ? 1.0 : 0.0);
+  }
+}
+
+// Trailing update of a panel, out of place: for the columns j >= k0 + b,
+// Wn[i, j] = Wo[i, j] + sum_r Z[i, r] Wo[p_r, j].  A block holds 64 columns x
+// 16 rows; the b pivot-row values of its columns are staged in LDS.
+__global__ void __launch_bounds__(256) k_gjb_update(int n, int k0, int b, const double *__restrict__ Wo,
+                                                    const double *__restrict__ Z, const int *__restrict__ piv,
+                                                    double *__restrict__ Wn) {
+  __shared__ double pr[kGjB][64];
+  const size_t w2 = 2 * static_cast<size_t>(n);
+  const int jl = threadIdx.x & 63, ig = threadIdx.x >> 6;
+  const int j = k0 + b + blockIdx.x * 64 + jl;
+  const bool colok = j < 2 * n;
+  for (int r = ig; r < b; r += 4) pr[r][jl] = colok ? Wo[piv[k0 + r] * w2 + j] : 0.0;
+  __syncthreads();
+  if (!colok) return;
+  for (int t = 0; t < 4; ++t) {
+    const int i = blockIdx.y * 16 + ig * 4 + t;
+    if (i >= n) break;
+    double acc = Wo[i * w2 + j];
+    const double *zi = Z + static_cast<size_t>(i) * b;
+    for (int r = 0; r < b; ++r) acc += zi[r] * pr[r][jl];
+    Wn[i * w2 + j] = acc;
+  }
+}
+
+// Compact inverse: Ainv[k, :] = W[piv[k], n:2n].
+__global__ void k_gjb_extract(int n, const double *__restrict__ W, const int *__restrict__ piv,
+                              double *__restrict__ Ainv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (j >= n) return;
+  Ainv[static_cast<size_t>(k) * n + j] = W[piv[k] * 2 * static_cast<size_t>(n) + n + j];
+}
+
+// x = A^{-1} b, the inverse row-major with leading dimension ld: 32 lanes
+// per row split the dot product.
 template <typename T>
-__global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__restrict__ W,
+__global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__restrict__ Ainv, size_t ld,
                                                        const T *__restrict__ b, T *__restrict__ x) {
   const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
   const int lane = threadIdx.x & 31;
   double s = 0.0;
   if (row < n) {
-    const double *r = W + static_cast<size_t>(row) * 2 * n + n;
+    const double *r = Ainv + static_cast<size_t>(row) * ld;
     for (int k = lane; k < n; k += 32) s += r[k] * static_cast<double>(b[k]);
   }
 #pragma unroll

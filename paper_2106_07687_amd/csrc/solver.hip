@@ -53,10 +53,30 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
+bool Profiler::wants(const std::string &key) const {
+  if (!on) return false;
+  if (only.empty()) return true;
+  return std::find(only.begin(), only.end(), key) != only.end();
+}
+
+bool Profiler::wants_level(int level) const {
+  if (!on) return false;
+  if (only.empty()) return true;
+  const std::string suffix = "@L" + std::to_string(level);
+  for (const auto &k : only)
+    if (k.size() > suffix.size() && k.compare(k.size() - suffix.size(), suffix.size(), suffix) == 0)
+      return true;
+  return false;
+}
+
 ProfScope::ProfScope(Profiler &pr, hipStream_t st, const char *name, int level)
     : p(pr.on ? &pr : nullptr), s(st) {
   if (!p) return;
   key = std::string(name) + "@L" + std::to_string(level);
+  if (!p->wants(key)) {
+    p = nullptr;
+    return;
+  }
   a = p->take();
   check(hipEventRecord(a, s), "hipEventRecord");
 }
@@ -92,6 +112,17 @@ LevelView DevLevel::view() const {
   v.colx = colx.p;
   v.vslot = vslot.p;
   return v;
+}
+
+hipStream_t Ctx::capture_stream() {
+  if (!cap_stream) check(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+  return cap_stream;
+}
+
+Ctx::~Ctx() {
+  s32.reset();
+  s64.reset();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 void Ctx::ensure_lps(int l, double dt) {
@@ -133,7 +164,71 @@ void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, 
 
 // ------------------------------------------------------------------ Solver
 template <typename T>
+Solver<T>::~Solver() {
+  clear_graphs();
+}
+
+template <typename T>
+void Solver<T>::clear_graphs() {
+  for (auto &kv : vgraphs_)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  vgraphs_.clear();
+  if (ginv_.exec) (void)hipGraphExecDestroy(ginv_.exec);
+  ginv_ = GraphSlot{};
+}
+
+// Graphs are used unless disabled, while not already capturing, and when no
+// profiled kernel key lives on the level (profiled launches stay eager so
+// that their events bracket them).
+template <typename T>
+bool Solver<T>::use_graph(int level) const {
+  return ctx_->prm.use_graphs != 0 && !capturing_ && !ctx_->prof.wants_level(level);
+}
+
+// Captures body() on the context's private capture stream (the kernels it
+// enqueues on ctx_->stream are redirected there and only recorded), then
+// launches the instantiated graph on the context's stream.
+template <typename T>
+template <class F>
+void Solver<T>::graph_run(GraphSlot &g, F &&body) {
+  if (!g.exec || g.gen != ctx_->graph_gen) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipStream_t cap = ctx_->capture_stream();
+    hipStream_t saved = ctx_->stream;
+    const bool prof_on = ctx_->prof.on;
+    hipGraph_t graph = nullptr;
+    check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    ctx_->stream = cap;
+    ctx_->prof.on = false;
+    capturing_ = true;
+    auto restore = [&]() {
+      ctx_->stream = saved;
+      ctx_->prof.on = prof_on;
+      capturing_ = false;
+    };
+    try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      restore();
+      throw;
+    }
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    restore();
+    check(e, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    check(ei, "hipGraphInstantiate");
+    g.gen = ctx_->graph_gen;
+  }
+  check(hipGraphLaunch(g.exec, ctx_->stream), "hipGraphLaunch");
+}
+
+template <typename T>
 void Solver<T>::setup(int finest) {
+  clear_graphs();
   ops_.clear();
   ops_.resize(finest + 1);
   for (int l = 0; l <= finest; ++l) {
@@ -152,6 +247,21 @@ void Solver<T>::setup(int finest) {
   W_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
   prow_.alloc(2 * static_cast<size_t>(n0_));
   colk_.alloc(static_cast<size_t>(n0_));
+  // blocked Gauss-Jordan (panels of kGjB columns, one thread per row) when
+  // level 0 has at most 512 unknowns, else one pivot and one elimination
+  // launch per column
+  gj_b_ = n0_ <= 512 ? kGjB : 0;
+  ainv_ = W_.p + n0_;
+  ainv_ld_ = 2 * static_cast<size_t>(n0_);
+  if (gj_b_ > 0) {
+    W2_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
+    Zp_.alloc(static_cast<size_t>(n0_) * gj_b_);
+    Ainv_.alloc(static_cast<size_t>(n0_) * n0_);
+    piv_.alloc(static_cast<size_t>(n0_));
+    used_.alloc(static_cast<size_t>(n0_));
+    ainv_ = Ainv_.p;
+    ainv_ld_ = static_cast<size_t>(n0_);
+  }
   lin_level_ = -1;
 }
 
@@ -179,13 +289,38 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
     }
   }
   if (!full) return;
-  // level-0 dense inverse (FP64): Gauss-Jordan with partial pivoting on
-  // [J_0 | I], one pivot kernel and one elimination kernel per column
+  if (use_graph(0))
+    graph_run(ginv_, [&]() { coarse_inverse(); });
+  else
+    coarse_inverse();
+  lin_level_ = level;
+}
+
+// Level-0 dense inverse (FP64): Gauss-Jordan with partial pivoting on
+// [J_0 | I], one pivot kernel and one elimination kernel per column.
+template <typename T>
+void Solver<T>::coarse_inverse() {
+  hipStream_t s = ctx_->stream;
   DevLevel &L0 = *ctx_->levels[0];
   hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, W_.p, W_.n, 0.0);
   hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
                      ops_[0].JQ.p, ops_[0].JX.p, W_.p, 2 * n0_);
   hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
+  if (gj_b_ > 0) {
+    ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
+    double *wo = W_.p, *wn = W2_.p;
+    for (int k0 = 0; k0 < n0_; k0 += gj_b_) {
+      const int b = std::min(gj_b_, n0_ - k0);
+      hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(512), 0, s, n0_, k0, b, wo, used_.p, piv_.p, Zp_.p);
+      const dim3 ug(blocks(2 * n0_ - k0 - b, 64), blocks(n0_, 16));
+      hipLaunchKernelGGL(k_gjb_update, ug, dim3(256), 0, s, n0_, k0, b, wo, Zp_.p, piv_.p, wn);
+      std::swap(wo, wn);
+    }
+    hipLaunchKernelGGL(k_gjb_extract, dim3(blocks(n0_, 256), n0_), dim3(256), 0, s, n0_, wo, piv_.p,
+                       Ainv_.p);
+    LAUNCH_CHECK("blocked coarse inverse");
+    return;
+  }
   {
     ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
     const dim3 eg(blocks(2 * n0_, 256), n0_);
@@ -195,7 +330,6 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
     }
   }
   LAUNCH_CHECK("coarse inverse");
-  lin_level_ = level;
 }
 
 template <typename T>
@@ -255,10 +389,22 @@ void Solver<T>::restrict_to(int l, const T *rf, T *rc) {
 
 template <typename T>
 void Solver<T>::vcycle(int l, const T *b, T *x) {
+  if (l > 0 && use_graph(l)) {
+    const auto key = std::make_tuple(l, static_cast<const void *>(b), static_cast<const void *>(x));
+    // bound the cache: keys of freed work vectors are never looked up again
+    if (vgraphs_.size() >= 512 && vgraphs_.find(key) == vgraphs_.end()) clear_graphs();
+    graph_run(vgraphs_[key], [&]() { vcycle_body(l, b, x); });
+    return;
+  }
+  vcycle_body(l, b, x);
+}
+
+template <typename T>
+void Solver<T>::vcycle_body(int l, const T *b, T *x) {
   hipStream_t s = ctx_->stream;
   if (l == 0) {
     ProfScope ps(ctx_->prof, s, "coarse_solve", 0);
-    hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, W_.p, b, x);
+    hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, ainv_, ainv_ld_, b, x);
     LAUNCH_CHECK("k_dense_solve");
     return;
   }
