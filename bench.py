@@ -260,6 +260,8 @@ def main():
     nL = ctx.level_info(args.coarse_level)[0]
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     log(f"setup levels 0..{args.level}: fine {nF} nodes / {cF} cells, {setup_s:.1f} s")
+    for l in range(args.level + 1):
+        log(f"workgroup sizes level {l}: {ctx.launch_config(l)}")
 
     # ---- full-depth GMG on the fine level (reference and baseline)
     sf = ctx.state(args.level)

@@ -73,6 +73,10 @@ typedef struct {
                              sweep from HIP graphs captured on first use (same
                              kernels, same order, bitwise the same results);
                              0: launch every kernel directly                    */
+  int autotune;           /* 1: at mesh setup, time the SpMV, Vanka and transfer
+                             kernels of every level at workgroup sizes 64, 128
+                             and 256 and keep the fastest (scheduling only:
+                             results are bitwise the same); 0: 256 throughout */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 
@@ -278,6 +282,10 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
+/* Workgroup sizes in use on `level`: block_sizes[0..4] = SpMV, Vanka apply,
+ * Vanka update, restriction from `level`, prolongation to `level` (5 ints,
+ * caller-owned).  DNNMG_ESTATE before dnnmg_setup_mesh. */
+int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:
  * q_blocks = number of 3x3 Q1 blocks (sum of the node neighbour counts),
  * x_entries = LPS-extra pressure entries, q_slots / x_slots = the same with

@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("newton_tol", C.c_double), ("newton_max", C.c_int),
                 ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int), ("gmres_max", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vanka_omega", C.c_double),
-                ("precision", C.c_int), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
+                ("precision", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
+                ("stream", C.c_void_p)]
 
 
 class CoarseMesh(C.Structure):
@@ -103,6 +104,7 @@ _SIGS = {
     "dnnmg_train_step_dev": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _FP]),
     "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
     "dnnmg_profile_select": (C.c_int, [_P, C.c_char_p]),
+    "dnnmg_launch_config": (C.c_int, [_P, C.c_int, _IP]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
@@ -230,6 +232,12 @@ class Context:
             k, n, ms = line.split()
             out[k] = (int(n), float(ms))
         return out
+
+    def launch_config(self, level):
+        """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong}."""
+        out = np.zeros(5, dtype=np.int32)
+        self._check(self.lib.dnnmg_launch_config(self.h, level, out.ctypes.data_as(_IP)))
+        return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong"), out.tolist()))
 
     def level_stats(self, level):
         v = [C.c_longlong() for _ in range(4)]

@@ -38,7 +38,8 @@ bool params_ok(const dnnmg_params *p) {
          p->gmres_rtol > 0 && p->gmres_rtol < 1 && p->gmres_restart >= 1 &&
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
-         (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1);
+         (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
+         (p->autotune == 0 || p->autotune == 1);
 }
 
 void upload_level(DevLevel &D, hipStream_t s) {
@@ -199,6 +200,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->vanka_omega = 0.6;
   p->precision = 1;
   p->use_graphs = 1;
+  p->autotune = 1;
   p->stream = nullptr;
   return DNNMG_OK;
 }
@@ -285,9 +287,11 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
     if (c.prm.precision == 1) {
       c.s32 = std::make_unique<Solver<float>>(&c);
       c.s32->setup(finest_level);
+      if (c.prm.autotune) c.s32->autotune();
     } else {
       c.s64 = std::make_unique<Solver<double>>(&c);
       c.s64->setup(finest_level);
+      if (c.prm.autotune) c.s64->autotune();
     }
     return DNNMG_OK;
   });
@@ -622,6 +626,28 @@ int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len) {
     std::memcpy(buf, out.c_str(), out.size() + 1);
     return DNNMG_OK;
   });
+}
+
+int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes) {
+  const int e = check_level(ctx, level);
+  if (e) return e;
+  if (!block_sizes) return DNNMG_EINVAL;
+  const Ctx &c = ctx->impl;
+  auto fill = [&](const auto &S) {
+    const auto &o = S.op(level);
+    block_sizes[0] = o.bs_spmv;
+    block_sizes[1] = o.bs_apply;
+    block_sizes[2] = o.bs_update;
+    block_sizes[3] = o.bs_restrict;
+    block_sizes[4] = o.bs_prolong;
+  };
+  if (c.s32)
+    fill(*c.s32);
+  else if (c.s64)
+    fill(*c.s64);
+  else
+    return DNNMG_ESTATE;
+  return DNNMG_OK;
 }
 
 int dnnmg_level_stats(const dnnmg_ctx *ctx, int level, long long *q_blocks, long long *x_entries,

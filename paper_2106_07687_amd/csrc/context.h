@@ -114,6 +114,10 @@ struct DevLevel {
 template <typename T>
 struct OpLevel {
   DevBuf<T> JQ, JX, inv, delta, r, b, x, t;
+  // workgroup sizes of the level's streaming kernels (autotuned at setup);
+  // restrict / prolong are the transfers between this level and the next
+  // coarser one
+  int bs_spmv = 256, bs_apply = 256, bs_update = 256, bs_restrict = 256, bs_prolong = 256;
 };
 
 class Ctx;
@@ -135,7 +139,12 @@ class Solver {
   void prolong_add(int l, const T *ec, T *xf);
   void restrict_to(int l, const T *rf, T *rc);
   OpLevel<T> &op(int l) { return ops_[l]; }
+  const OpLevel<T> &op(int l) const { return ops_[l]; }
   ~Solver();
+  // Times each streaming kernel of every level at workgroup sizes 64, 128
+  // and 256 and keeps the fastest (the choice changes scheduling only: every
+  // thread does the same arithmetic, results are bitwise the same).
+  void autotune();
 
  private:
   Ctx *ctx_;

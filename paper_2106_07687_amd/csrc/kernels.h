@@ -754,17 +754,21 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ W, const double *__
 }
 
 // Blocked Gauss-Jordan on [A | I] (n x 2n, row-major) with implicit
-// pivoting: rows stay in place; column k's pivot is the not yet used row of
-// largest |value| (first such row on ties), recorded in piv[k].  After all
-// columns, row piv[k] of the right half is row k of A^{-1}.
+// pivoting: rows stay in place; column k's pivot is a not yet used row of
+// largest |value| (see the panel's pivot key), recorded in piv[k].  After
+// all columns, row piv[k] of the right half is row k of A^{-1}.
 //
-// Panel step (one workgroup, n <= 512, thread i holds row i of the panel's
-// kGjB columns in registers): the panel's column steps are run on the panel
-// alone.  Their composite is G = I + sum_r (G e_{p_r} - e_{p_r}) e_{p_r}^T
-// (p_r the panel's pivot rows), and G e_{p_r} is obtained by carrying the
-// unit column e_{p_r} along from step r on (the steps before r leave it
-// unchanged): thread i also holds row i of Q = [G e_{p_0} .. G e_{p_{b-1}}].
-// Output Z = Q - [e_{p_0} .. e_{p_{b-1}}] and the pivot rows.
+// Panel step (one workgroup of 64 * ceil(n / 64) <= 512 threads, thread i
+// holds row i of the panel's kGjB columns in registers): the panel's column
+// steps are run on the panel alone, in place.  Their composite is
+// G = I + sum_r (G e_{p_r} - e_{p_r}) e_{p_r}^T (p_r the panel's pivot rows),
+// and G e_{p_r} is the unit column e_{p_r} carried along from step r on (the
+// steps before r leave it unchanged): in place, column r of the panel turns
+// into G e_{p_r} at step r (the classic in-place inversion update).  Output
+// Z = [G e_{p_r}] - [e_{p_r}] and the pivot rows.  The pivot is chosen on a
+// 32-bit key: |value| rounded to FP32 with its 10 low mantissa bits replaced
+// by 1023 - row (rows within 2^-13 relative count as equal; the lower row
+// wins), reduced by one integer maximum.
 constexpr int kGjB = 32;
 // a[c] for a runtime c without dynamic register indexing
 __device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
@@ -777,56 +781,36 @@ __device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
 __global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const double *__restrict__ W,
                                                    int *__restrict__ used_g, int *__restrict__ piv,
                                                    double *__restrict__ Z) {
-  __shared__ double prow[2][2 * kGjB];
-  __shared__ double rv[2][8];
-  __shared__ int ri[2][8];
+  __shared__ double prow[2][kGjB];
+  __shared__ unsigned rk[2][8];
   __shared__ int spiv[kGjB];
   const int i = threadIdx.x;
-  const int nw = (blockDim.x + 63) / 64;
+  const int nw = blockDim.x >> 6;
   const bool live = i < n;
   const size_t w2 = 2 * static_cast<size_t>(n);
-  double P[kGjB], Q[kGjB];
+  double R[kGjB];
 #pragma unroll
-  for (int c = 0; c < kGjB; ++c) {
-    P[c] = (live && c < b) ? W[i * w2 + k0 + c] : 0.0;
-    Q[c] = 0.0;
-  }
+  for (int c = 0; c < kGjB; ++c) R[c] = (live && c < b) ? W[i * w2 + k0 + c] : 0.0;
   bool used = !live || (k0 > 0 && used_g[i] != 0);
   for (int c = 0; c < b; ++c) {
     const int q = c & 1;
-    const double pc = gj_pick(P, c);
-    double best = used ? -1.0 : fabs(pc);
-    int bi = i;
+    const double rc = gj_pick(R, c);
+    unsigned key = used ? 0u
+                        : ((__float_as_uint(fabsf(static_cast<float>(rc))) & ~0x3FFu) |
+                           (1023u - static_cast<unsigned>(i)));
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
-    if ((i & 63) == 0) {
-      rv[q][i >> 6] = best;
-      ri[q][i >> 6] = bi;
-    }
+    for (int off = 32; off > 0; off >>= 1) key = max(key, static_cast<unsigned>(__shfl_xor(static_cast<int>(key), off)));
+    if ((i & 63) == 0) rk[q][i >> 6] = key;
     __syncthreads();
-    best = rv[q][0];
-    bi = ri[q][0];
-    for (int w = 1; w < nw; ++w)
-      if (rv[q][w] > best || (rv[q][w] == best && ri[q][w] < bi)) {
-        best = rv[q][w];
-        bi = ri[q][w];
-      }
-    const int p = bi;
-    if (i == p) {   // scaled pivot row [P | Q + e_c]
-      const double ip = 1.0 / pc;
+    key = rk[q][0];
+    for (int w = 1; w < nw; ++w) key = max(key, rk[q][w]);
+    const int p = 1023 - static_cast<int>(key & 0x3FFu);
+    if (i == p) {
+      const double ip = 1.0 / rc;
 #pragma unroll
       for (int cc = 0; cc < kGjB; ++cc) {
-        P[cc] = cc > c ? P[cc] * ip : 0.0;
-        Q[cc] = (cc == c ? 1.0 : Q[cc]) * ip;
-        prow[q][cc] = P[cc];
-        prow[q][kGjB + cc] = Q[cc];
+        R[cc] = (cc == c) ? ip : R[cc] * ip;
+        prow[q][cc] = R[cc];
       }
       used = true;
       piv[k0 + c] = p;
@@ -835,10 +819,7 @@ __global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const d
     __syncthreads();
     if (i != p && live) {
 #pragma unroll
-      for (int cc = 0; cc < kGjB; ++cc) {
-        if (cc > c) P[cc] -= pc * prow[q][cc];
-        Q[cc] -= pc * prow[q][kGjB + cc];
-      }
+      for (int cc = 0; cc < kGjB; ++cc) R[cc] = ((cc == c) ? 0.0 : R[cc]) - rc * prow[q][cc];
     }
   }
   if (live) used_g[i] = used ? 1 : 0;
@@ -846,7 +827,7 @@ __global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const d
   if (live) {
 #pragma unroll
     for (int r = 0; r < kGjB; ++r)
-      if (r < b) Z[static_cast<size_t>(i) * b + r] = Q[r] - ((i == spiv[r]) ? 1.0 : 0.0);
+      if (r < b) Z[static_cast<size_t>(i) * b + r] = R[r] - ((i == spiv[r]) ? 1.0 : 0.0);
   }
 }
 

@@ -266,6 +266,81 @@ void Solver<T>::setup(int finest) {
 }
 
 template <typename T>
+void Solver<T>::autotune() {
+  hipStream_t s = ctx_->stream;
+  for (auto &o : ops_) {   // defined contents for the timing runs
+    for (DevBuf<T> *v : {&o.JQ, &o.JX, &o.inv, &o.delta, &o.r, &o.b, &o.x, &o.t})
+      hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(v->n, 256), 1024)), dim3(256), 0, s, v->p, v->n,
+                         T(0));
+  }
+  LAUNCH_CHECK("autotune fill");
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw DnnmgError{DNNMG_EDEVICE, "hipEventCreate failed"};
+  }
+  const int cand[3] = {64, 128, 256};
+  auto pick = [&](auto launch) {
+    float best_t = 1e30f;
+    int best = 256;
+    for (int rep = 0; rep < 2; ++rep)
+      for (int ci = 0; ci < 3; ++ci) {
+        const int bs = cand[rep ? 2 - ci : ci];
+        launch(bs);
+        check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int k = 0; k < 4; ++k) launch(bs);
+        check(hipEventRecord(e1, s), "hipEventRecord");
+        check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (ms < best_t) {
+          best_t = ms;
+          best = bs;
+        }
+      }
+    return best;
+  };
+  try {
+    const T omega = static_cast<T>(ctx_->prm.vanka_omega);
+    for (int l = 0; l < static_cast<int>(ops_.size()); ++l) {
+      DevLevel &L = *ctx_->levels[l];
+      OpLevel<T> &o = ops_[l];
+      const LevelView v = L.view();
+      o.bs_spmv = pick([&](int bs) {
+        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
+                           o.b.p, o.t.p);
+      });
+      if (l == 0) continue;
+      o.bs_apply = pick([&](int bs) {
+        hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
+                           o.delta.p);
+      });
+      o.bs_update = pick([&](int bs) {
+        hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.delta.p, omega,
+                           o.t.p);
+      });
+      DevLevel &Cl = *ctx_->levels[l - 1];
+      OpLevel<T> &oc = ops_[l - 1];
+      TransferView tv{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
+      o.bs_restrict = pick([&](int bs) {
+        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bs)), dim3(bs), 0, s, tv, o.r.p, oc.t.p);
+      });
+      o.bs_prolong = pick([&](int bs) {
+        hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, tv, oc.x.p, o.t.p);
+      });
+      LAUNCH_CHECK("autotune");
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+template <typename T>
 void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) {
   hipStream_t s = ctx_->stream;
   if (lin_level_ < level) full = true;   // never factorised at this depth
@@ -311,7 +386,8 @@ void Solver<T>::coarse_inverse() {
     double *wo = W_.p, *wn = W2_.p;
     for (int k0 = 0; k0 < n0_; k0 += gj_b_) {
       const int b = std::min(gj_b_, n0_ - k0);
-      hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(512), 0, s, n0_, k0, b, wo, used_.p, piv_.p, Zp_.p);
+      hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(64 * blocks(n0_, 64)), 0, s, n0_, k0, b, wo, used_.p,
+                         piv_.p, Zp_.p);
       const dim3 ug(blocks(2 * n0_ - k0 - b, 64), blocks(n0_, 16));
       hipLaunchKernelGGL(k_gjb_update, ug, dim3(256), 0, s, n0_, k0, b, wo, Zp_.p, piv_.p, wn);
       std::swap(wo, wn);
@@ -337,7 +413,7 @@ void Solver<T>::spmv(int l, const T *x, const T *b, T *y) {
   DevLevel &L = *ctx_->levels[l];
   OpLevel<T> &o = ops_[l];
   ProfScope ps(ctx_->prof, ctx_->stream, b ? "residual_spmv" : "spmv", l);
-  hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, 256)), dim3(256), 0, ctx_->stream, L.view(),
+  hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, o.bs_spmv)), dim3(o.bs_spmv), 0, ctx_->stream, L.view(),
                      o.JQ.p, o.JX.p, x, b, y);
   LAUNCH_CHECK("k_spmv");
 }
@@ -354,12 +430,12 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
   }
   {
     ProfScope ps(ctx_->prof, s, "vanka_apply", l);
-    hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, 256)), dim3(256), 0, s, L.view(),
+    hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
                        o.inv.p, r, o.delta.p);
   }
   {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
-    hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, 256)), dim3(256), 0, s, L.view(),
+    hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, o.bs_update)), dim3(o.bs_update), 0, s, L.view(),
                        o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x);
   }
   LAUNCH_CHECK("vanka");
@@ -371,7 +447,8 @@ void Solver<T>::prolong_add(int l, const T *ec, T *xf) {
   DevLevel &Cl = *ctx_->levels[l - 1];
   TransferView tv{F.h.Nc, F.h.Ec, F.h.N, F.edge_ends.p, Cl.cells.p, F.rptr.p, F.ridx.p, Cl.flag.p};
   ProfScope ps(ctx_->prof, ctx_->stream, "prolong", l);
-  hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(F.h.N, 256)), dim3(256), 0, ctx_->stream, tv, ec,
+  const int bs = ops_[l].bs_prolong;
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(F.h.N, bs)), dim3(bs), 0, ctx_->stream, tv, ec,
                      xf);
   LAUNCH_CHECK("k_prolong_add");
 }
@@ -382,7 +459,8 @@ void Solver<T>::restrict_to(int l, const T *rf, T *rc) {
   DevLevel &Cl = *ctx_->levels[l - 1];
   TransferView tv{F.h.Nc, F.h.Ec, F.h.N, F.edge_ends.p, Cl.cells.p, F.rptr.p, F.ridx.p, Cl.flag.p};
   ProfScope ps(ctx_->prof, ctx_->stream, "restrict", l);
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(F.h.Nc, 256)), dim3(256), 0, ctx_->stream, tv, rf,
+  const int bs = ops_[l].bs_restrict;
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(F.h.Nc, bs)), dim3(bs), 0, ctx_->stream, tv, rf,
                      rc);
   LAUNCH_CHECK("k_restrict");
 }

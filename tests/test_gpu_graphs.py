@@ -1,4 +1,5 @@
-"""Graph replay of V-cycles and of the level-0 Gauss-Jordan sweep (GPU).
+"""Scheduling-only features (GPU): graph replay of V-cycles and of the
+level-0 Gauss-Jordan sweep, and the workgroup-size autotuner.
 
 The library captures the launch sequence of a V-cycle (and of the coarse
 inverse) once and replays it; the replay runs the same kernels in the same
@@ -97,3 +98,25 @@ def test_solves_and_steps_bitwise_equal_with_torch_stream():
     sg.close()
     se.close()
     assert n > 0
+
+
+def test_autotuned_launches_are_bitwise_equal():
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(1)
+    ctxs = []
+    for tune in (1, 0):
+        ctx = P.Context(precision=1, nu=macro.nu, autotune=tune)
+        ctx.setup_mesh(macro, LEVEL)
+        ctxs.append(ctx)
+    for l in range(LEVEL + 1):
+        cfg = ctxs[0].launch_config(l)
+        print(f"[tune] level {l}: {cfg}", flush=True)
+        assert set(cfg.values()) <= {64, 128, 256}
+        assert set(ctxs[1].launch_config(l).values()) == {256}
+    sts = [c.state(LEVEL) for c in ctxs]
+    for k in range(2):
+        infos = [c.step(st, DT) for c, st in zip(ctxs, sts)]
+        assert infos[0] == infos[1]
+        assert np.array_equal(sts[0].get()[0], sts[1].get()[0]), k
+    for st in sts:
+        st.close()
