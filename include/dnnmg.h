@@ -46,6 +46,7 @@ extern "C" {
 typedef struct dnnmg_ctx dnnmg_ctx;
 typedef struct dnnmg_state dnnmg_state;
 typedef struct dnnmg_net dnnmg_net;
+typedef struct dnnmg_batch dnnmg_batch;
 
 /* Solver parameters.  Defaults (dnnmg_params_default) follow the readings of
  * the paper's unstated constants: theta = 1/2 (Crank-Nicolson, Sec. 2.1),
@@ -268,6 +269,41 @@ int dnnmg_train_step(dnnmg_net *net, const float *X, const float *D, int T, int 
                      float lr, float *loss);
 int dnnmg_train_step_dev(dnnmg_net *net, const float *X_dev, const float *D_dev, int T, int B,
                          int ckpt, float lr, float *loss);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent simulations of the plain method (Sec. 2: each one the
+ * time step of eqs. nonlinearshort/newton on its own mesh and viscosity),
+ * advanced together.  Simulations of equal depth are merged into one group
+ * whose launches cover all of them (the level-0 direct solve is block
+ * diagonal, one block per simulation, each at most 1024 unknowns); the groups
+ * run concurrently on streams the batch creates (params->stream is ignored).
+ * A group's Newton and GMRES norms span its members: a group step converges
+ * when the union's residual meets newton_tol, so each member's does. */
+typedef struct {
+  const dnnmg_coarse_mesh *mesh;   /* macro mesh (borrowed for the create call) */
+  double nu;                       /* viscosity of this simulation              */
+  int depth;                       /* finest level (0..9)                      */
+} dnnmg_sim_desc;
+/* Creates the batch: groups by depth, merged meshes, one context and one
+ * zero state per group.  DNNMG_EINVAL on a bad description (message through
+ * dnnmg_batch_last_error when *out could not be made: NULL handle). */
+int dnnmg_batch_create(const dnnmg_params *p, const dnnmg_sim_desc *sims, int n_sims, dnnmg_batch **out);
+int dnnmg_batch_destroy(dnnmg_batch *b);
+const char *dnnmg_batch_last_error(const dnnmg_batch *b);
+int dnnmg_batch_groups(const dnnmg_batch *b, int *n_groups);
+/* Depth, member count and node count (union) of group g. */
+int dnnmg_batch_group_info(const dnnmg_batch *b, int g, int *depth, int *n_sims, int *n_nodes);
+/* Group of simulation `sim` and its node count at its depth. */
+int dnnmg_batch_info(const dnnmg_batch *b, int sim, int *group, int *n_nodes);
+/* Host copies of one simulation's state (3 N doubles, node-interleaved, in
+ * the node numbering a context of that mesh alone would use); _set also sets
+ * the time of the simulation's whole group. */
+int dnnmg_batch_set(dnnmg_batch *b, int sim, const double *uvp, double t);
+int dnnmg_batch_get(const dnnmg_batch *b, int sim, double *uvp, double *t);
+/* One time step of every simulation; stats (optional) receives one entry per
+ * group.  On DNNMG_ENOCONV the failing group's states are rolled back; the
+ * other groups have advanced. */
+int dnnmg_batch_step(dnnmg_batch *b, double dt, dnnmg_step_stats *stats);
 
 /* Instrumentation (not part of the method).  When enabled, the library
  * records a pair of HIP events on its stream around every launch of its main

@@ -3,6 +3,6 @@
 The numerical work runs in libdnnmg.so (hand-written gfx950 HIP kernels).  This
 package holds only the ctypes binding (`_lib`) and the build script (`build`).
 """
-from ._lib import (Context, State, Net, DnnmgError, load, header_symbols, LIB_PATH)
+from ._lib import (Context, State, Net, Batch, DnnmgError, load, header_symbols, LIB_PATH)
 
-__all__ = ["Context", "State", "Net", "DnnmgError", "load", "header_symbols", "LIB_PATH"]
+__all__ = ["Context", "State", "Net", "Batch", "DnnmgError", "load", "header_symbols", "LIB_PATH"]

@@ -44,6 +44,10 @@ class CoarseMesh(C.Structure):
                 ("n_curve", C.c_int), ("curve", C.POINTER(C.c_double))]
 
 
+class SimDesc(C.Structure):
+    _fields_ = [("mesh", C.POINTER(CoarseMesh)), ("nu", C.c_double), ("depth", C.c_int)]
+
+
 class StepStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int), ("gmres_iters", C.c_int),
                 ("gmres_iters_max", C.c_int), ("res_initial", C.c_double),
@@ -108,6 +112,15 @@ _SIGS = {
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "dnnmg_batch_create": (C.c_int, [C.POINTER(Params), C.POINTER(SimDesc), C.c_int, C.POINTER(_P)]),
+    "dnnmg_batch_destroy": (C.c_int, [_P]),
+    "dnnmg_batch_last_error": (C.c_char_p, [_P]),
+    "dnnmg_batch_groups": (C.c_int, [_P, _IP]),
+    "dnnmg_batch_group_info": (C.c_int, [_P, C.c_int, _IP, _IP, _IP]),
+    "dnnmg_batch_info": (C.c_int, [_P, C.c_int, _IP, _IP]),
+    "dnnmg_batch_set": (C.c_int, [_P, C.c_int, _DP, C.c_double]),
+    "dnnmg_batch_get": (C.c_int, [_P, C.c_int, _DP, C.POINTER(C.c_double)]),
+    "dnnmg_batch_step": (C.c_int, [_P, C.c_double, C.POINTER(StepStats)]),
 }
 
 _lib = None
@@ -142,6 +155,29 @@ def _dp(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _coarse_mesh(macro):
+    """CoarseMesh struct of a synthetic macro mesh, plus the arrays it points to."""
+    xy = _f64(macro.xy).reshape(-1)
+    q = np.ascontiguousarray(macro.quads, dtype=np.int32).reshape(-1)
+    be = np.ascontiguousarray(macro.bedges, dtype=np.int32).reshape(-1)
+    cv = _f64(macro.curves).reshape(-1)
+    if cv.size == 0:
+        cv = np.zeros(5)
+    m = CoarseMesh(macro.n_vert, _dp(xy), macro.n_cell, q.ctypes.data_as(_IP),
+                   be.size // 3, be.ctypes.data_as(_IP), macro.curves.shape[0], _dp(cv))
+    return m, (xy, q, be, cv)
+
+
+def _params(precision, kw):
+    lib = load()
+    p = Params()
+    lib.dnnmg_params_default(C.byref(p))
+    p.precision = precision
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
 
 
 class Context:
@@ -184,14 +220,7 @@ class Context:
         self._check(self.lib.dnnmg_set_params(self.h, C.byref(self.params)))
 
     def setup_mesh(self, macro, finest_level):
-        xy = _f64(macro.xy).reshape(-1)
-        q = np.ascontiguousarray(macro.quads, dtype=np.int32).reshape(-1)
-        be = np.ascontiguousarray(macro.bedges, dtype=np.int32).reshape(-1)
-        cv = _f64(macro.curves).reshape(-1)
-        if cv.size == 0:
-            cv = np.zeros(5)
-        m = CoarseMesh(macro.n_vert, _dp(xy), macro.n_cell, q.ctypes.data_as(_IP),
-                       be.size // 3, be.ctypes.data_as(_IP), macro.curves.shape[0], _dp(cv))
+        m, keep = _coarse_mesh(macro)
         self._check(self.lib.dnnmg_setup_mesh(self.h, C.byref(m), finest_level))
         self.finest = finest_level
 
@@ -426,3 +455,73 @@ class State:
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx.lib.dnnmg_state_destroy(self.h)
         self.h = None
+
+
+class Batch:
+    """Owner of one dnnmg_batch: `sims` is a list of (macro mesh, nu, depth)."""
+
+    def __init__(self, sims, precision=1, **kw):
+        self.lib = load()
+        self.params = _params(precision, kw)
+        keep, descs = [], (SimDesc * len(sims))()
+        meshes = []
+        for k, (macro, nu, depth) in enumerate(sims):
+            m, arrs = _coarse_mesh(macro)
+            meshes.append(m)
+            keep.append(arrs)
+            descs[k].mesh = C.pointer(meshes[-1])
+            descs[k].nu = nu
+            descs[k].depth = depth
+        h = _P()
+        rc = self.lib.dnnmg_batch_create(C.byref(self.params), descs, len(sims), C.byref(h))
+        if rc != OK:
+            raise DnnmgError(rc, "dnnmg_batch_create failed")
+        self.h = h
+        self.n_sims = len(sims)
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = self.lib.dnnmg_batch_last_error(self.h)
+            raise DnnmgError(rc, msg.decode() if msg else "")
+
+    def n_groups(self):
+        n = C.c_int()
+        self._check(self.lib.dnnmg_batch_groups(self.h, C.byref(n)))
+        return n.value
+
+    def group_info(self, g):
+        d, n, nn = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.lib.dnnmg_batch_group_info(self.h, g, C.byref(d), C.byref(n), C.byref(nn)))
+        return dict(depth=d.value, n_sims=n.value, n_nodes=nn.value)
+
+    def info(self, sim):
+        g, n = C.c_int(), C.c_int()
+        self._check(self.lib.dnnmg_batch_info(self.h, sim, C.byref(g), C.byref(n)))
+        return g.value, n.value
+
+    def set(self, sim, uvp, t):
+        uvp = _f64(uvp)
+        self._check(self.lib.dnnmg_batch_set(self.h, sim, _dp(uvp), t))
+
+    def get(self, sim):
+        out = np.empty(3 * self.info(sim)[1])
+        t = C.c_double()
+        self._check(self.lib.dnnmg_batch_get(self.h, sim, _dp(out), C.byref(t)))
+        return out, t.value
+
+    def step(self, dt):
+        """One time step of every simulation; per-group stats dicts."""
+        st = (StepStats * self.n_groups())()
+        self._check(self.lib.dnnmg_batch_step(self.h, dt, st))
+        return [x.as_dict() for x in st]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dnnmg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

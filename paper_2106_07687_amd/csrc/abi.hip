@@ -253,6 +253,8 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
       return fail(ctx, DNNMG_EINVAL, "boundary edge out of range");
   }
   if (ctx->impl.finest >= 0) return fail(ctx, DNNMG_ESTATE, "mesh already set up");
+  if (!ctx->impl.macro_blk.empty() && static_cast<int>(ctx->impl.macro_blk.size()) != m->n_cell)
+    return fail(ctx, DNNMG_EINVAL, "batch cell map does not match the macro mesh");
   return guarded(ctx, [&]() {
     Ctx &c = ctx->impl;
     std::string err;
@@ -273,6 +275,19 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
       if (l == 0) {   // level 0 has no coarser multigrid level
         D->h.rptr.clear();
         D->h.ridx.clear();
+      }
+      if (!c.macro_blk.empty()) {   // simulation batch: viscosity per node, level-0 blocks
+        const HostLevel &h = D->h;
+        std::vector<double> nu(h.N);
+        std::vector<int> b0(l == 0 ? h.N : 0);
+        for (int i = 0; i < h.N; ++i) {
+          const int cell = h.cadj[h.cadj_ptr[i]] >> 2;   // cells descend as 4 c + k
+          const int blk = c.macro_blk[cell >> (2 * l + 2)];
+          nu[i] = c.blk_nu[blk];
+          if (l == 0) b0[i] = blk;
+        }
+        D->nnu.upload(nu, c.stream);
+        if (l == 0) c.blk0 = std::move(b0);
       }
       upload_level(*D, c.stream);
       c.levels.push_back(std::move(D));

@@ -106,6 +106,7 @@ struct DevLevel {
   DevBuf<int> cadj_ptr, cadj, padj_ptr, padj, patch_nodes, wq, wx, oq, ox, colq, colx;
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
   DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
+  DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)
   double sP_dt = -1.0, sP_nu = -1.0, sP_alpha0 = -1.0;
   LevelView view() const;
 };
@@ -172,10 +173,9 @@ class Solver {
   // per column), second workspace, panel transforms, pivot rows, used-row
   // flags, and the compact inverse read by the coarse solve
   int gj_b_ = 0;
+  int nblk_ = 1, nb_ = 0;          // level-0 blocks and their padded size (unknowns)
   DevBuf<double> W2_, Zp_, Ainv_;
-  DevBuf<int> piv_, used_;
-  const double *ainv_ = nullptr;   // A0^{-1}, row-major with leading dimension ainv_ld_
-  size_t ainv_ld_ = 0;
+  DevBuf<int> piv_, used_, g2l_, blk_, bdof_;
   // GMRES workspace
   int gm_level_ = -1, gm_m_ = 0;
   DevBuf<T> V_, Z_, w_;
@@ -192,6 +192,11 @@ class Ctx {
   std::string last_error;
   Profiler prof;
   long graph_gen = 0;              // bumped when captured graphs go stale
+  // simulation batches (empty otherwise): macro cell -> simulation, its
+  // viscosity, and level-0 node -> simulation (the coarse solve's blocks)
+  std::vector<int> macro_blk;
+  std::vector<double> blk_nu;
+  std::vector<int> blk0;
   hipStream_t cap_stream = nullptr;
   hipStream_t capture_stream();    // private stream used only for graph capture
   ~Ctx();

@@ -33,6 +33,7 @@ struct LevelView {
   const int *wq, *wx, *oq, *ox;
   const int *colq, *colx;
   const uint8_t *vslot;     // 16 per cell
+  const double *nnu;        // N: viscosity per node (simulation batches), or null: Phys::nu
 };
 
 struct Phys {
@@ -115,6 +116,7 @@ __device__ __constant__ int kChildToPatch[4][4] = {{0, 1, 4, 3}, {1, 2, 5, 4}, {
 __global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
   const int P = blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= L.NP) return;
+  const double nu = L.nnu ? L.nnu[L.cells[4 * P].x] : ph.nu;
   double S[9][9];
 #pragma unroll
   for (int i = 0; i < 9; ++i)
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *
 #pragma unroll
         for (int b = 0; b < 4; ++b) St[a][b] += det * (gx[a] * gx[b] + gy[a] * gy[b]);
     }
-    const double alpha = ph.alpha0 / (ph.nu / area + ph.inv_dt);
+    const double alpha = ph.alpha0 / (nu / area + ph.inv_dt);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const do
                            const double *__restrict__ sP, double *__restrict__ R) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
-  const double th = ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  const double th = ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
   double Au = 0.0, Av = 0.0, Ap = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const do
 __global__ void __launch_bounds__(128) k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
-  const double tho = 1.0 - ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  const double tho = 1.0 - ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
   double fu = 0.0, fv = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
@@ -327,7 +329,7 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
   const int s = i / kS, lane = i % kS;
-  const double th = ph.theta, nu = ph.nu, idt = ph.inv_dt;
+  const double th = ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
   const size_t base = static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
   const uint8_t fl = L.flag[i];
   const bool dir = fl & 1;
@@ -695,6 +697,46 @@ __global__ void __launch_bounds__(64) k_dense_from_sell(LevelView L, const T *__
   }
 }
 
+// Block-diagonal level 0 (simulation batches; one block for a single mesh):
+// node i belongs to block blk[i] with local index g2l[i].  Block s of the
+// workspace is [A_s | I] padded to nb unknowns (nb x 2 nb, row-major; the
+// padding rows and columns hold the identity).
+template <typename T>
+__global__ void __launch_bounds__(64) k_dense_from_sell_blk(LevelView L, const T *__restrict__ JQ,
+                                                           const T *__restrict__ JX, const int *__restrict__ g2l,
+                                                           const int *__restrict__ blk, int nb,
+                                                           double *__restrict__ W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.N) return;
+  const int s = i / kS, lane = i % kS;
+  const size_t w2 = 2 * static_cast<size_t>(nb);
+  double *Ws = W + static_cast<size_t>(blk[i]) * nb * w2;
+  const int li = g2l[i];
+  for (int k = 0; k < L.wq[s]; ++k) {
+    const int lj = g2l[L.colq[(L.oq[s] + k) * kS + lane]];
+    for (int f = 0; f < 3; ++f)
+      for (int g = 0; g < 3; ++g)
+        Ws[(3 * li + f) * w2 + 3 * lj + g] +=
+            static_cast<double>(JQ[(static_cast<size_t>(L.oq[s] + k) * 9 + 3 * f + g) * kS + lane]);
+  }
+  for (int k = 0; k < L.wx[s]; ++k) {
+    const int lj = g2l[L.colx[(L.ox[s] + k) * kS + lane]];
+    Ws[(3 * li + 2) * w2 + 3 * lj + 2] += static_cast<double>(JX[static_cast<size_t>(L.ox[s] + k) * kS + lane]);
+  }
+}
+
+// Identity right halves and identity padding rows of every block
+// (bdof[s nb + r] < 0 marks a padding unknown).
+__global__ void k_gjb_init(int nblk, int nb, const int *__restrict__ bdof, double *__restrict__ W) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sb = blockIdx.y;
+  if (r >= nb || sb >= nblk) return;
+  const size_t w2 = 2 * static_cast<size_t>(nb);
+  double *Ws = W + static_cast<size_t>(sb) * nb * w2;
+  Ws[r * w2 + nb + r] = 1.0;
+  if (bdof[static_cast<size_t>(sb) * nb + r] < 0) Ws[r * w2 + r] = 1.0;
+}
+
 // Multi-workgroup Gauss-Jordan, one pivot column k per pair of launches.
 // Pivot step (one workgroup): partial pivoting on column k, row swap,
 // normalisation of the pivot row, copies of the pivot row (prow) and of
@@ -758,7 +800,7 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ W, const double *__
 // largest |value| (see the panel's pivot key), recorded in piv[k].  After
 // all columns, row piv[k] of the right half is row k of A^{-1}.
 //
-// Panel step (one workgroup of 64 * ceil(n / 64) <= 512 threads, thread i
+// Panel step (one workgroup of 64 * ceil(n / 64) <= 1024 threads, thread i
 // holds row i of the panel's kGjB columns in registers): the panel's column
 // steps are run on the panel alone, in place.  Their composite is
 // G = I + sum_r (G e_{p_r} - e_{p_r}) e_{p_r}^T (p_r the panel's pivot rows),
@@ -778,11 +820,16 @@ __device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
   return v;
 }
 
-__global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const double *__restrict__ W,
+__global__ void __launch_bounds__(1024) k_gjb_panel(int n, int k0, int b, const double *__restrict__ W,
                                                    int *__restrict__ used_g, int *__restrict__ piv,
                                                    double *__restrict__ Z) {
+  // block blockIdx.x of a block-diagonal batch: its own workspace and records
+  W += static_cast<size_t>(blockIdx.x) * n * 2 * n;
+  used_g += static_cast<size_t>(blockIdx.x) * n;
+  piv += static_cast<size_t>(blockIdx.x) * n;
+  Z += static_cast<size_t>(blockIdx.x) * n * kGjB;
   __shared__ double prow[2][kGjB];
-  __shared__ unsigned rk[2][8];
+  __shared__ unsigned rk[2][16];
   __shared__ int spiv[kGjB];
   const int i = threadIdx.x;
   const int nw = blockDim.x >> 6;
@@ -837,6 +884,11 @@ __global__ void __launch_bounds__(512) k_gjb_panel(int n, int k0, int b, const d
 __global__ void __launch_bounds__(256) k_gjb_update(int n, int k0, int b, const double *__restrict__ Wo,
                                                     const double *__restrict__ Z, const int *__restrict__ piv,
                                                     double *__restrict__ Wn) {
+  const size_t sb = blockIdx.z;   // block of a block-diagonal batch
+  Wo += sb * n * 2 * n;
+  Wn += sb * n * 2 * n;
+  Z += sb * n * kGjB;
+  piv += sb * n;
   __shared__ double pr[kGjB][64];
   const size_t w2 = 2 * static_cast<size_t>(n);
   const int jl = threadIdx.x & 63, ig = threadIdx.x >> 6;
@@ -860,6 +912,10 @@ __global__ void k_gjb_extract(int n, const double *__restrict__ W, const int *__
                               double *__restrict__ Ainv) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
+  const size_t sb = blockIdx.z;
+  W += sb * n * 2 * n;
+  piv += sb * n;
+  Ainv += sb * n * n;
   if (j >= n) return;
   Ainv[static_cast<size_t>(k) * n + j] = W[piv[k] * 2 * static_cast<size_t>(n) + n + j];
 }
@@ -879,6 +935,31 @@ __global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__re
 #pragma unroll
   for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
   if (row < n && lane == 0) x[row] = static_cast<T>(s);
+}
+
+// x = blockdiag(A_s)^{-1} b on the padded blocks (compact inverses, nb x nb
+// each): 32 lanes per row split the dot product; padding unknowns skipped.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_solve_blk(int nblk, int nb, const double *__restrict__ Ainv,
+                                                         const int *__restrict__ bdof, const T *__restrict__ b,
+                                                         T *__restrict__ x) {
+  const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int lane = threadIdx.x & 31;
+  const bool ok = row < nblk * nb;
+  const int sb = ok ? row / nb : 0;
+  const int dst = ok ? bdof[row] : -1;
+  double s = 0.0;
+  if (dst >= 0) {
+    const double *r = Ainv + static_cast<size_t>(row) * nb;
+    const int *bd = bdof + static_cast<size_t>(sb) * nb;
+    for (int k = lane; k < nb; k += 32) {
+      const int g = bd[k];
+      if (g >= 0) s += r[k] * static_cast<double>(b[g]);
+    }
+  }
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+  if (dst >= 0 && lane == 0) x[dst] = static_cast<T>(s);
 }
 
 __global__ void k_identity_right(int n, double *__restrict__ W) {

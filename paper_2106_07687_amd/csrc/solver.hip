@@ -111,6 +111,7 @@ LevelView DevLevel::view() const {
   v.colq = colq.p;
   v.colx = colx.p;
   v.vslot = vslot.p;
+  v.nnu = nnu.p;
   return v;
 }
 
@@ -244,23 +245,43 @@ void Solver<T>::setup(int finest) {
     o.t.alloc(3 * static_cast<size_t>(h.N));
   }
   n0_ = 3 * ctx_->levels[0]->h.N;
-  W_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
-  prow_.alloc(2 * static_cast<size_t>(n0_));
-  colk_.alloc(static_cast<size_t>(n0_));
-  // blocked Gauss-Jordan (panels of kGjB columns, one thread per row) when
-  // level 0 has at most 512 unknowns, else one pivot and one elimination
-  // launch per column
-  gj_b_ = n0_ <= 512 ? kGjB : 0;
-  ainv_ = W_.p + n0_;
-  ainv_ld_ = 2 * static_cast<size_t>(n0_);
+  // Level-0 blocks: one per simulation of a batch (its nodes are those of its
+  // own mesh), a single block otherwise.  A block is solved by blocked
+  // Gauss-Jordan (panels of kGjB columns, one thread per row) when it has at
+  // most 1024 unknowns; a single larger block falls back to one pivot and one
+  // elimination launch per column.
+  const int N0 = ctx_->levels[0]->h.N;
+  std::vector<int> blk(N0, 0);
+  if (!ctx_->blk0.empty()) {
+    if (static_cast<int>(ctx_->blk0.size()) != N0)
+      throw DnnmgError{DNNMG_EINVAL, "level-0 block map does not match the mesh"};
+    blk = ctx_->blk0;
+  }
+  nblk_ = 1 + *std::max_element(blk.begin(), blk.end());
+  std::vector<int> cnt(nblk_, 0), g2l(N0);
+  for (int i = 0; i < N0; ++i) g2l[i] = cnt[blk[i]]++;
+  nb_ = 3 * *std::max_element(cnt.begin(), cnt.end());
+  gj_b_ = nb_ <= 1024 ? kGjB : 0;
+  if (gj_b_ == 0 && nblk_ > 1)
+    throw DnnmgError{DNNMG_EINVAL, "a level-0 block of the batch exceeds 1024 unknowns"};
   if (gj_b_ > 0) {
-    W2_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
-    Zp_.alloc(static_cast<size_t>(n0_) * gj_b_);
-    Ainv_.alloc(static_cast<size_t>(n0_) * n0_);
-    piv_.alloc(static_cast<size_t>(n0_));
-    used_.alloc(static_cast<size_t>(n0_));
-    ainv_ = Ainv_.p;
-    ainv_ld_ = static_cast<size_t>(n0_);
+    std::vector<int> bdof(static_cast<size_t>(nblk_) * nb_, -1);
+    for (int i = 0; i < N0; ++i)
+      for (int f = 0; f < 3; ++f) bdof[static_cast<size_t>(blk[i]) * nb_ + 3 * g2l[i] + f] = 3 * i + f;
+    const size_t wsz = static_cast<size_t>(nblk_) * nb_ * 2 * nb_;
+    W_.alloc(wsz);
+    W2_.alloc(wsz);
+    Zp_.alloc(static_cast<size_t>(nblk_) * nb_ * gj_b_);
+    Ainv_.alloc(static_cast<size_t>(nblk_) * nb_ * nb_);
+    piv_.alloc(static_cast<size_t>(nblk_) * nb_);
+    used_.alloc(static_cast<size_t>(nblk_) * nb_);
+    g2l_.upload(g2l, ctx_->stream);
+    blk_.upload(blk, ctx_->stream);
+    bdof_.upload(bdof, ctx_->stream);
+  } else {
+    W_.alloc(static_cast<size_t>(n0_) * 2 * n0_);
+    prow_.alloc(2 * static_cast<size_t>(n0_));
+    colk_.alloc(static_cast<size_t>(n0_));
   }
   lin_level_ = -1;
 }
@@ -377,33 +398,34 @@ template <typename T>
 void Solver<T>::coarse_inverse() {
   hipStream_t s = ctx_->stream;
   DevLevel &L0 = *ctx_->levels[0];
-  hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, W_.p, W_.n, 0.0);
-  hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
-                     ops_[0].JQ.p, ops_[0].JX.p, W_.p, 2 * n0_);
-  hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
+  ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
+  hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, W_.p, W_.n, 0.0);
   if (gj_b_ > 0) {
-    ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
+    const int nb = nb_;
+    hipLaunchKernelGGL(k_dense_from_sell_blk<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
+                       ops_[0].JQ.p, ops_[0].JX.p, g2l_.p, blk_.p, nb, W_.p);
+    hipLaunchKernelGGL(k_gjb_init, dim3(blocks(nb, 256), nblk_), dim3(256), 0, s, nblk_, nb, bdof_.p, W_.p);
     double *wo = W_.p, *wn = W2_.p;
-    for (int k0 = 0; k0 < n0_; k0 += gj_b_) {
-      const int b = std::min(gj_b_, n0_ - k0);
-      hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(64 * blocks(n0_, 64)), 0, s, n0_, k0, b, wo, used_.p,
+    for (int k0 = 0; k0 < nb; k0 += gj_b_) {
+      const int b = std::min(gj_b_, nb - k0);
+      hipLaunchKernelGGL(k_gjb_panel, dim3(nblk_), dim3(64 * blocks(nb, 64)), 0, s, nb, k0, b, wo, used_.p,
                          piv_.p, Zp_.p);
-      const dim3 ug(blocks(2 * n0_ - k0 - b, 64), blocks(n0_, 16));
-      hipLaunchKernelGGL(k_gjb_update, ug, dim3(256), 0, s, n0_, k0, b, wo, Zp_.p, piv_.p, wn);
+      const dim3 ug(blocks(2 * nb - k0 - b, 64), blocks(nb, 16), nblk_);
+      hipLaunchKernelGGL(k_gjb_update, ug, dim3(256), 0, s, nb, k0, b, wo, Zp_.p, piv_.p, wn);
       std::swap(wo, wn);
     }
-    hipLaunchKernelGGL(k_gjb_extract, dim3(blocks(n0_, 256), n0_), dim3(256), 0, s, n0_, wo, piv_.p,
+    hipLaunchKernelGGL(k_gjb_extract, dim3(blocks(nb, 256), nb, nblk_), dim3(256), 0, s, nb, wo, piv_.p,
                        Ainv_.p);
     LAUNCH_CHECK("blocked coarse inverse");
     return;
   }
-  {
-    ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
-    const dim3 eg(blocks(2 * n0_, 256), n0_);
-    for (int k = 0; k < n0_; ++k) {
-      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
-      hipLaunchKernelGGL(k_gj_elim, eg, dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
-    }
+  hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
+                     ops_[0].JQ.p, ops_[0].JX.p, W_.p, 2 * n0_);
+  hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
+  const dim3 eg(blocks(2 * n0_, 256), n0_);
+  for (int k = 0; k < n0_; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
+    hipLaunchKernelGGL(k_gj_elim, eg, dim3(256), 0, s, n0_, k, W_.p, prow_.p, colk_.p);
   }
   LAUNCH_CHECK("coarse inverse");
 }
@@ -482,7 +504,12 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
   hipStream_t s = ctx_->stream;
   if (l == 0) {
     ProfScope ps(ctx_->prof, s, "coarse_solve", 0);
-    hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, ainv_, ainv_ld_, b, x);
+    if (gj_b_ > 0)
+      hipLaunchKernelGGL(k_dense_solve_blk<T>, dim3(blocks(static_cast<size_t>(nblk_) * nb_, 8)), dim3(256), 0,
+                         s, nblk_, nb_, Ainv_.p, bdof_.p, b, x);
+    else
+      hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, W_.p + n0_,
+                         2 * static_cast<size_t>(n0_), b, x);
     LAUNCH_CHECK("k_dense_solve");
     return;
   }

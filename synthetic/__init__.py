@@ -6,8 +6,8 @@ of the method's arithmetic (no refinement, no quadrature, no solver, no
 network evaluation), so the oracle and the HIP path can both consume it
 without sharing any code of the method.
 """
-from .channel import (MacroMesh, channel_obstacle, rectangle, random_state,
-                      gru_weights, WORKLOADS)
+from .channel import (MacroMesh, channel_obstacle, channel_obstacles, rectangle,
+                      random_state, gru_weights, WORKLOADS)
 
-__all__ = ["MacroMesh", "channel_obstacle", "rectangle", "random_state",
-           "gru_weights", "WORKLOADS"]
+__all__ = ["MacroMesh", "channel_obstacle", "channel_obstacles", "rectangle",
+           "random_state", "gru_weights", "WORKLOADS"]

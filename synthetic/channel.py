@@ -118,6 +118,107 @@ def channel_obstacle(seed: int, Re: float = 100.0, box: float = 0.1,
                      info=dict(seed=seed, Re=Re, cx=cx, cy=cy, r=r))
 
 
+def _strip_mesh(obs, n_downstream):
+    """Macro mesh of the channel with one or more obstacles in x-disjoint
+    strips.  `obs` rows (cx, cy, a, b, phi, w), sorted by cx; w is the
+    half-width of the square box holding the obstacle.  Every vertical grid
+    line carries 4 vertices (y = 0, y1, y2, H): inside a strip (y1, y2) are its
+    box's y-range; the columns between strips are 3 trapezoids joining the
+    neighbouring strips' lines (so the mesh stays conforming)."""
+    xy, quads, bedges, curves = [], [], [], []
+
+    def column_line(x, y1, y2):
+        base = len(xy)
+        for y in (0.0, y1, y2, CHANNEL_H):
+            xy.append((x, y))
+        return [base, base + 1, base + 2, base + 3]
+
+    def join(lft, rgt):
+        for r in range(3):
+            quads.append((lft[r], rgt[r], rgt[r + 1], lft[r + 1]))
+        bedges.append((lft[0], rgt[0], TAG_WALL))
+        bedges.append((lft[3], rgt[3], TAG_WALL))
+
+    first = obs[0]
+    line = column_line(0.0, first[1] - first[5], first[1] + first[5])
+    for r in range(3):
+        bedges.append((line[r], line[r + 1], TAG_INFLOW))
+    for k, (cx, cy, a, b, phi, w) in enumerate(obs):
+        left = column_line(cx - w, cy - w, cy + w)
+        join(line, left)
+        right = column_line(cx + w, cy - w, cy + w)
+        # bottom and top cells of the strip, then the hole ring
+        quads.append((left[0], right[0], right[1], left[1]))
+        quads.append((left[2], right[2], right[3], left[3]))
+        bedges.append((left[0], right[0], TAG_WALL))
+        bedges.append((left[3], right[3], TAG_WALL))
+        corners = [right[2], left[2], left[1], right[1]]   # from the upper right, CCW
+        arc = []
+        for q in range(4):
+            arc.append(len(xy))
+            xy.append(tuple(_ray_to_ellipse(cx, cy, a, b, phi, np.pi / 4 + q * np.pi / 2)))
+        for q in range(4):
+            q1 = (q + 1) % 4
+            quads.append((arc[q], corners[q], corners[q1], arc[q1]))
+            bedges.append((arc[q], arc[q1], TAG_OBSTACLE + k))
+        curves.append((cx, cy, a, b, phi))
+        line = right
+    last = obs[-1]
+    x0 = last[0] + last[5]
+    wts = np.cumsum(np.arange(1, n_downstream + 1, dtype=np.float64))
+    wts /= wts[-1]
+    for t in wts:
+        nxt = column_line(x0 + (CHANNEL_L - x0) * t, last[1] - last[5], last[1] + last[5])
+        join(line, nxt)
+        line = nxt
+    for r in range(3):
+        bedges.append((line[r], line[r + 1], TAG_OUTFLOW))
+    return (np.asarray(xy, dtype=np.float64), np.asarray(quads, dtype=np.int32),
+            np.asarray(bedges, dtype=np.int32), np.asarray(curves, dtype=np.float64))
+
+
+def channel_obstacles(seed: int, n_downstream: int = 3, max_tries: int = 2000) -> MacroMesh:
+    """Channel with 1-3 seeded circular or elliptical obstacles, a seeded
+    Reynolds number and a seeded mesh depth (the batched-solve workload).
+
+    Draw order (PCG64, numpy.random.default_rng(seed)): n_obs ~ U{1, 2, 3};
+    per obstacle: ellipse with probability 1/2, semi-axis a ~ U[0.03, 0.07],
+    aspect ~ U[1, 2] (b = a / aspect; a circle has b = a), rotation
+    phi ~ U[0, pi), then centres drawn x ~ U[0.15, 1.0], y ~ U[0.1, 0.31]
+    until the obstacle keeps 0.05 from both walls and its square box (half-
+    width w = min(1.7 a, cy - 0.02, H - cy - 0.02)) keeps a 0.05 x-gap to the
+    boxes already placed (so obstacles are >= 0.05 apart); then Re ~ U[50, 200]
+    and depth ~ U{4, ..., 7}.  nu = 0.1 / Re as in `channel_obstacle`.
+    """
+    rng = np.random.default_rng(seed)
+    n_obs = int(rng.integers(1, 4))
+    placed = []
+    for _ in range(n_obs):
+        ellipse = rng.uniform() < 0.5
+        a = rng.uniform(0.03, 0.07)
+        aspect = rng.uniform(1.0, 2.0)
+        b = a / aspect if ellipse else a
+        phi = rng.uniform(0.0, np.pi) if ellipse else 0.0
+        for _ in range(max_tries):
+            cx = rng.uniform(0.15, 1.0)
+            cy = rng.uniform(0.1, 0.31)
+            if cy - a < 0.05 or CHANNEL_H - cy - a < 0.05:
+                continue
+            w = min(1.7 * a, cy - 0.02, CHANNEL_H - cy - 0.02)
+            if cx - w < 0.05:
+                continue
+            if all(abs(cx - o[0]) >= w + o[5] + 0.05 for o in placed):
+                placed.append((cx, cy, a, b, phi, w))
+                break
+    placed.sort(key=lambda o: o[0])
+    Re = rng.uniform(50.0, 200.0)
+    depth = int(rng.integers(4, 8))
+    xy, quads, bedges, curves = _strip_mesh(placed, n_downstream)
+    return MacroMesh(xy=xy, quads=quads, bedges=bedges, curves=curves, nu=0.1 / Re,
+                     info=dict(seed=seed, Re=Re, depth=depth, n_obs=len(placed),
+                               obstacles=[tuple(o[:5]) for o in placed]))
+
+
 def rectangle(nx: int, ny: int, Lx: float = 1.0, Ly: float = 1.0, nu: float = 0.1,
               x0: float = 0.0, y0: float = 0.0, skew: float = 0.0) -> MacroMesh:
     """Obstacle-free macro mesh of [x0, x0+Lx] x [y0, y0+Ly] with nx x ny cells.
@@ -179,6 +280,8 @@ WORKLOADS = {
     "c1_fp64_parity": dict(seeds=(0, 1, 2, 3), level=3, dt=0.01, steps=10, Re=100.0),
     "c2_mixed_at_scale": dict(seeds=(0,), level=7, dt=0.005, steps=200, Re=100.0,
                               oracle_level=5),
+    "c3_batched": dict(seeds=tuple(range(100, 164)), dt=0.005, steps=100,
+                       generator="channel_obstacles"),
     "c4_dnnmg_inference": dict(seeds=(0,), coarse_level=5, fine_level=7, dt=0.005,
                                hidden=128, layers=2, n_in=490, n_out=162),
     "c5_training": dict(seeds=tuple(range(200, 216)), batch=8192, seq=32,

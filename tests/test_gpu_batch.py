@@ -1,0 +1,103 @@
+"""Batched plain solves (GPU): simulations of uneven depth merged per depth.
+
+Every member of a batch must follow the trajectory it has alone: in FP64
+mode (tight Newton tolerance) against a context that holds only that
+simulation, to 1e-10 relative L2 per field, and one member against the FP64
+oracle's direct-solve Newton steps; in mixed precision against the lone
+mixed-precision context to 1e-5 per step.  Inputs: seeded multi-obstacle
+channels (1-3 obstacles, uneven Re) at small depths so the oracle finishes in
+seconds.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, mesh, solver
+from synthetic import channel_obstacles
+
+pytestmark = pytest.mark.gpu
+
+DT = 0.01
+# seeds with 3, 2 and 1 obstacles; depths chosen small (two groups)
+SIMS = [(100, 2), (103, 3), (105, 2)]
+
+
+def _macros():
+    return [channel_obstacles(s) for s, _ in SIMS]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _fields(a, b):
+    a, b = a.reshape(-1, 3), b.reshape(-1, 3)
+    return max(_rel(a[:, f], b[:, f]) for f in range(3))
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-14, 1e-10), (1, 1e-10, 1e-5)])
+def test_batch_members_follow_their_lone_trajectories(precision, tol, bar):
+    import paper_2106_07687_amd as P
+    macros = _macros()
+    batch = P.Batch([(m, m.nu, d) for m, (_, d) in zip(macros, SIMS)], precision=precision,
+                    newton_tol=tol)
+    assert batch.n_groups() == 2
+    infos = [batch.group_info(g) for g in range(2)]
+    print(f"[batch] precision {precision} groups {infos}", flush=True)
+    assert sorted(i["depth"] for i in infos) == [2, 3]
+    lone = []
+    for m, (_, d) in zip(macros, SIMS):
+        ctx = P.Context(precision=precision, nu=m.nu, newton_tol=tol)
+        ctx.setup_mesh(m, d)
+        lone.append((ctx, ctx.state(d)))
+    for k in range(3):
+        stats = batch.step(DT)
+        assert all(s["converged"] == 1 for s in stats), stats
+        for j, (ctx, st) in enumerate(lone):
+            ctx.step(st, DT)
+            xb, tb = batch.get(j)
+            xl, tl = st.get()
+            assert xb.shape == xl.shape
+            err = _fields(xb, xl)
+            print(f"[batch] step {k} sim {j}: rel {err:.2e}", flush=True)
+            assert abs(tb - tl) < 1e-14
+            assert err <= bar, (k, j, err)
+    for ctx, st in lone:
+        st.close()
+        ctx.close()
+    batch.close()
+
+
+def test_batch_member_matches_oracle():
+    import paper_2106_07687_amd as P
+    macros = _macros()
+    batch = P.Batch([(m, m.nu, d) for m, (_, d) in zip(macros, SIMS)], precision=0,
+                    newton_tol=1e-14)
+    j = 0                                     # three obstacles, depth 2
+    m, d = macros[j], SIMS[j][1]
+    L = mesh.hierarchy(m, d)[d]
+    prob = fem.Problem(nu=m.nu, dt=DT)
+    x = np.zeros(3 * L.n_nodes)
+    for k in range(3):
+        batch.step(DT)
+        x = solver.newton_step(L, prob, x, (k + 1) * DT, tol=1e-13)
+        err = _fields(batch.get(j)[0], x)
+        print(f"[batch] oracle step {k}: rel {err:.2e}", flush=True)
+        assert err <= 1e-10
+    batch.close()
+
+
+def test_batch_set_get_is_per_member():
+    import paper_2106_07687_amd as P
+    macros = _macros()
+    batch = P.Batch([(m, m.nu, d) for m, (_, d) in zip(macros, SIMS)], precision=1)
+    n = [batch.info(j)[1] for j in range(len(SIMS))]
+    for j, (m, (_, d)) in enumerate(zip(macros, SIMS)):
+        assert n[j] == mesh.hierarchy(m, d)[d].n_nodes
+    rng = np.random.default_rng(0)
+    xs = [rng.standard_normal(3 * k) for k in n]
+    for j in range(len(SIMS)):
+        batch.set(j, xs[j], 0.5)
+    for j in range(len(SIMS)):
+        x, t = batch.get(j)
+        assert np.array_equal(x, xs[j]) and t == 0.5
+    batch.close()
