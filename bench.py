@@ -51,6 +51,42 @@ def kernel_bytes(ctx, key, level):
     return None
 
 
+def run_batch(P, args, log):
+    """Batched plain solves: seeded multi-obstacle channels (seeds 100, 101, ...),
+    each at its own Re and depth (4-7), all advanced together."""
+    import torch
+
+    from synthetic import channel_obstacles
+    macros = [channel_obstacles(s) for s in range(100, 100 + args.batch_sims)]
+    t0 = time.perf_counter()
+    batch = P.Batch([(m, m.nu, m.info["depth"]) for m in macros], precision=1)
+    setup_s = time.perf_counter() - t0
+    groups = [batch.group_info(g) for g in range(batch.n_groups())]
+    log(f"batch: {args.batch_sims} simulations in {len(groups)} depth groups {groups}, "
+        f"setup {setup_s:.1f} s")
+    for k in range(args.batch_warmup):
+        log(f"batch warmup {k}: {batch.step(args.dt)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [batch.step(args.dt) for _ in range(args.batch_steps)]
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    for k, st in enumerate(stats):
+        log(f"batch step {k}: {st}")
+    dofs = sum(3 * g["n_nodes"] for g in groups)
+    out = {"simulations": args.batch_sims, "seeds": f"100..{99 + args.batch_sims}",
+           "groups": [dict(g, newton_iters=sum(st[i]["newton_iters"] for st in stats),
+                           gmres_iters=sum(st[i]["gmres_iters"] for st in stats))
+                      for i, g in enumerate(groups)],
+           "dofs": dofs, "steps": args.batch_steps, "warmup": args.batch_warmup,
+           "steps_per_s": round(args.batch_steps / sec, 4),
+           "sim_steps_per_s": round(args.batch_sims * args.batch_steps / sec, 3),
+           "dof_updates_per_s": round(dofs * args.batch_steps / sec, 1),
+           "setup_s": round(setup_s, 2), "precision": "mixed"}
+    batch.close()
+    return out
+
+
 def cpu_baseline(seed: int, level: int, fine_level: int, dt: float):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -218,6 +254,10 @@ def main():
                          "directly (no graphs; events add launch overhead to the timings)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured graphs")
+    ap.add_argument("--batch-sims", type=int, default=64,
+                    help="batched plain solves: simulations (0 skips the leg)")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-warmup", type=int, default=1)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="device copy of this many MiB before the run (calibrates "
                          "hardware traffic counters against a known byte count)")
@@ -346,6 +386,8 @@ def main():
         tf = flop / (ms / cnt / 1e3) / 1e12
         mfma = {"kernel": mkey, "achieved": round(tf, 2), "peak": 2500.0,
                 "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5), "avg_us": round(1e3 * ms / cnt, 2)}
+    # ---- batched plain solves
+    batch_info = run_batch(P, args, log) if args.batch_sims > 0 else None
     # ---- BPTT training throughput at the training batch shape (synthetic rows)
     train = None
     if args.train_iters > 0:
@@ -407,6 +449,7 @@ def main():
         "roofline": roof,
         "mfma": mfma,
         "train": train,
+        "batch": batch_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)

@@ -103,7 +103,7 @@ retry:
   for (int it = 0; it <= c.prm.newton_max; ++it) {
     c.residual(l, st.x.p, c.xo_save.p, use_pending ? st.pending_rhs.p : nullptr, t_new, dt,
                c.R.p);
-    const double nr = c.norm2_f64(c.R.p, n);
+    const double nr = c.norm2_max_seg(l, c.R.p);   // batches: every simulation's own norm
     if (it == 0) loc.res_initial = nr;
     loc.res_final = nr;
     loc.newton_iters = it;
@@ -287,6 +287,32 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
           if (l == 0) b0[i] = blk;
         }
         D->nnu.upload(nu, c.stream);
+        // per-simulation reduction chunks: runs of equal simulation in node
+        // order, cut at 1024 nodes, listed simulation by simulation
+        std::vector<int> seg(h.N);
+        for (int i = 0; i < h.N; ++i) seg[i] = c.macro_blk[(h.cadj[h.cadj_ptr[i]] >> 2) >> (2 * l + 2)];
+        const int nseg = static_cast<int>(c.blk_nu.size());
+        std::vector<std::vector<std::pair<int, int>>> runs(nseg);
+        for (int i = 0; i < h.N;) {
+          int j = i;
+          while (j < h.N && seg[j] == seg[i] && j - i < 1024) ++j;
+          runs[seg[i]].push_back({3 * i, 3 * (j - i)});
+          i = j;
+        }
+        std::vector<int> cs, cl, sp(1, 0);
+        for (int g = 0; g < nseg; ++g) {
+          for (auto &r : runs[g]) {
+            cs.push_back(r.first);
+            cl.push_back(r.second);
+          }
+          sp.push_back(static_cast<int>(cs.size()));
+        }
+        D->nseg = nseg;
+        D->nchunk = static_cast<int>(cs.size());
+        D->segn.upload(seg, c.stream);
+        D->cstart.upload(cs, c.stream);
+        D->clen.upload(cl, c.stream);
+        D->seg_ptr.upload(sp, c.stream);
         if (l == 0) c.blk0 = std::move(b0);
       }
       upload_level(*D, c.stream);

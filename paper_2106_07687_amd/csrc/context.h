@@ -107,6 +107,10 @@ struct DevLevel {
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
   DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
   DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)
+  // batches: simulation of each node and the chunks of per-simulation
+  // reductions (starts/lengths in unknowns, grouped by simulation: seg_ptr)
+  int nseg = 1, nchunk = 0;
+  DevBuf<int> segn, cstart, clen, seg_ptr;
   double sP_dt = -1.0, sP_nu = -1.0, sP_alpha0 = -1.0;
   LevelView view() const;
 };
@@ -182,6 +186,14 @@ class Solver {
   DevBuf<double> partial_, hdev_;
   std::vector<double> hhost_;
   void ensure_gmres(int level, int m);
+  // GMRES with per-simulation inner products, Hessenberg matrices and Givens
+  // rotations on a batch level (each simulation's own Krylov space).
+  int gmres_batched(int level, const T *b, T *x, double rtol, int restart, int maxit, double *res0,
+                    double *res);
+  DevBuf<double> spart_, sdev_, scoef_;
+  std::vector<double> shost_;
+  // segmented dots of V[0..m) with w on `level` into dev (segment-major, m per segment)
+  void seg_dots(int level, int m, const T *V, size_t ld, const T *w, double *dev);
 };
 
 class Ctx {
@@ -221,6 +233,10 @@ class Ctx {
   }
   void ensure_lps(int l, double dt);
   double norm2_f64(const double *x, int n);   // ||x||_2, synchronising
+  // largest per-simulation ||x||_2 on a batch level (= ||x||_2 otherwise)
+  double norm2_max_seg(int l, const double *x);
+  DevBuf<double> seg_partial, seg_out;
+  std::vector<double> seg_host;
   void residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                 double dt, double *R);
 };

@@ -1044,5 +1044,82 @@ __global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict_
   if (i < n) x[i] += static_cast<double>(w[i]);
 }
 
+// ---------------------------------------------------- per-simulation BLAS-1
+// Batches: the unknowns of one simulation ("segment") form runs of the node
+// order; runs are cut into chunks (start and length in unknowns) listed
+// segment by segment in increasing position.  Segmented reductions sum each
+// chunk in a fixed order, then each segment's chunks in list order, so the
+// result does not depend on scheduling.  segn holds the segment of each node.
+
+// partial[c * m + v] = V[v] . w over chunk c  (FP64 accumulation)
+template <typename T>
+__global__ void k_multidot_chunks(const int *__restrict__ cstart, const int *__restrict__ clen, int m,
+                                  const T *__restrict__ Vb, size_t ld, const T *__restrict__ w,
+                                  double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x, v = blockIdx.y;
+  const T *vv = Vb + static_cast<size_t>(v) * ld;
+  const int i0 = cstart[c], i1 = i0 + clen[c];
+  double s = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+    s += static_cast<double>(vv[i]) * static_cast<double>(w[i]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[static_cast<size_t>(c) * m + v] = sh[0];
+}
+
+// out[g * m + v] = sum over the chunks of segment g (seg_ptr CSR) of partial
+__global__ void k_reduce_seg(const int *__restrict__ seg_ptr, int m, const double *__restrict__ partial,
+                             double *__restrict__ out) {
+  __shared__ double sh[256];
+  const int g = blockIdx.x, v = blockIdx.y;
+  double s = 0.0;
+  for (int c = seg_ptr[g] + threadIdx.x; c < seg_ptr[g + 1]; c += blockDim.x)
+    s += partial[static_cast<size_t>(c) * m + v];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[static_cast<size_t>(g) * m + v] = sh[0];
+}
+
+// w -= sum_v h[seg, v] V[v]  (coefficients per segment, stride hs)
+template <typename T>
+__global__ void k_multi_axpy_seg(int n, int m, const T *__restrict__ Vb, size_t ld, const double *__restrict__ h,
+                                 int hs, const int *__restrict__ segn, T *__restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *hg = h + static_cast<size_t>(segn[i / 3]) * hs;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += hg[v] * static_cast<double>(Vb[static_cast<size_t>(v) * ld + i]);
+  w[i] = static_cast<T>(static_cast<double>(w[i]) - s);
+}
+
+// x += sum_v y[seg, v] Z[v]
+template <typename T>
+__global__ void k_combine_seg(int n, int m, const T *__restrict__ Zb, size_t ld, const double *__restrict__ y,
+                              int ys, const int *__restrict__ segn, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *yg = y + static_cast<size_t>(segn[i / 3]) * ys;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += yg[v] * static_cast<double>(Zb[static_cast<size_t>(v) * ld + i]);
+  x[i] = static_cast<T>(static_cast<double>(x[i]) + s);
+}
+
+// y = a[seg] x
+template <typename T>
+__global__ void k_scale_copy_seg(int n, const double *__restrict__ a, const int *__restrict__ segn,
+                                 const T *__restrict__ x, T *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<T>(a[segn[i / 3]] * static_cast<double>(x[i]));
+}
+
 }  // namespace
 }  // namespace dnnmg

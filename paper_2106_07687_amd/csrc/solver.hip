@@ -153,6 +153,27 @@ double Ctx::norm2_f64(const double *x, int n) {
   return std::sqrt(h);
 }
 
+double Ctx::norm2_max_seg(int l, const double *x) {
+  DevLevel &L = *levels[l];
+  if (L.nseg <= 1) return norm2_f64(x, 3 * L.h.N);
+  if (seg_partial.n < static_cast<size_t>(L.nchunk)) seg_partial.alloc(L.nchunk);
+  if (seg_out.n < static_cast<size_t>(L.nseg)) seg_out.alloc(L.nseg);
+  hipLaunchKernelGGL(k_multidot_chunks<double>, dim3(L.nchunk, 1), dim3(256), 0, stream, L.cstart.p, L.clen.p, 1, x,
+                     size_t(0), x, seg_partial.p);
+  hipLaunchKernelGGL(k_reduce_seg, dim3(L.nseg, 1), dim3(256), 0, stream, L.seg_ptr.p, 1, seg_partial.p,
+                     seg_out.p);
+  LAUNCH_CHECK("segmented norm");
+  seg_host.resize(L.nseg);
+  check(hipMemcpyAsync(seg_host.data(), seg_out.p, sizeof(double) * L.nseg, hipMemcpyDeviceToHost, stream),
+        "norm D2H");
+  check(hipStreamSynchronize(stream), "norm sync");
+  double mx = 0.0;
+  for (double v : seg_host) mx = std::max(mx, std::sqrt(v));
+  for (double v : seg_host)
+    if (!std::isfinite(v)) return v;
+  return mx;
+}
+
 void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                    double dt, double *Rout) {
   ensure_lps(l, dt);
@@ -547,6 +568,7 @@ void Solver<T>::ensure_gmres(int level, int m) {
 template <typename T>
 int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int maxit,
                      double *res0, double *res_out) {
+  if (ctx_->levels[level]->nseg > 1) return gmres_batched(level, b, x, rtol, restart, maxit, res0, res_out);
   hipStream_t s = ctx_->stream;
   const int n = 3 * ctx_->levels[level]->h.N;
   const size_t ld = static_cast<size_t>(n);
@@ -655,6 +677,175 @@ int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int 
   }
   check(hipStreamSynchronize(s), "gmres end");
   if (res_out) *res_out = resid;
+  return it;
+}
+
+template <typename T>
+void Solver<T>::seg_dots(int level, int m, const T *V, size_t ld, const T *w, double *dev) {
+  DevLevel &L = *ctx_->levels[level];
+  hipStream_t s = ctx_->stream;
+  ProfScope ps(ctx_->prof, s, "gs_dots", level);
+  hipLaunchKernelGGL(k_multidot_chunks<T>, dim3(L.nchunk, m), dim3(256), 0, s, L.cstart.p, L.clen.p, m, V, ld, w,
+                     spart_.p);
+  hipLaunchKernelGGL(k_reduce_seg, dim3(L.nseg, m), dim3(256), 0, s, L.seg_ptr.p, m, spart_.p, dev);
+}
+
+// Restarted right-preconditioned GMRES on a batch level: the operator and the
+// V-cycle are block diagonal over the simulations, and every inner product,
+// Hessenberg column, Givens rotation and least-squares solve is kept per
+// simulation, so each simulation iterates in its own Krylov space (as it
+// would alone).  A simulation that has converged (or broken down) is frozen:
+// its basis vectors are zeroed from then on and its coefficients ignored.
+// The launches are shared; the loop ends when every simulation has converged.
+template <typename T>
+int Solver<T>::gmres_batched(int level, const T *b, T *x, double rtol, int restart, int maxit,
+                             double *res0, double *res_out) {
+  hipStream_t s = ctx_->stream;
+  DevLevel &L = *ctx_->levels[level];
+  const int n = 3 * L.h.N, G = L.nseg;
+  const size_t ld = static_cast<size_t>(n);
+  restart = std::max(1, std::min(restart, 64));
+  ensure_gmres(level, restart);
+  const int m = restart;
+  const size_t sp_need = static_cast<size_t>(L.nchunk) * (m + 1);
+  if (spart_.n < sp_need) spart_.alloc(sp_need);
+  const size_t sd_need = static_cast<size_t>(G) * (2 * (m + 1) + 1);
+  if (sdev_.n < sd_need) sdev_.alloc(sd_need);
+  if (scoef_.n < static_cast<size_t>(G) * m) scoef_.alloc(static_cast<size_t>(G) * m);
+  shost_.resize(sd_need);
+  auto d2h = [&](size_t cnt) {
+    check(hipMemcpyAsync(shost_.data(), sdev_.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "gmres D2H");
+    check(hipStreamSynchronize(s), "gmres sync");
+  };
+  auto scale_to = [&](const std::vector<double> &a, const T *src, T *dst) {
+    check(hipMemcpyAsync(scoef_.p, a.data(), sizeof(double) * G, hipMemcpyHostToDevice, s), "H2D");
+    hipLaunchKernelGGL(k_scale_copy_seg<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, scoef_.p, L.segn.p, src,
+                       dst);
+  };
+  hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x, static_cast<size_t>(n),
+                     T(0));
+  seg_dots(level, 1, b, ld, b, sdev_.p);
+  d2h(G);
+  std::vector<double> beta0(G), target(G), resid(G);
+  std::vector<char> done(G);
+  double b0max = 0.0;
+  for (int g = 0; g < G; ++g) {
+    beta0[g] = std::sqrt(std::max(shost_[g], 0.0));
+    target[g] = rtol * beta0[g];
+    resid[g] = beta0[g];
+    done[g] = !(beta0[g] > 0.0);
+    b0max = std::max(b0max, beta0[g]);
+  }
+  if (res0) *res0 = b0max;
+  if (res_out) *res_out = b0max;
+  if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) return 0;
+  std::vector<std::vector<double>> H(G, std::vector<double>(static_cast<size_t>(m + 1) * m)), cs(G),
+      sn(G), gv(G);
+  std::vector<int> jend(G, 0);
+  std::vector<double> sc(G), y(static_cast<size_t>(G) * m);
+  int it = 0;
+  bool first = true;
+  OpLevel<T> &o = ops_[level];
+  while (it < maxit) {
+    // v_0 = r / ||r|| per simulation (r = b on the first cycle)
+    const T *r = b;
+    std::vector<double> beta(G);
+    if (first) {
+      beta = beta0;
+    } else {
+      spmv(level, x, b, o.t.p);
+      seg_dots(level, 1, o.t.p, ld, o.t.p, sdev_.p);
+      d2h(G);
+      for (int g = 0; g < G; ++g) beta[g] = std::sqrt(std::max(shost_[g], 0.0));
+      r = o.t.p;
+    }
+    first = false;
+    for (int g = 0; g < G; ++g) {
+      sc[g] = (!done[g] && beta[g] > 0.0) ? 1.0 / beta[g] : 0.0;
+      if (!(beta[g] > 0.0)) done[g] = 1;
+      cs[g].assign(m, 0.0);
+      sn[g].assign(m, 0.0);
+      gv[g].assign(m + 1, 0.0);
+      gv[g][0] = beta[g];
+      std::fill(H[g].begin(), H[g].end(), 0.0);
+      jend[g] = 0;
+    }
+    scale_to(sc, r, V_.p);
+    std::vector<char> active(done);   // frozen at the start of this cycle
+    int jmax = 0;
+    for (int j = 0; j < m; ++j) {
+      T *vj = V_.p + static_cast<size_t>(j) * ld;
+      T *zj = Z_.p + static_cast<size_t>(j) * ld;
+      vcycle(level, vj, zj);
+      spmv(level, zj, nullptr, w_.p);
+      const int k = j + 1;
+      double *h1 = sdev_.p, *h2 = sdev_.p + static_cast<size_t>(G) * k, *hn = sdev_.p + 2 * static_cast<size_t>(G) * k;
+      seg_dots(level, k, V_.p, ld, w_.p, h1);
+      hipLaunchKernelGGL(k_multi_axpy_seg<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, k, V_.p, ld, h1, k,
+                         L.segn.p, w_.p);
+      seg_dots(level, k, V_.p, ld, w_.p, h2);
+      hipLaunchKernelGGL(k_multi_axpy_seg<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, k, V_.p, ld, h2, k,
+                         L.segn.p, w_.p);
+      seg_dots(level, 1, w_.p, ld, w_.p, hn);
+      LAUNCH_CHECK("batched gmres iteration");
+      d2h(2 * static_cast<size_t>(G) * k + G);
+      ++it;
+      jmax = k;
+      for (int g = 0; g < G; ++g) {
+        sc[g] = 0.0;
+        if (done[g]) continue;
+        std::vector<double> &Hg = H[g];
+        const double hnorm = std::sqrt(std::max(shost_[2 * static_cast<size_t>(G) * k + g], 0.0));
+        for (int i = 0; i <= j; ++i)
+          Hg[i * m + j] = shost_[static_cast<size_t>(g) * k + i] + shost_[static_cast<size_t>(G) * k + g * k + i];
+        Hg[(j + 1) * m + j] = hnorm;
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[g][i] * Hg[i * m + j] + sn[g][i] * Hg[(i + 1) * m + j];
+          Hg[(i + 1) * m + j] = -sn[g][i] * Hg[i * m + j] + cs[g][i] * Hg[(i + 1) * m + j];
+          Hg[i * m + j] = t;
+        }
+        const double den = std::hypot(Hg[j * m + j], Hg[(j + 1) * m + j]);
+        jend[g] = k;
+        if (!(den > 0.0)) {   // breakdown: the current iterate is this simulation's best
+          jend[g] = j;
+          done[g] = 1;
+          continue;
+        }
+        cs[g][j] = Hg[j * m + j] / den;
+        sn[g][j] = Hg[(j + 1) * m + j] / den;
+        Hg[j * m + j] = den;
+        Hg[(j + 1) * m + j] = 0.0;
+        gv[g][j + 1] = -sn[g][j] * gv[g][j];
+        gv[g][j] = cs[g][j] * gv[g][j];
+        resid[g] = std::fabs(gv[g][j + 1]);
+        if (resid[g] <= target[g] || !(hnorm > 0.0))
+          done[g] = 1;
+        else
+          sc[g] = 1.0 / hnorm;
+      }
+      if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; }) || it >= maxit) break;
+      if (j + 1 < m) scale_to(sc, w_.p, V_.p + static_cast<size_t>(j + 1) * ld);
+    }
+    // per-simulation least squares and x += Z y
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int g = 0; g < G; ++g) {
+      if (active[g]) continue;   // frozen before this cycle: nothing to add
+      const std::vector<double> &Hg = H[g];
+      double *yg = y.data() + static_cast<size_t>(g) * m;
+      for (int i = jend[g] - 1; i >= 0; --i) {
+        double acc = gv[g][i];
+        for (int k2 = i + 1; k2 < jend[g]; ++k2) acc -= Hg[i * m + k2] * yg[k2];
+        yg[i] = acc / Hg[i * m + i];
+      }
+    }
+    check(hipMemcpyAsync(scoef_.p, y.data(), sizeof(double) * G * m, hipMemcpyHostToDevice, s), "H2D");
+    hipLaunchKernelGGL(k_combine_seg<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, jmax, Z_.p, ld, scoef_.p, m,
+                       L.segn.p, x);
+    LAUNCH_CHECK("batched gmres combine");
+    if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) break;
+  }
+  check(hipStreamSynchronize(s), "gmres end");
+  if (res_out) *res_out = *std::max_element(resid.begin(), resid.end());
   return it;
 }
 

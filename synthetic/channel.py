@@ -122,14 +122,17 @@ def _strip_mesh(obs, n_downstream):
     """Macro mesh of the channel with one or more obstacles in x-disjoint
     strips.  `obs` rows (cx, cy, a, b, phi, w), sorted by cx; w is the
     half-width of the square box holding the obstacle.  Every vertical grid
-    line carries 4 vertices (y = 0, y1, y2, H): inside a strip (y1, y2) are its
-    box's y-range; the columns between strips are 3 trapezoids joining the
-    neighbouring strips' lines (so the mesh stays conforming)."""
+    line carries 4 vertices (y = 0, y1, y2, H): inside a strip (y1, y2) is its
+    box's y-range; elsewhere the lines move linearly towards the neutral
+    (H/3, 2H/3), so no row inherits a thin box margin over a long distance.
+    Columns outside the strips are at most 0.3 wide (the downstream ones are
+    graded 1:2:..:n_downstream), each a row of 3 quads."""
     xy, quads, bedges, curves = [], [], [], []
+    neutral = (CHANNEL_H / 3.0, 2.0 * CHANNEL_H / 3.0)
 
-    def column_line(x, y1, y2):
+    def column_line(x, y12):
         base = len(xy)
-        for y in (0.0, y1, y2, CHANNEL_H):
+        for y in (0.0, y12[0], y12[1], CHANNEL_H):
             xy.append((x, y))
         return [base, base + 1, base + 2, base + 3]
 
@@ -139,15 +142,32 @@ def _strip_mesh(obs, n_downstream):
         bedges.append((lft[0], rgt[0], TAG_WALL))
         bedges.append((lft[3], rgt[3], TAG_WALL))
 
-    first = obs[0]
-    line = column_line(0.0, first[1] - first[5], first[1] + first[5])
+    def fill(line, x0, y0, x1, y1, xs=None):
+        """Columns from the existing line at x0 (rows y0) to a new line at x1
+        (rows y1); returns the last line."""
+        if xs is None:
+            n = max(1, int(np.ceil((x1 - x0) / 0.3 - 1e-9)))
+            xs = [x0 + (x1 - x0) * (k + 1) / n for k in range(n)]
+        for x in xs:
+            t = (x - x0) / (x1 - x0)
+            nxt = column_line(x, ((1 - t) * y0[0] + t * y1[0], (1 - t) * y0[1] + t * y1[1]))
+            join(line, nxt)
+            line = nxt
+        return line
+
+    line = column_line(0.0, neutral)
     for r in range(3):
         bedges.append((line[r], line[r + 1], TAG_INFLOW))
+    x_prev, y_prev = 0.0, neutral
     for k, (cx, cy, a, b, phi, w) in enumerate(obs):
-        left = column_line(cx - w, cy - w, cy + w)
-        join(line, left)
-        right = column_line(cx + w, cy - w, cy + w)
-        # bottom and top cells of the strip, then the hole ring
+        box = (cy - w, cy + w)
+        # approach the strip: move to neutral first when there is room, then to the box
+        mid = 0.5 * (x_prev + cx - w)
+        if cx - w - x_prev > 0.45 and x_prev > 0.0:
+            line = fill(line, x_prev, y_prev, mid, neutral)
+            x_prev, y_prev = mid, neutral
+        left = fill(line, x_prev, y_prev, cx - w, box)
+        right = column_line(cx + w, box)
         quads.append((left[0], right[0], right[1], left[1]))
         quads.append((left[2], right[2], right[3], left[3]))
         bedges.append((left[0], right[0], TAG_WALL))
@@ -162,22 +182,20 @@ def _strip_mesh(obs, n_downstream):
             quads.append((arc[q], corners[q], corners[q1], arc[q1]))
             bedges.append((arc[q], arc[q1], TAG_OBSTACLE + k))
         curves.append((cx, cy, a, b, phi))
-        line = right
-    last = obs[-1]
-    x0 = last[0] + last[5]
+        line, x_prev, y_prev = right, cx + w, box
     wts = np.cumsum(np.arange(1, n_downstream + 1, dtype=np.float64))
     wts /= wts[-1]
-    for t in wts:
-        nxt = column_line(x0 + (CHANNEL_L - x0) * t, last[1] - last[5], last[1] + last[5])
-        join(line, nxt)
-        line = nxt
+    xs = [x_prev + (CHANNEL_L - x_prev) * t for t in wts]
+    # the first downstream column returns to the neutral rows
+    line = fill(line, x_prev, y_prev, xs[0], neutral, xs=[xs[0]])
+    line = fill(line, xs[0], neutral, CHANNEL_L, neutral, xs=xs[1:])
     for r in range(3):
         bedges.append((line[r], line[r + 1], TAG_OUTFLOW))
     return (np.asarray(xy, dtype=np.float64), np.asarray(quads, dtype=np.int32),
             np.asarray(bedges, dtype=np.int32), np.asarray(curves, dtype=np.float64))
 
 
-def channel_obstacles(seed: int, n_downstream: int = 3, max_tries: int = 2000) -> MacroMesh:
+def channel_obstacles(seed: int, n_downstream: int = 4, max_tries: int = 2000) -> MacroMesh:
     """Channel with 1-3 seeded circular or elliptical obstacles, a seeded
     Reynolds number and a seeded mesh depth (the batched-solve workload).
 
@@ -185,10 +203,12 @@ def channel_obstacles(seed: int, n_downstream: int = 3, max_tries: int = 2000) -
     per obstacle: ellipse with probability 1/2, semi-axis a ~ U[0.03, 0.07],
     aspect ~ U[1, 2] (b = a / aspect; a circle has b = a), rotation
     phi ~ U[0, pi), then centres drawn x ~ U[0.15, 1.0], y ~ U[0.1, 0.31]
-    until the obstacle keeps 0.05 from both walls and its square box (half-
-    width w = min(1.7 a, cy - 0.02, H - cy - 0.02)) keeps a 0.05 x-gap to the
-    boxes already placed (so obstacles are >= 0.05 apart); then Re ~ U[50, 200]
-    and depth ~ U{4, ..., 7}.  nu = 0.1 / Re as in `channel_obstacle`.
+    until the obstacle keeps 0.05 from both walls and its square box keeps a
+    0.05 x-gap to the boxes already placed (so obstacles are >= 0.05 apart);
+    then Re ~ U[50, 200] and depth ~ U{4, ..., 7}.  nu = 0.1 / Re as in
+    `channel_obstacle`.  Box half-width w = min(1.7 a, a + 0.4 g) with g the
+    smaller wall gap cy - a, H - cy - a: the ring around the obstacle gets 40%
+    of the gap, the row between box and wall 60%.
     """
     rng = np.random.default_rng(seed)
     n_obs = int(rng.integers(1, 4))
@@ -202,9 +222,10 @@ def channel_obstacles(seed: int, n_downstream: int = 3, max_tries: int = 2000) -
         for _ in range(max_tries):
             cx = rng.uniform(0.15, 1.0)
             cy = rng.uniform(0.1, 0.31)
-            if cy - a < 0.05 or CHANNEL_H - cy - a < 0.05:
+            gap = min(cy - a, CHANNEL_H - cy - a)
+            if gap < 0.05:
                 continue
-            w = min(1.7 * a, cy - 0.02, CHANNEL_H - cy - 0.02)
+            w = min(1.7 * a, a + 0.4 * gap)
             if cx - w < 0.05:
                 continue
             if all(abs(cx - o[0]) >= w + o[5] + 0.05 for o in placed):
