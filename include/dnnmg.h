@@ -149,11 +149,11 @@ int dnnmg_state_get(const dnnmg_state *s, double *uvp, double *t);
 int dnnmg_state_device_ptr(dnnmg_state *s, double **uvp_dev);
 
 /* One time step t -> t + dt of the plain method on the state's level
- * (Algorithm 1, lines 2-4): Newton (eq. newton) from x^(0) = x_{n-1} with the
+ * (the coarse solve of Algorithm 1): Newton (eq. newton) from x^(0) = x_{n-1} with the
  * Dirichlet values of t + dt imposed; each Newton system solved by GMRES with
  * one multigrid V-cycle per preconditioner application.  If the state holds a
  * pending DNN-MG right-hand side (set by dnnmg_correct) it replaces f_n
- * (Algorithm 1, line 3 with b_L^n).  On DNNMG_ENOCONV the state is restored
+ * (Algorithm 1 with b_L^n).  On DNNMG_ENOCONV the state is restored
  * to its value before the call. */
 int dnnmg_step(dnnmg_ctx *ctx, dnnmg_state *s, double dt, dnnmg_step_stats *stats);
 
@@ -225,7 +225,7 @@ typedef struct {
   double *rhs_coarse;     /* 3 x N_L restricted right-hand side b^L          */
 } dnnmg_correct_out;
 
-/* DNN-MG correction after a coarse step (Algorithm 1, lines 6-9): x~ = P^m x
+/* DNN-MG correction after a coarse step (Algorithm 1, the correction after the coarse step): x~ = P^m x
  * on level F; fine residual r^F = f^F(v_prev) - A^F(x~) (Dirichlet rows 0,
  * divided by the lumped mass); per-patch network; scatter-average of the
  * velocity corrections d (0 on Dirichlet nodes); b^F = Rhs(x~ + d) (explicit
@@ -235,7 +235,7 @@ typedef struct {
 int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt,
                   dnnmg_correct_out *dbg);
 
-/* Algorithm 1, lines 8-9 for a given fine velocity (teacher forcing when
+/* The Rhs and restriction of Algorithm 1 for a given fine velocity (teacher forcing when
  * generating training data from fine solutions): b^F = Rhs(v_fine) on level
  * F, b^L = (P^m)^T b^F stored as the coarse state's pending right-hand side,
  * and v_prev <- v_fine.  v_fine: host, 3 doubles per fine node (pressure

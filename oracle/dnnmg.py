@@ -1,24 +1,24 @@
-"""Oracle DNN-MG correction (Algorithm 1, lines 6-9; Sec. 2.2), FP64 numpy.
+"""Oracle DNN-MG correction (Algorithm 1, the steps after the coarse solve; Sec. 2.2), FP64 numpy.
 
 State of a DNN-MG simulation on coarse level L with fine level F = L + m:
 x^L (the coarse iterate), the previous corrected fine velocity v^F_prev, the
 GRU hidden states (one set per patch), and the pending coarse right-hand side
 b^L for the next Newton solve.
 
-One correction, after Newton on level L produced x^L_n (Algorithm 1, l. 2-4):
-  1. x~ = P^m x^L_n (prolongated velocity and pressure, Algorithm 1, l. 6);
+One correction, after Newton on level L produced x^L_n (Algorithm 1):
+  1. x~ = P^m x^L_n (prolongated velocity and pressure);
   2. r^F = f^F_n(v^F_prev) - A^F_n(x~) (the fine residual of eq.
      nonlinearshort), Dirichlet rows set to zero;
   3. per patch: inputs [v~1, v~2, p~, r1, r2, rp] at the patch's fine nodes
      (residual rows divided by the node's lumped mass) and 4 geometry
      features, standardised per channel (reading N5);
   4. the GRU stack and head give a velocity correction per patch node
-     (Algorithm 1, l. 7; velocity only);
+     (velocity only);
   5. d = mean of the predictions of all patches containing a node, 0 on
      Dirichlet nodes (reading N6);
   6. b^F = Rhs(v~ + d) (the explicit velocity rows of f^F of eq. varformv),
-     pressure rows 0 (Algorithm 1, l. 8);
-  7. b^L = (P^m)^T b^F (Algorithm 1, l. 9); v^F_prev <- v~ + d.
+     pressure rows 0 (the Rhs of Algorithm 1);
+  7. b^L = (P^m)^T b^F (restriction, Algorithm 1); v^F_prev <- v~ + d.
 
 Readings (paper silent): N4 patch = the 2x2 level-L cells of one level-(L-1)
 cell, i.e. (2^(m+1) + 1)^2 fine nodes in the parent's lexicographic order;
@@ -215,7 +215,7 @@ class DnnmgOracle:
 
 def dnnmg_residual(levels, prob, L, x, x_old, bL, t_new):
     """Residual of Newton on level L when a DNN-MG right-hand side replaces
-    f_n (Algorithm 1, line 3 with b_L^n): R = b^L - A^L_impl(x), Dirichlet
+    f_n (the coarse solve of Algorithm 1 with b_L^n): R = b^L - A^L_impl(x), Dirichlet
     rows g - x.  A^L_impl is A_n without the old-state terms."""
     Lv = levels[L]
     z = np.zeros_like(x)
@@ -231,7 +231,7 @@ def dnnmg_residual(levels, prob, L, x, x_old, bL, t_new):
 
 def dnnmg_newton(levels, prob, L, x_old, bL, t_new, tol=1e-10, maxit=20):
     """Newton with direct solves for A^L_impl(x) = b^L (or the plain f^L(x_old)
-    if bL is None), Algorithm 1, lines 2-4."""
+    if bL is None), the coarse solve of Algorithm 1."""
     import scipy.sparse.linalg as spla
     from . import solver
     Lv = levels[L]

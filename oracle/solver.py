@@ -183,7 +183,7 @@ def gmres(A, b, precond, rtol=1e-2, restart=30, maxit=100):
 def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1e-2,
                    restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6):
     """Newton's method (eq. newton) with GMRES + V-cycle linear solves, as in
-    Algorithm 1, lines 2-4 (full steps, reading N1)."""
+    the coarse solve of Algorithm 1 (full steps, reading N1)."""
     fine = levels[-1]
     x = fem.impose_bc(fine, prob, x_old, t_new)
     stats = dict(newton=0, gmres=[], res=[])

@@ -1,4 +1,4 @@
-// DNN-MG correction (Algorithm 1, lines 6-9): patch tables, the GRU patch
+// DNN-MG correction (Algorithm 1, the correction after the coarse step): patch tables, the GRU patch
 // network in BF16 MFMA GEMMs, and the C-ABI calls dnnmg_net_* / dnnmg_correct.
 #include <algorithm>
 #include <cmath>
@@ -185,8 +185,8 @@ void prolong_chain(Net &n, const double *xL) {
   check(hipGetLastError(), "prolong_chain");
 }
 
-// b^F = Rhs(n.vc) on level F (Algorithm 1, l. 8), b^L = (P^m)^T b^F into the
-// coarse state's pending right-hand side (l. 9), then v_prev <- n.vc.
+// b^F = Rhs(n.vc) on level F (Algorithm 1), b^L = (P^m)^T b^F into the
+// coarse state's pending right-hand side, then v_prev <- n.vc.
 void rhs_and_restrict(Net &n, State &st, double dt) {
   Ctx &c = *n.ctx;
   hipStream_t s = c.stream;

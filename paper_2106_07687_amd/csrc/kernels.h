@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const do
 // Explicit part of the velocity rows of f_n (eq. varformv) for a given
 // velocity field v: 1/k (v, phi) - (1 - theta)((v.grad) v, phi)
 // - (1 - theta) nu (grad v, grad phi); pressure rows 0.  This is Rhs() of
-// Algorithm 1 (line 7) without external force.
+// Algorithm 1 without external force.
 __global__ void __launch_bounds__(128) k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;

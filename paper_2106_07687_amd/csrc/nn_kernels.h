@@ -1,4 +1,4 @@
-// gfx950 kernels of the DNN-MG patch network (Algorithm 1, lines 6-9):
+// gfx950 kernels of the DNN-MG patch network (Algorithm 1, the correction after the coarse step):
 // patch gather with input standardisation, BF16 MFMA GEMMs with FP32
 // accumulation, GRU gate update, output scatter-average, and the backward
 // counterparts used by BPTT training.
@@ -130,7 +130,7 @@ __global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const fl
   }
 }
 
-// Patch gather (Algorithm 1, l. 7 inputs): one workgroup per patch writes the
+// Patch gather (Algorithm 1, the network inputs): one workgroup per patch writes the
 // standardised input row [u, v, p, r_u, r_v, r_p at the S2 patch nodes;
 // aspect, skew, h_rel, Peclet] as BF16 into X (ld = ldx, padding zeroed).
 // Residual rows are divided by the lumped mass; Dirichlet velocity residual

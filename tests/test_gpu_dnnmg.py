@@ -1,4 +1,4 @@
-"""Parity of the HIP DNN-MG correction (Algorithm 1, lines 6-9) with the oracle.
+"""Parity of the HIP DNN-MG correction (Algorithm 1, the correction after the coarse step) with the oracle.
 
 The network runs in BF16 (weights, inputs and the GEMM copy of the hidden
 state) with FP32 accumulation and gates.  Bars: against a BF16-emulating

@@ -1,7 +1,7 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 oracle.
 
 Tolerances: FP64 mode, single operations 1e-12 relative (rounding order
-only); time steps 1e-10 relative L2 per field (spec bar); mixed mode
+only); time steps 1e-10 relative L2 per field (the FP64 parity bar); mixed mode
 1e-5 relative L2 per step.  Inputs are seeded (synthetic.*) on the channel
 configuration of the FP64 parity workload (level 3, ~5.5k nodes: 87 SELL
 slices, the last one ragged).

@@ -3,7 +3,7 @@
 Small instance of the training and inference workflow: fine solutions on
 level F = 3 from the library's own Newton-GMRES-multigrid solver; teacher-
 forced coarse steps on level L = 1 (the coarse right-hand side restricted
-from the fine velocity of the previous step, Algorithm 1 lines 8-9) give the
+from the fine velocity of the previous step, as in Algorithm 1) give the
 network inputs and the targets d* = v^F_n - P^2 v^L_n; BPTT with Adam on the
 GPU; then a free-running DNN-MG simulation (Algorithm 1) is compared with the
 plain coarse simulation MG(L).  The error measure is the relative l2 error of

@@ -53,7 +53,7 @@ def _mms(nu):
 def test_manufactured_solution_second_order_velocity():
     """Steady problem (1/k = 0, theta = 1) with a manufactured divergence-free
     velocity that satisfies the do-nothing condition on x = 1: the velocity
-    error in L2 must fall as O(h^2) (spec MMS pin)."""
+    error in L2 must fall as O(h^2) (manufactured-solution pin)."""
     nu = 0.1
     u, v, p, fx, fy = _mms(nu)
     bc = lambda X, Y, t: (u(X, Y) + 0 * X, v(X, Y) + 0 * X)
