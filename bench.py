@@ -142,20 +142,38 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level7_kernels.md")
 
 
 def kernel_sha1(kernel):
-    """SHA-1 of a kernel's source text (its definition in csrc/kernels.h)."""
+    """SHA-1 of a kernel's source text in csrc/kernels.h: its definition plus
+    the definitions of the device functions it calls (transitively)."""
     import hashlib
     import re
     src = open(os.path.join(ROOT, "paper_2106_07687_amd", "csrc", "kernels.h")).read()
-    m = re.search(r"__global__[^;{]*?\b" + kernel + r"\(", src)
-    if not m:
+
+    def definition(name, kind):
+        m = re.search(kind + r"[^;{]*?\b" + name + r"\(", src)
+        if not m:
+            return None
+        i = src.index("{", m.end())
+        depth = 0
+        for j in range(i, len(src)):
+            depth += {"{": 1, "}": -1}.get(src[j], 0)
+            if depth == 0:
+                return src[m.start():j + 1]
         return None
-    i = src.index("{", m.end())
-    depth = 0
-    for j in range(i, len(src)):
-        depth += {"{": 1, "}": -1}.get(src[j], 0)
-        if depth == 0:
-            return hashlib.sha1(src[m.start():j + 1].encode()).hexdigest()
-    return None
+
+    text = definition(kernel, "__global__")
+    if text is None:
+        return None
+    parts, seen, todo = [text], {kernel}, [text]
+    while todo:
+        body = todo.pop()
+        for callee in re.findall(r"\b([a-z_0-9]+_(?:item|row))\(", body):
+            if callee not in seen:
+                seen.add(callee)
+                d = definition(callee, "__device__")
+                if d:
+                    parts.append(d)
+                    todo.append(d)
+    return hashlib.sha1("\n".join(parts).encode()).hexdigest()
 
 
 def measured_traffic(name, level):

@@ -76,8 +76,14 @@ typedef struct {
                              0: launch every kernel directly                    */
   int autotune;           /* 1: at mesh setup, time the SpMV, Vanka and transfer
                              kernels of every level at workgroup sizes 64, 128
-                             and 256 and keep the fastest (scheduling only:
-                             results are bitwise the same); 0: 256 throughout */
+                             and 256, the fused residual + Vanka apply against
+                             the separate kernels, and the bottom of the V-cycle
+                             (levels <= 2 and the coarse solve) in a single
+                             workgroup against its launches, and keep the
+                             fastest (scheduling only: results are bitwise the
+                             same); 0: 256 throughout, separate kernels;
+                             2: as 0 with the fused apply on every level;
+                             3: as 0 with the single-workgroup bottom cycle  */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 
@@ -318,9 +324,11 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..4] = SpMV, Vanka apply,
- * Vanka update, restriction from `level`, prolongation to `level` (5 ints,
- * caller-owned).  DNNMG_ESTATE before dnnmg_setup_mesh. */
+/* Workgroup sizes in use on `level`: block_sizes[0..6] = SpMV, Vanka apply,
+ * Vanka update, restriction from `level`, prolongation to `level`, the fused
+ * residual + Vanka apply (0: SpMV and apply run separately), and the
+ * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0)
+ * (7 ints, caller-owned).  DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:
  * q_blocks = number of 3x3 Q1 blocks (sum of the node neighbour counts),

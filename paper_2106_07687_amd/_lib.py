@@ -263,10 +263,14 @@ class Context:
         return out
 
     def launch_config(self, level):
-        """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong}."""
-        out = np.zeros(5, dtype=np.int32)
+        """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong,
+        vanka_smooth, vcycle_small} (vanka_smooth 0: residual and apply run
+        separately; vcycle_small 1024: the level runs inside the
+        single-workgroup bottom cycle)."""
+        out = np.zeros(7, dtype=np.int32)
         self._check(self.lib.dnnmg_launch_config(self.h, level, out.ctypes.data_as(_IP)))
-        return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong"), out.tolist()))
+        return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong", "vanka_smooth",
+                         "vcycle_small"), out.tolist()))
 
     def level_stats(self, level):
         v = [C.c_longlong() for _ in range(4)]

@@ -39,7 +39,7 @@ bool params_ok(const dnnmg_params *p) {
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
-         (p->autotune == 0 || p->autotune == 1);
+         (p->autotune >= 0 && p->autotune <= 3);
 }
 
 void upload_level(DevLevel &D, hipStream_t s) {
@@ -328,11 +328,15 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
     if (c.prm.precision == 1) {
       c.s32 = std::make_unique<Solver<float>>(&c);
       c.s32->setup(finest_level);
-      if (c.prm.autotune) c.s32->autotune();
+      if (c.prm.autotune == 1) c.s32->autotune();
+      if (c.prm.autotune == 2) c.s32->fuse_all();
+      if (c.prm.autotune == 3) c.s32->set_small_top(kSmallLevels - 1);
     } else {
       c.s64 = std::make_unique<Solver<double>>(&c);
       c.s64->setup(finest_level);
-      if (c.prm.autotune) c.s64->autotune();
+      if (c.prm.autotune == 1) c.s64->autotune();
+      if (c.prm.autotune == 2) c.s64->fuse_all();
+      if (c.prm.autotune == 3) c.s64->set_small_top(kSmallLevels - 1);
     }
     return DNNMG_OK;
   });
@@ -681,6 +685,8 @@ int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes) {
     block_sizes[2] = o.bs_update;
     block_sizes[3] = o.bs_restrict;
     block_sizes[4] = o.bs_prolong;
+    block_sizes[5] = o.bs_smooth;
+    block_sizes[6] = (level >= 1 && level <= S.small_top()) ? 1024 : 0;
   };
   if (c.s32)
     fill(*c.s32);

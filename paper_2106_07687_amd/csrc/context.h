@@ -123,6 +123,7 @@ struct OpLevel {
   // restrict / prolong are the transfers between this level and the next
   // coarser one
   int bs_spmv = 256, bs_apply = 256, bs_update = 256, bs_restrict = 256, bs_prolong = 256;
+  int bs_smooth = 0;   // > 0: residual + Vanka apply fused (k_vanka_smooth) at this size
 };
 
 class Ctx;
@@ -150,10 +151,22 @@ class Solver {
   // and 256 and keeps the fastest (the choice changes scheduling only: every
   // thread does the same arithmetic, results are bitwise the same).
   void autotune();
+  // Fused residual + Vanka apply on every level, workgroup size 256 (a fixed
+  // configuration, e.g. for reproducible comparisons).
+  void fuse_all() {
+    for (auto &o : ops_) o.bs_smooth = 256;
+  }
+  // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup
+  // launch; 0 = off.  Needs the blocked level-0 inverse.
+  void set_small_top(int top) { small_top_ = gj_b_ > 0 ? std::min(top, kSmallLevels - 1) : 0; }
+  int small_top() const { return small_top_; }
 
  private:
   Ctx *ctx_;
   int lin_level_ = -1;
+  int small_top_ = 0;
+  SmallCycle<T> small_params(int top, const T *b, T *x);
+  void launch_small(int top, const T *b, T *x);
   // Launch-bound sequences (a V-cycle from a given level, the level-0
   // Gauss-Jordan sweep) are captured once into HIP graphs and replayed; a
   // slot is rebuilt when the context's graph generation changes.

@@ -419,20 +419,20 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
 // -------------------------------------------------------------- SpMV
 // y = b - J x (if b) or y = J x, T precision.
 constexpr int kSpmvChunk = 16;
+// Row i of J x (3 values).  Chunks of kSpmvChunk neighbours: all column
+// indices of a chunk are loaded before the x values they select, so the
+// dependent index -> x chain costs two memory latencies per chunk instead of
+// two per neighbour (the same summation order as a plain loop).
 template <typename T>
-__global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
-                       const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.N) return;
+__device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                         const T *__restrict__ x, int i, T &a0, T &a1, T &a2) {
   const int s = i / kS, lane = i % kS;
   const int wq = L.wq[s], wx = L.wx[s];
   const T *jq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
   const int *cq = L.colq + static_cast<size_t>(L.oq[s]) * kS + lane;
-  T a0 = 0, a1 = 0, a2 = 0;
-  // Chunks of kSpmvChunk neighbours: all column indices of a chunk are loaded
-  // before the x values they select, so the dependent index -> x chain costs
-  // two memory latencies per chunk instead of two per neighbour (the same
-  // summation order as a plain loop).
+  a0 = 0;
+  a1 = 0;
+  a2 = 0;
   for (int k0 = 0; k0 < wq; k0 += kSpmvChunk) {
     int jv[kSpmvChunk];
 #pragma unroll
@@ -465,6 +465,17 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
     for (int u = 0; u < kSpmvChunk; ++u)
       if (jv[u] >= 0) a2 += jx[(k0 + u) * kS] * xv[u];
   }
+}
+
+// Each kernel below is a grid over items (nodes, cells) calling the item
+// function of the same name; the single-workgroup coarse V-cycle calls the
+// same item functions, so both paths compute bitwise the same values.
+template <typename T>
+__device__ __forceinline__ void spmv_item(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                          const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y,
+                                          int i) {
+  T a0, a1, a2;
+  spmv_row(L, JQ, JX, x, i, a0, a1, a2);
   if (b) {
     y[3 * i] = b[3 * i] - a0;
     y[3 * i + 1] = b[3 * i + 1] - a1;
@@ -474,6 +485,13 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
     y[3 * i + 1] = a1;
     y[3 * i + 2] = a2;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                       const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < L.N) spmv_item(L, JQ, JX, x, b, y, i);
 }
 
 // -------------------------------------------------------------- Vanka
@@ -561,10 +579,8 @@ __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__re
 // delta_c = inv_c r|_c, one thread per cell, stored entry-major
 // delta[(3 a + f) * C + c].
 template <typename T>
-__global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
-                              T *__restrict__ delta) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= L.C) return;
+__device__ __forceinline__ void apply_item(const LevelView &L, const T *__restrict__ inv, const T *__restrict__ r,
+                                           T *__restrict__ delta, int c) {
   const int4 cn = L.cells[c];
   const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
   T rc[12];
@@ -581,15 +597,64 @@ __global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__res
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
+                              T *__restrict__ delta) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < L.C) apply_item(L, inv, r, delta, c);
+}
+
+// Fused residual + Vanka apply (for small levels, where launches and memory
+// latency dominate): 4 threads per cell, thread a evaluates the residual row
+// b - J x of the cell's node a with the row arithmetic of k_spmv; the four
+// rows are exchanged between the cell's lanes; thread a then forms the
+// correction rows 3a..3a+2 with the arithmetic of k_vanka_apply.  Results are
+// bitwise those of k_spmv followed by k_vanka_apply (a node shared by several
+// cells is evaluated by each of them).  The workgroup size is a multiple of 4.
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_smooth(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                                      const T *__restrict__ x, const T *__restrict__ b,
+                                                      const T *__restrict__ inv, T *__restrict__ delta) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = gid >> 2, a = gid & 3;
+  const bool live = c < L.C;
+  T r0 = 0, r1 = 0, r2 = 0;
+  if (live) {
+    const int4 cn = L.cells[c];
+    const int node = a == 0 ? cn.x : a == 1 ? cn.y : a == 2 ? cn.z : cn.w;
+    T a0, a1, a2;
+    spmv_row(L, JQ, JX, x, node, a0, a1, a2);
+    r0 = b[3 * node] - a0;
+    r1 = b[3 * node + 1] - a1;
+    r2 = b[3 * node + 2] - a2;
+  }
+  const int lb = (threadIdx.x & 63) & ~3;
+  T rc[12];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    rc[3 * q] = __shfl(r0, lb + q);
+    rc[3 * q + 1] = __shfl(r1, lb + q);
+    rc[3 * q + 2] = __shfl(r2, lb + q);
+  }
+  if (!live) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = 3 * a + q;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
+    delta[static_cast<size_t>(i) * L.C + c] = s;
+  }
+}
+
 // x_j += omega / m_j * sum over the cells containing j of their corrections.
 // The first kCadj (cell, slot) entries of a node are loaded before any of
 // their corrections, so that a thread waits on two memory latencies, not on
 // two per cell (small levels have too few waves to hide a dependent chain).
 constexpr int kCadj = 8;
 template <typename T>
-__global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.N) return;
+__device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,
+                                            T *__restrict__ x, int i) {
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
   const size_t C = static_cast<size_t>(L.C);
@@ -623,14 +688,19 @@ __global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__re
   x[3 * i + 2] += w * a2;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < L.N) update_item(L, delta, omega, x, i);
+}
+
 // -------------------------------------------------------------- transfers
 
 
 // x_fine += P e_coarse (bilinear interpolation in parent coordinates).
 template <typename T>
-__global__ void k_prolong_add(TransferView tv, const T *__restrict__ ec, T *__restrict__ xf) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= tv.Nf) return;
+__device__ __forceinline__ void prolong_item(const TransferView &tv, const T *__restrict__ ec, T *__restrict__ xf,
+                                             int f) {
   T v0, v1, v2;
   if (f < tv.Nc) {
     v0 = ec[3 * f];
@@ -652,11 +722,16 @@ __global__ void k_prolong_add(TransferView tv, const T *__restrict__ ec, T *__re
   xf[3 * f + 2] += v2;
 }
 
+template <typename T>
+__global__ void k_prolong_add(TransferView tv, const T *__restrict__ ec, T *__restrict__ xf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < tv.Nf) prolong_item(tv, ec, xf, f);
+}
+
 // r_coarse = P^T r_fine with the Dirichlet velocity rows of the coarse level zeroed.
 template <typename T>
-__global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= tv.Nc) return;
+__device__ __forceinline__ void restrict_item(const TransferView &tv, const T *__restrict__ rf, T *__restrict__ rc,
+                                              int j) {
   T a0 = 0, a1 = 0, a2 = 0;
   for (int e = tv.rptr[j]; e < tv.rptr[j + 1]; ++e) {
     const int f = tv.ridx[e];
@@ -672,6 +747,12 @@ __global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restr
   rc[3 * j] = a0;
   rc[3 * j + 1] = a1;
   rc[3 * j + 2] = a2;
+}
+
+template <typename T>
+__global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < tv.Nc) restrict_item(tv, rf, rc, j);
 }
 
 // -------------------------------------------------------------- coarse solve
@@ -940,11 +1021,9 @@ __global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__re
 // x = blockdiag(A_s)^{-1} b on the padded blocks (compact inverses, nb x nb
 // each): 32 lanes per row split the dot product; padding unknowns skipped.
 template <typename T>
-__global__ void __launch_bounds__(256) k_dense_solve_blk(int nblk, int nb, const double *__restrict__ Ainv,
-                                                         const int *__restrict__ bdof, const T *__restrict__ b,
-                                                         T *__restrict__ x) {
-  const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int lane = threadIdx.x & 31;
+__device__ __forceinline__ void dense_row_blk(int nblk, int nb, const double *__restrict__ Ainv,
+                                              const int *__restrict__ bdof, const T *__restrict__ b,
+                                              T *__restrict__ x, int row, int lane) {
   const bool ok = row < nblk * nb;
   const int sb = ok ? row / nb : 0;
   const int dst = ok ? bdof[row] : -1;
@@ -960,6 +1039,13 @@ __global__ void __launch_bounds__(256) k_dense_solve_blk(int nblk, int nb, const
 #pragma unroll
   for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
   if (dst >= 0 && lane == 0) x[dst] = static_cast<T>(s);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_solve_blk(int nblk, int nb, const double *__restrict__ Ainv,
+                                                         const int *__restrict__ bdof, const T *__restrict__ b,
+                                                         T *__restrict__ x) {
+  dense_row_blk(nblk, nb, Ainv, bdof, b, x, blockIdx.x * 8 + (threadIdx.x >> 5), threadIdx.x & 31);
 }
 
 __global__ void k_identity_right(int n, double *__restrict__ W) {
@@ -1042,6 +1128,72 @@ template <typename T>
 __global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] += static_cast<double>(w[i]);
+}
+
+// --------------------------------------------- single-workgroup coarse cycle
+// The bottom of a V-cycle (levels top..1 and the level-0 solve, top <= 2) in
+// one workgroup: the phases of the multi-launch V-cycle (zero the iterate,
+// Vanka sweeps, residual, restriction, coarse solve, prolongation) run in the
+// same order, separated by workgroup barriers instead of kernel boundaries,
+// each phase looping over its items with the item functions of the kernels
+// above, so every value is bitwise the one of the multi-launch path.
+constexpr int kSmallLevels = 3;
+template <typename T>
+struct SmallLevel {
+  LevelView L;
+  TransferView tv;            // from the next coarser level (unused on level 0)
+  const T *JQ, *JX, *inv;
+  T *delta, *r, *b, *x;
+};
+template <typename T>
+struct SmallCycle {
+  SmallLevel<T> lv[kSmallLevels];
+  int top, nu_pre, nu_post, nblk, nb;
+  T omega;
+  const double *Ainv;
+  const int *bdof;
+};
+
+template <typename T>
+__device__ void small_sweep(const SmallLevel<T> &V, T omega, bool zero_start) {
+  const T *r = V.b;
+  if (!zero_start) {
+    for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
+    __syncthreads();
+    r = V.r;
+  }
+  for (int c = threadIdx.x; c < V.L.C; c += blockDim.x) apply_item(V.L, V.inv, r, V.delta, c);
+  __syncthreads();
+  for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) update_item(V.L, V.delta, omega, V.x, i);
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int l = kSmallLevels - 1; l >= 1; --l) {
+    if (l > P.top) continue;
+    const SmallLevel<T> &V = P.lv[l];
+    for (int i = tid; i < 3 * V.L.N; i += nt) V.x[i] = T(0);
+    __syncthreads();
+    for (int k = 0; k < P.nu_pre; ++k) small_sweep(V, P.omega, k == 0);
+    for (int i = tid; i < V.L.N; i += nt) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
+    __syncthreads();
+    for (int j = tid; j < V.tv.Nc; j += nt) restrict_item(V.tv, V.r, P.lv[l - 1].b, j);
+    __syncthreads();
+  }
+  for (int row = tid >> 5; row < P.nblk * P.nb; row += nt >> 5)
+    dense_row_blk(P.nblk, P.nb, P.Ainv, P.bdof, P.lv[0].b, P.lv[0].x, row, tid & 31);
+  __syncthreads();
+#pragma unroll
+  for (int l = 1; l < kSmallLevels; ++l) {
+    if (l > P.top) continue;
+    const SmallLevel<T> &V = P.lv[l];
+    for (int f = tid; f < V.tv.Nf; f += nt) prolong_item(V.tv, P.lv[l - 1].x, V.x, f);
+    __syncthreads();
+    for (int k = 0; k < P.nu_post; ++k) small_sweep(V, P.omega, false);
+  }
 }
 
 // ---------------------------------------------------- per-simulation BLAS-1

@@ -323,6 +323,7 @@ void Solver<T>::autotune() {
     throw DnnmgError{DNNMG_EDEVICE, "hipEventCreate failed"};
   }
   const int cand[3] = {64, 128, 256};
+  float last_t = 0.0f;   // time of the last pick's winner (4 launches, ms)
   auto pick = [&](auto launch) {
     float best_t = 1e30f;
     int best = 256;
@@ -341,6 +342,7 @@ void Solver<T>::autotune() {
           best = bs;
         }
       }
+    last_t = best_t;
     return best;
   };
   try {
@@ -358,6 +360,21 @@ void Solver<T>::autotune() {
         hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
                            o.delta.p);
       });
+      // residual + apply: separate kernels at their best sizes, or fused
+      o.bs_smooth = 0;
+      const int bsp = o.bs_spmv, bap = o.bs_apply;
+      pick([&](int) {
+        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bsp)), dim3(bsp), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
+                           o.b.p, o.r.p);
+        hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bap)), dim3(bap), 0, s, v, o.inv.p, o.r.p,
+                           o.delta.p);
+      });
+      const float t_sep = last_t;
+      const int bsm = pick([&](int bs) {
+        hipLaunchKernelGGL(k_vanka_smooth<T>, dim3(blocks(4 * static_cast<size_t>(L.h.C), bs)), dim3(bs), 0, s,
+                           v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.inv.p, o.delta.p);
+      });
+      if (last_t < t_sep) o.bs_smooth = bsm;
       o.bs_update = pick([&](int bs) {
         hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.delta.p, omega,
                            o.t.p);
@@ -373,6 +390,23 @@ void Solver<T>::autotune() {
       });
       LAUNCH_CHECK("autotune");
     }
+    // bottom of the V-cycle in one workgroup (levels 1..top), if faster than
+    // the launches it replaces (those replayed from a graph, as in use)
+    small_top_ = 0;
+    const int tmax = std::min(kSmallLevels - 1, static_cast<int>(ops_.size()) - 1);
+    for (int top = 1; top <= tmax && gj_b_ > 0; ++top) {
+      OpLevel<T> &o = ops_[top];
+      const int keep = small_top_;
+      pick([&](int) { vcycle(top, o.b.p, o.x.p); });
+      const float t_multi = last_t;
+      small_top_ = top;
+      pick([&](int) { vcycle(top, o.b.p, o.x.p); });
+      if (!(last_t < t_multi)) {
+        small_top_ = keep;
+        break;
+      }
+    }
+    clear_graphs();
   } catch (...) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -467,11 +501,15 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
   OpLevel<T> &o = ops_[l];
   hipStream_t s = ctx_->stream;
   const T *r = b;
-  if (!zero_start) {
-    spmv(l, x, b, o.r.p);
-    r = o.r.p;
-  }
-  {
+  if (!zero_start && o.bs_smooth > 0) {
+    ProfScope ps(ctx_->prof, s, "vanka_smooth", l);
+    hipLaunchKernelGGL(k_vanka_smooth<T>, dim3(blocks(4 * static_cast<size_t>(L.h.C), o.bs_smooth)),
+                       dim3(o.bs_smooth), 0, s, L.view(), o.JQ.p, o.JX.p, x, b, o.inv.p, o.delta.p);
+  } else {
+    if (!zero_start) {
+      spmv(l, x, b, o.r.p);
+      r = o.r.p;
+    }
     ProfScope ps(ctx_->prof, s, "vanka_apply", l);
     hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
                        o.inv.p, r, o.delta.p);
@@ -509,7 +547,49 @@ void Solver<T>::restrict_to(int l, const T *rf, T *rc) {
 }
 
 template <typename T>
+SmallCycle<T> Solver<T>::small_params(int top, const T *b, T *x) {
+  SmallCycle<T> P{};
+  for (int l = 0; l <= top; ++l) {
+    DevLevel &L = *ctx_->levels[l];
+    OpLevel<T> &o = ops_[l];
+    SmallLevel<T> &V = P.lv[l];
+    V.L = L.view();
+    if (l > 0) {
+      DevLevel &Cl = *ctx_->levels[l - 1];
+      V.tv = TransferView{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
+    }
+    V.JQ = o.JQ.p;
+    V.JX = o.JX.p;
+    V.inv = o.inv.p;
+    V.delta = o.delta.p;
+    V.r = o.r.p;
+    V.b = l == top ? const_cast<T *>(b) : o.b.p;
+    V.x = l == top ? x : o.x.p;
+  }
+  P.top = top;
+  P.nu_pre = ctx_->prm.nu_pre;
+  P.nu_post = ctx_->prm.nu_post;
+  P.omega = static_cast<T>(ctx_->prm.vanka_omega);
+  P.nblk = nblk_;
+  P.nb = nb_;
+  P.Ainv = Ainv_.p;
+  P.bdof = bdof_.p;
+  return P;
+}
+
+template <typename T>
+void Solver<T>::launch_small(int top, const T *b, T *x) {
+  ProfScope ps(ctx_->prof, ctx_->stream, "vcycle_small", top);
+  hipLaunchKernelGGL(k_vcycle_small<T>, dim3(1), dim3(1024), 0, ctx_->stream, small_params(top, b, x));
+  LAUNCH_CHECK("k_vcycle_small");
+}
+
+template <typename T>
 void Solver<T>::vcycle(int l, const T *b, T *x) {
+  if (l >= 1 && l <= small_top_) {
+    launch_small(l, b, x);
+    return;
+  }
   if (l > 0 && use_graph(l)) {
     const auto key = std::make_tuple(l, static_cast<const void *>(b), static_cast<const void *>(x));
     // bound the cache: keys of freed work vectors are never looked up again

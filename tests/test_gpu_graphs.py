@@ -111,12 +111,62 @@ def test_autotuned_launches_are_bitwise_equal():
     for l in range(LEVEL + 1):
         cfg = ctxs[0].launch_config(l)
         print(f"[tune] level {l}: {cfg}", flush=True)
-        assert set(cfg.values()) <= {64, 128, 256}
-        assert set(ctxs[1].launch_config(l).values()) == {256}
+        assert set(cfg.values()) <= {0, 64, 128, 256, 1024}
+        assert set(ctxs[1].launch_config(l).values()) <= {0, 256}
     sts = [c.state(LEVEL) for c in ctxs]
     for k in range(2):
         infos = [c.step(st, DT) for c, st in zip(ctxs, sts)]
         assert infos[0] == infos[1]
         assert np.array_equal(sts[0].get()[0], sts[1].get()[0]), k
+    for st in sts:
+        st.close()
+
+
+def test_fused_residual_and_apply_is_bitwise_equal():
+    """autotune=2 fuses the residual into the Vanka apply on every level."""
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(2)
+    ctxs = []
+    for tune in (2, 0):
+        ctx = P.Context(precision=1, nu=macro.nu, autotune=tune)
+        ctx.setup_mesh(macro, LEVEL)
+        ctxs.append(ctx)
+    assert all(ctxs[0].launch_config(l)["vanka_smooth"] == 256 for l in range(1, LEVEL + 1))
+    lev = mesh.hierarchy(macro, LEVEL)
+    x = random_state(lev[LEVEL].n_nodes, 5) * 0.3
+    sts = []
+    for ctx in ctxs:
+        st = ctx.state(LEVEL)
+        st.set(x, 0.0)
+        ctx.linearize(st, LEVEL, DT)
+        sts.append(st)
+    for l in (LEVEL, 2, 1):
+        b = _rhs(lev, l, 80 + l)
+        x0 = _rhs(lev, l, 90 + l) * 0.1
+        assert np.array_equal(ctxs[0].vanka_sweep(l, x0, b), ctxs[1].vanka_sweep(l, x0, b)), l
+        assert np.array_equal(ctxs[0].vcycle(l, b), ctxs[1].vcycle(l, b)), l
+    for st in sts:
+        st.close()
+
+
+def test_single_workgroup_bottom_cycle_is_bitwise_equal():
+    """autotune=3 runs levels 1-2 and the coarse solve in one workgroup."""
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(3)
+    ctxs = []
+    for tune in (3, 0):
+        ctx = P.Context(precision=1, nu=macro.nu, autotune=tune)
+        ctx.setup_mesh(macro, LEVEL)
+        ctxs.append(ctx)
+    assert [ctxs[0].launch_config(l)["vcycle_small"] for l in range(LEVEL + 1)] == [0, 1024, 1024, 0]
+    sts = [c.state(LEVEL) for c in ctxs]
+    lev = mesh.hierarchy(macro, LEVEL)
+    for k in range(2):
+        infos = [c.step(st, DT) for c, st in zip(ctxs, sts)]
+        assert infos[0] == infos[1], k
+        assert np.array_equal(sts[0].get()[0], sts[1].get()[0]), k
+    for l in (1, 2, LEVEL):
+        b = _rhs(lev, l, 100 + l)
+        assert np.array_equal(ctxs[0].vcycle(l, b), ctxs[1].vcycle(l, b)), l
     for st in sts:
         st.close()
