@@ -309,6 +309,8 @@ def main():
                     help="roofline: HIP events only around the fine-level GMG kernels and "
                          "the network kernels; all: every kernel of every level, launched "
                          "directly (no graphs; events add launch overhead to the timings)")
+    ap.add_argument("--newton-predictor", type=int, default=1, choices=(0, 1),
+                    help="1: Newton starts from the linear extrapolation of the last two states")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured graphs")
     ap.add_argument("--batch-sims", type=int, default=64,
@@ -339,7 +341,7 @@ def main():
         del src, dst
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
-                    use_graphs=0 if args.no_graphs else 1)
+                    use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor)
     F = args.level
     if args.profile == "all":
         gmg_keys = dnn_keys = None
@@ -503,7 +505,8 @@ def main():
                    "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
                    "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
                    "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats),
-                   "graphs": not args.no_graphs, "profile": args.profile},
+                   "graphs": not args.no_graphs, "profile": args.profile,
+                   "newton_predictor": args.newton_predictor},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

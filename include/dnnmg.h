@@ -52,8 +52,9 @@ typedef struct dnnmg_batch dnnmg_batch;
  * the paper's unstated constants: theta = 1/2 (Crank-Nicolson, Sec. 2.1),
  * LPS parameter alpha_T = alpha0 / (nu / h_T^2 + 1/k) with alpha0 = 0.5,
  * Newton with full steps and absolute tolerance 1e-10 on the l2 norm of the
- * nonlinear residual, GMRES(30) with relative tolerance 1e-2 and at most 100
- * iterations, V(2,2) cycles with additive cell-Vanka (omega = 0.6). */
+ * nonlinear residual, started from the linear extrapolation of the last two
+ * states, GMRES(30) with relative tolerance 1e-2 and at most 100 iterations,
+ * V(2,2) cycles with additive cell-Vanka (omega = 0.6); graphs, autotuning. */
 typedef struct {
   double nu;              /* kinematic viscosity (the paper's 1/Re)              */
   double alpha0;          /* LPS scale                                           */
@@ -84,6 +85,10 @@ typedef struct {
                              same); 0: 256 throughout, separate kernels;
                              2: as 0 with the fused apply on every level;
                              3: as 0 with the single-workgroup bottom cycle  */
+  int newton_predictor;   /* 0: Newton starts from x_{n-1}; 1: from the linear
+                             extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
+                             x_{n-2}) once a state has taken a step (the
+                             converged x_n is the same to the tolerance)      */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 

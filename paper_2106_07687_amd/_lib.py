@@ -34,6 +34,7 @@ class Params(C.Structure):
                 ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int), ("gmres_max", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vanka_omega", C.c_double),
                 ("precision", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
+                ("newton_predictor", C.c_int),
                 ("stream", C.c_void_p)]
 
 

@@ -39,7 +39,7 @@ bool params_ok(const dnnmg_params *p) {
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
-         (p->autotune >= 0 && p->autotune <= 3);
+         (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1);
 }
 
 void upload_level(DevLevel &D, hipStream_t s) {
@@ -97,6 +97,12 @@ int step_impl(Ctx &c, State &st, double dt, dnnmg_step_stats *stats) {
   bool ok = false;
   OpLevel<T> &o = S.op(l);
   bool use_pending = st.has_pending;
+  if (c.prm.newton_predictor && st.has_prev && st.dt_prev > 0.0) {
+    // Newton starts from x_{n-1} + (k_n / k_{n-1}) (x_{n-1} - x_{n-2})
+    hipLaunchKernelGGL(k_extrapolate, dim3(blocks(n, 256)), dim3(256), 0, s, n, dt / st.dt_prev, st.xprev.p,
+                       st.x.p);
+    check(hipGetLastError(), "predictor");
+  }
 retry:
   hipLaunchKernelGGL(k_impose_bc, dim3(blocks(N, 256)), dim3(256), 0, s, c.levels[l]->view(),
                      c.phys(dt, t_new), st.x.p);
@@ -127,7 +133,7 @@ retry:
   }
   if (!ok && use_pending) {
     // switch-off of the network for this step (Sec. 3.3): redo the step with
-    // the plain right-hand side f_n(x_{n-1})
+    // the plain right-hand side f_n(x_{n-1}), from x_{n-1}
     check(hipMemcpyAsync(st.x.p, c.xo_save.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s),
           "fallback restore");
     use_pending = false;
@@ -145,6 +151,12 @@ retry:
   }
   st.t = t_new;
   st.has_pending = false;
+  if (c.prm.newton_predictor) {
+    if (st.xprev.n != static_cast<size_t>(n)) st.xprev.alloc(n);
+    check(hipMemcpyAsync(st.xprev.p, c.xo_save.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "xprev");
+    st.has_prev = true;
+    st.dt_prev = dt;
+  }
   return DNNMG_OK;
 }
 
@@ -201,6 +213,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->precision = 1;
   p->use_graphs = 1;
   p->autotune = 1;
+  p->newton_predictor = 1;
   p->stream = nullptr;
   return DNNMG_OK;
 }
@@ -411,6 +424,7 @@ int dnnmg_state_set(dnnmg_state *s, const double *uvp, double t) {
     check(hipStreamSynchronize(c.stream), "state sync");
     s->impl.t = t;
     s->impl.has_pending = false;
+    s->impl.has_prev = false;
     return DNNMG_OK;
   });
 }

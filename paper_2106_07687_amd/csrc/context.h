@@ -261,6 +261,9 @@ struct State {
   DevBuf<double> x;
   DevBuf<double> pending_rhs;   // DNN-MG right-hand side for the next step
   bool has_pending = false;
+  DevBuf<double> xprev;         // state before the last step (Newton predictor)
+  bool has_prev = false;
+  double dt_prev = 0.0;
 };
 
 inline int blocks(size_t n, int bs) { return static_cast<int>((n + bs - 1) / bs); }

@@ -1124,6 +1124,12 @@ __global__ void k_convert(int n, const A *__restrict__ x, B *__restrict__ y) {
   if (i < n) y[i] = static_cast<B>(x[i]);
 }
 
+// x <- x + a (x - y): linear extrapolation from the two previous states.
+__global__ void k_extrapolate(int n, double a, const double *__restrict__ y, double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += a * (x[i] - y[i]);
+}
+
 template <typename T>
 __global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
