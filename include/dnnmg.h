@@ -329,11 +329,12 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..6] = SpMV, Vanka apply,
+/* Workgroup sizes in use on `level`: block_sizes[0..7] = SpMV, Vanka apply,
  * Vanka update, restriction from `level`, prolongation to `level`, the fused
- * residual + Vanka apply (0: SpMV and apply run separately), and the
- * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0)
- * (7 ints, caller-owned).  DNNMG_ESTATE before dnnmg_setup_mesh. */
+ * residual + Vanka apply (0: SpMV and apply run separately), the
+ * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0),
+ * and the fused residual + restriction (0: separate) (8 ints, caller-owned).
+ * DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:
  * q_blocks = number of 3x3 Q1 blocks (sum of the node neighbour counts),

@@ -265,13 +265,14 @@ class Context:
 
     def launch_config(self, level):
         """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong,
-        vanka_smooth, vcycle_small} (vanka_smooth 0: residual and apply run
-        separately; vcycle_small 1024: the level runs inside the
-        single-workgroup bottom cycle)."""
-        out = np.zeros(7, dtype=np.int32)
+        vanka_smooth, vcycle_small, restrict_residual} (vanka_smooth 0:
+        residual and apply run separately; vcycle_small 1024: the level runs
+        inside the single-workgroup bottom cycle; restrict_residual 0: the
+        residual is stored, then restricted)."""
+        out = np.zeros(8, dtype=np.int32)
         self._check(self.lib.dnnmg_launch_config(self.h, level, out.ctypes.data_as(_IP)))
         return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong", "vanka_smooth",
-                         "vcycle_small"), out.tolist()))
+                         "vcycle_small", "restrict_residual"), out.tolist()))
 
     def level_stats(self, level):
         v = [C.c_longlong() for _ in range(4)]

@@ -124,6 +124,7 @@ struct OpLevel {
   // coarser one
   int bs_spmv = 256, bs_apply = 256, bs_update = 256, bs_restrict = 256, bs_prolong = 256;
   int bs_smooth = 0;   // > 0: residual + Vanka apply fused (k_vanka_smooth) at this size
+  int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
 };
 
 class Ctx;
@@ -154,7 +155,10 @@ class Solver {
   // Fused residual + Vanka apply on every level, workgroup size 256 (a fixed
   // configuration, e.g. for reproducible comparisons).
   void fuse_all() {
-    for (auto &o : ops_) o.bs_smooth = 256;
+    for (auto &o : ops_) {
+      o.bs_smooth = 256;
+      o.bs_rres = 256;
+    }
   }
   // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup
   // launch; 0 = off.  Needs the blocked level-0 inverse.
@@ -198,6 +202,13 @@ class Solver {
   DevBuf<T> V_, Z_, w_;
   DevBuf<double> partial_, hdev_;
   std::vector<double> hhost_;
+  // pipelined Hessenberg read-back: one device slot, pinned host slot and
+  // event per Arnoldi step
+  DevBuf<double> hcol_;
+  double *hpin_ = nullptr;
+  std::vector<hipEvent_t> hev_;
+  int hslots_ = 0;
+  void free_pipeline();
   void ensure_gmres(int level, int m);
   // GMRES with per-simulation inner products, Hessenberg matrices and Givens
   // rotations on a batch level (each simulation's own Krylov space).

@@ -652,9 +652,15 @@ __global__ void __launch_bounds__(256) k_vanka_smooth(LevelView L, const T *__re
 // their corrections, so that a thread waits on two memory latencies, not on
 // two per cell (small levels have too few waves to hide a dependent chain).
 constexpr int kCadj = 8;
+// Explicit fused multiply-add (the rounding must not depend on whether the
+// compiler contracts a product that other code also uses).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// set: x is zero on entry (first sweep from a zero iterate): store instead of add.
 template <typename T>
 __device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,
-                                            T *__restrict__ x, int i) {
+                                            T *__restrict__ x, int i, bool set = false) {
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
   const size_t C = static_cast<size_t>(L.C);
@@ -683,15 +689,22 @@ __device__ __forceinline__ void update_item(const LevelView &L, const T *__restr
     a2 += delta[static_cast<size_t>(3 * a + 2) * C + c];
   }
   const T w = omega / static_cast<T>(e1 - e0);
-  x[3 * i] += w * a0;
-  x[3 * i + 1] += w * a1;
-  x[3 * i + 2] += w * a2;
+  if (set) {
+    x[3 * i] = w * a0;
+    x[3 * i + 1] = w * a1;
+    x[3 * i + 2] = w * a2;
+  } else {
+    x[3 * i] = fma_t(w, a0, x[3 * i]);
+    x[3 * i + 1] = fma_t(w, a1, x[3 * i + 1]);
+    x[3 * i + 2] = fma_t(w, a2, x[3 * i + 2]);
+  }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x) {
+__global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__restrict__ delta, T omega, T *__restrict__ x,
+                                                      int set) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < L.N) update_item(L, delta, omega, x, i);
+  if (i < L.N) update_item(L, delta, omega, x, i, set != 0);
 }
 
 // -------------------------------------------------------------- transfers
@@ -753,6 +766,37 @@ template <typename T>
 __global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < tv.Nc) restrict_item(tv, rf, rc, j);
+}
+
+// r_coarse = P^T (b - J x) without storing the fine residual: each coarse
+// node evaluates the residual rows of the fine nodes it restricts from (a fine
+// node is evaluated by each coarse node that weights it) with the row
+// arithmetic of k_spmv and sums them as k_restrict does: bitwise the result
+// of k_spmv followed by k_restrict.
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_residual(TransferView tv, LevelView Lf, const T *__restrict__ JQ,
+                                                           const T *__restrict__ JX, const T *__restrict__ x,
+                                                           const T *__restrict__ b, T *__restrict__ rc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= tv.Nc) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int e = tv.rptr[j]; e < tv.rptr[j + 1]; ++e) {
+    const int f = tv.ridx[e];
+    T s0, s1, s2;
+    spmv_row(Lf, JQ, JX, x, f, s0, s1, s2);
+    const T r0 = b[3 * f] - s0, r1 = b[3 * f + 1] - s1, r2 = b[3 * f + 2] - s2;
+    const T w = f < tv.Nc ? T(1) : (f < tv.Nc + tv.Ec ? T(0.5) : T(0.25));
+    a0 += w * r0;
+    a1 += w * r1;
+    a2 += w * r2;
+  }
+  if (tv.cflag[j] & 1) {
+    a0 = 0;
+    a1 = 0;
+  }
+  rc[3 * j] = a0;
+  rc[3 * j + 1] = a1;
+  rc[3 * j + 2] = a2;
 }
 
 // -------------------------------------------------------------- coarse solve
@@ -1112,6 +1156,15 @@ __global__ void k_combine(int n, int m, const T *__restrict__ Zb, size_t ld,
   x[i] = static_cast<T>(static_cast<double>(x[i]) + s);
 }
 
+// y = x / sqrt(h2) (y untouched when h2 <= 0): the next Krylov basis vector,
+// normalised with the squared norm the device has just reduced.
+template <typename T>
+__global__ void k_scale_by_norm(int n, const double *__restrict__ h2, const T *__restrict__ x, T *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double hn = sqrt(fmax(*h2, 0.0));
+  if (i < n && hn > 0.0) y[i] = static_cast<T>((1.0 / hn) * static_cast<double>(x[i]));
+}
+
 template <typename T>
 __global__ void k_scale_copy(int n, double a, const T *__restrict__ x, T *__restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1170,7 +1223,7 @@ __device__ void small_sweep(const SmallLevel<T> &V, T omega, bool zero_start) {
   }
   for (int c = threadIdx.x; c < V.L.C; c += blockDim.x) apply_item(V.L, V.inv, r, V.delta, c);
   __syncthreads();
-  for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) update_item(V.L, V.delta, omega, V.x, i);
+  for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) update_item(V.L, V.delta, omega, V.x, i, zero_start);
   __syncthreads();
 }
 
@@ -1181,8 +1234,10 @@ __global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
   for (int l = kSmallLevels - 1; l >= 1; --l) {
     if (l > P.top) continue;
     const SmallLevel<T> &V = P.lv[l];
-    for (int i = tid; i < 3 * V.L.N; i += nt) V.x[i] = T(0);
-    __syncthreads();
+    if (P.nu_pre == 0) {   // otherwise the first sweep stores into x
+      for (int i = tid; i < 3 * V.L.N; i += nt) V.x[i] = T(0);
+      __syncthreads();
+    }
     for (int k = 0; k < P.nu_pre; ++k) small_sweep(V, P.omega, k == 0);
     for (int i = tid; i < V.L.N; i += nt) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
     __syncthreads();

@@ -188,6 +188,7 @@ void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, 
 template <typename T>
 Solver<T>::~Solver() {
   clear_graphs();
+  free_pipeline();
 }
 
 template <typename T>
@@ -377,7 +378,7 @@ void Solver<T>::autotune() {
       if (last_t < t_sep) o.bs_smooth = bsm;
       o.bs_update = pick([&](int bs) {
         hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.delta.p, omega,
-                           o.t.p);
+                           o.t.p, 0);
       });
       DevLevel &Cl = *ctx_->levels[l - 1];
       OpLevel<T> &oc = ops_[l - 1];
@@ -388,6 +389,20 @@ void Solver<T>::autotune() {
       o.bs_prolong = pick([&](int bs) {
         hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, tv, oc.x.p, o.t.p);
       });
+      // residual + restriction: separate at their best sizes, or fused
+      o.bs_rres = 0;
+      const int bsr = o.bs_restrict;
+      pick([&](int) {
+        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bsp)), dim3(bsp), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
+                           o.b.p, o.r.p);
+        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bsr)), dim3(bsr), 0, s, tv, o.r.p, oc.t.p);
+      });
+      const float t_sep2 = last_t;
+      const int bsrr = pick([&](int bs) {
+        hipLaunchKernelGGL(k_restrict_residual<T>, dim3(blocks(L.h.Nc, bs)), dim3(bs), 0, s, tv, v, o.JQ.p,
+                           o.JX.p, o.x.p, o.b.p, oc.t.p);
+      });
+      if (last_t < t_sep2) o.bs_rres = bsrr;
       LAUNCH_CHECK("autotune");
     }
     // bottom of the V-cycle in one workgroup (levels 1..top), if faster than
@@ -517,7 +532,7 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
   {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
     hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, o.bs_update)), dim3(o.bs_update), 0, s, L.view(),
-                       o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x);
+                       o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x, zero_start ? 1 : 0);
   }
   LAUNCH_CHECK("vanka");
 }
@@ -618,14 +633,34 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
   OpLevel<T> &o = ops_[l];
   OpLevel<T> &oc = ops_[l - 1];
   const size_t n = 3 * static_cast<size_t>(L.h.N);
-  hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x, n, T(0));
   const int nu1 = ctx_->prm.nu_pre, nu2 = ctx_->prm.nu_post;
+  // zero iterate: the first sweep stores its update (no separate fill)
+  if (nu1 == 0)
+    hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x, n, T(0));
   for (int k = 0; k < nu1; ++k) vanka_sweep(l, x, b, k == 0);
-  spmv(l, x, b, o.r.p);
-  restrict_to(l, o.r.p, oc.b.p);
+  if (o.bs_rres > 0) {
+    DevLevel &Cl = *ctx_->levels[l - 1];
+    TransferView tv{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
+    ProfScope ps(ctx_->prof, s, "restrict_residual", l);
+    hipLaunchKernelGGL(k_restrict_residual<T>, dim3(blocks(L.h.Nc, o.bs_rres)), dim3(o.bs_rres), 0, s, tv,
+                       L.view(), o.JQ.p, o.JX.p, x, b, oc.b.p);
+    LAUNCH_CHECK("k_restrict_residual");
+  } else {
+    spmv(l, x, b, o.r.p);
+    restrict_to(l, o.r.p, oc.b.p);
+  }
   vcycle(l - 1, oc.b.p, oc.x.p);
   prolong_add(l, oc.x.p, x);
   for (int k = 0; k < nu2; ++k) vanka_sweep(l, x, b, false);
+}
+
+template <typename T>
+void Solver<T>::free_pipeline() {
+  for (auto e : hev_) (void)hipEventDestroy(e);
+  hev_.clear();
+  if (hpin_) (void)hipHostFree(hpin_);
+  hpin_ = nullptr;
+  hslots_ = 0;
 }
 
 template <typename T>
@@ -638,6 +673,16 @@ void Solver<T>::ensure_gmres(int level, int m) {
   partial_.alloc(static_cast<size_t>(1024) * (m + 2));
   hdev_.alloc(static_cast<size_t>(2 * (m + 2)));
   hhost_.assign(2 * (m + 2), 0.0);
+  if (hslots_ < m) {
+    free_pipeline();
+    const size_t stride = 2 * static_cast<size_t>(m + 1) + 1;
+    hcol_.alloc(stride * m);
+    if (hipHostMalloc(reinterpret_cast<void **>(&hpin_), sizeof(double) * stride * m) != hipSuccess)
+      throw DnnmgError{DNNMG_ENOMEM, "hipHostMalloc failed"};
+    hev_.resize(m, nullptr);
+    for (auto &e : hev_) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    hslots_ = m;
+  }
   gm_level_ = level;
   gm_m_ = m;
 }
@@ -645,6 +690,14 @@ void Solver<T>::ensure_gmres(int level, int m) {
 // Right-preconditioned restarted GMRES (Saad) with classical Gram-Schmidt
 // applied twice (FP64 dot products) and Givens rotations.  x = 0 on entry is
 // assumed (Newton corrections); returns the iteration count.
+//
+// Pipelining: each Arnoldi step normalises its new basis vector on the device
+// and copies its Hessenberg column (the two Gram-Schmidt passes and the norm)
+// to pinned host memory with an event; the host enqueues step j + 1 before it
+// reads column j, so the GPU does not wait for the host's Givens rotations.
+// It waits for column j at once only when the residual history predicts that
+// step j may meet the tolerance (or at a restart or the iteration limit); a
+// step enqueued past convergence is discarded (its basis vectors unused).
 template <typename T>
 int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int maxit,
                      double *res0, double *res_out) {
@@ -673,8 +726,10 @@ int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int 
   if (res_out) *res_out = beta0;
   if (beta0 == 0.0) return 0;
   const int m = restart;
-  std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  int it = 0;
+  const size_t stride = 2 * static_cast<size_t>(m + 1) + 1;
+  const double target = rtol * beta0;
+  std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), rh;
+  int it = 0;            // Arnoldi steps whose columns were used
   double resid = beta0;
   OpLevel<T> &o = ops_[level];
   bool first = true;
@@ -699,50 +754,73 @@ int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int 
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
-      T *vj = V_.p + static_cast<size_t>(j) * ld;
-      T *zj = Z_.p + static_cast<size_t>(j) * ld;
-      vcycle(level, vj, zj);
-      spmv(level, zj, nullptr, w_.p);
-      // CGS2
-      dots(j + 1, w_.p, hdev_.p);
-      hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld,
-                         hdev_.p, w_.p);
-      dots(j + 1, w_.p, hdev_.p + (j + 1));
-      hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld,
-                         hdev_.p + (j + 1), w_.p);
-      hipLaunchKernelGGL(k_multidot<T>, dim3(nb, 1), dim3(256), 0, s, n, 1, w_.p, ld, w_.p,
-                         partial_.p);
-      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, nb, 1, partial_.p,
-                         hdev_.p + 2 * (j + 1));
-      LAUNCH_CHECK("gmres iteration");
-      check(hipMemcpyAsync(hhost_.data(), hdev_.p, sizeof(double) * (2 * (j + 1) + 1),
-                           hipMemcpyDeviceToHost, s),
-            "gmres D2H");
-      check(hipStreamSynchronize(s), "gmres sync");
-      const double hn = std::sqrt(std::max(hhost_[2 * (j + 1)], 0.0));
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hhost_[i] + hhost_[j + 1 + i];
-      H[(j + 1) * m + j] = hn;
-      if (j + 1 <= m && hn > 0.0)
-        hipLaunchKernelGGL(k_scale_copy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, 1.0 / hn,
-                           w_.p, V_.p + static_cast<size_t>(j + 1) * ld);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-        H[i * m + j] = t;
+    rh.assign(1, beta);
+    int jend = 0, done_cols = 0;
+    bool conv = false;
+    // host side of column c: Hessenberg entries, rotations, residual estimate
+    auto process = [&](int c) {
+      check(hipEventSynchronize(hev_[c]), "gmres column");
+      const double *hc = hpin_ + stride * c;
+      const double hn = std::sqrt(std::max(hc[2 * (c + 1)], 0.0));
+      for (int i = 0; i <= c; ++i) H[i * m + c] = hc[i] + hc[c + 1 + i];
+      H[(c + 1) * m + c] = hn;
+      for (int i = 0; i < c; ++i) {
+        const double t = cs[i] * H[i * m + c] + sn[i] * H[(i + 1) * m + c];
+        H[(i + 1) * m + c] = -sn[i] * H[i * m + c] + cs[i] * H[(i + 1) * m + c];
+        H[i * m + c] = t;
       }
-      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-      cs[j] = H[j * m + j] / den;
-      sn[j] = H[(j + 1) * m + j] / den;
-      H[j * m + j] = den;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
+      const double den = std::hypot(H[c * m + c], H[(c + 1) * m + c]);
+      cs[c] = H[c * m + c] / den;
+      sn[c] = H[(c + 1) * m + c] / den;
+      H[c * m + c] = den;
+      H[(c + 1) * m + c] = 0.0;
+      g[c + 1] = -sn[c] * g[c];
+      g[c] = cs[c] * g[c];
       ++it;
-      jend = j + 1;
-      resid = std::fabs(g[j + 1]);
-      if (resid <= rtol * beta0 || it >= maxit) break;
+      jend = c + 1;
+      done_cols = c + 1;
+      resid = std::fabs(g[c + 1]);
+      rh.push_back(resid);
+      conv = resid <= target;
+    };
+    int enq = 0;   // steps enqueued in this cycle
+    while (!conv && done_cols < m && it < maxit) {
+      if (enq < m && it + (enq - done_cols) < maxit) {
+        const int j = enq++;
+        T *vj = V_.p + static_cast<size_t>(j) * ld;
+        T *zj = Z_.p + static_cast<size_t>(j) * ld;
+        double *hc = hcol_.p + stride * j;
+        vcycle(level, vj, zj);
+        spmv(level, zj, nullptr, w_.p);
+        // CGS2, the new vector's norm, its normalisation
+        dots(j + 1, w_.p, hc);
+        hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld, hc,
+                           w_.p);
+        dots(j + 1, w_.p, hc + (j + 1));
+        hipLaunchKernelGGL(k_multi_axpy<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, j + 1, V_.p, ld,
+                           hc + (j + 1), w_.p);
+        hipLaunchKernelGGL(k_multidot<T>, dim3(nb, 1), dim3(256), 0, s, n, 1, w_.p, ld, w_.p, partial_.p);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, nb, 1, partial_.p, hc + 2 * (j + 1));
+        hipLaunchKernelGGL(k_scale_by_norm<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, hc + 2 * (j + 1),
+                           w_.p, V_.p + static_cast<size_t>(j + 1) * ld);
+        LAUNCH_CHECK("gmres iteration");
+        check(hipMemcpyAsync(hpin_ + stride * j, hc, sizeof(double) * (2 * (j + 1) + 1),
+                             hipMemcpyDeviceToHost, s),
+              "gmres D2H");
+        check(hipEventRecord(hev_[j], s), "gmres event");
+      }
+      // columns older than the newest: the GPU already has the next step queued
+      while (!conv && done_cols < enq - 1) process(done_cols);
+      if (conv || done_cols >= enq) continue;
+      // the newest column: wait for it now only if it may finish the solve
+      const int c = done_cols;
+      bool wait_now = enq >= m || it + (enq - done_cols) >= maxit;
+      if (!wait_now && rh.size() >= 3) {
+        const double r1 = rh[rh.size() - 1], r2 = rh[rh.size() - 2];
+        const double rate = r2 > 0.0 ? r1 / r2 : 1.0;
+        wait_now = r1 * std::min(rate, 1.0) <= 3.0 * target;
+      }
+      if (wait_now) process(c);
     }
     for (int i = jend - 1; i >= 0; --i) {
       double sacc = g[i];
@@ -753,7 +831,7 @@ int Solver<T>::gmres(int level, const T *b, T *x, double rtol, int restart, int 
     hipLaunchKernelGGL(k_combine<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, jend, Z_.p, ld,
                        hdev_.p, x);
     LAUNCH_CHECK("gmres combine");
-    if (resid <= rtol * beta0) break;
+    if (resid <= target) break;
   }
   check(hipStreamSynchronize(s), "gmres end");
   if (res_out) *res_out = resid;
