@@ -122,6 +122,18 @@ def run_steps(ctx, st, steps, dt, net=None):
     return stats
 
 
+def fine_state(ctx, xl, level, fine_level, corr=None):
+    """P^m x^L on the fine level, with the network's velocity correction added."""
+    x = xl
+    for l in range(level + 1, fine_level + 1):
+        x = ctx.prolong(l, x)
+    if corr is not None:
+        x = x.reshape(-1, 3).copy()
+        x[:, :2] += corr
+        x = x.reshape(-1)
+    return x
+
+
 def velocity_error(ctx, xl, level, fine_level, x_fine, corr=None):
     """Relative l2 error of the fine-level velocity (P^m v^L [+ d]) against
     the fine solution."""
@@ -416,6 +428,12 @@ def main():
     # velocity errors against the fine solution at every timed step (untimed
     # replays of the same deterministic runs)
     err_dnn, err_mgl = [], []
+    n_obs = len(macro.curves)
+    funcs = {}
+
+    def fdict(x):
+        j, d, lf = ctx.functionals(args.level, x, n_obs)
+        return {"j_div": j, "drag": float(d[0]), "lift": float(lf[0])}
     for with_net in (True, False):
         st = ctx.state(args.coarse_level)
         if with_net:
@@ -427,9 +445,14 @@ def main():
             if n > args.warmup:
                 e = velocity_error(ctx, xl, args.coarse_level, args.level, xF[n], corr)
                 (err_dnn if with_net else err_mgl).append(e)
+            if n == nsteps:   # functionals of the last step (Sec. 3.3)
+                funcs["dnnmg" if with_net else "mg_coarse"] = fdict(
+                    fine_state(ctx, xl, args.coarse_level, args.level, corr))
         st.close()
+    funcs["reference_fine_gmg"] = fdict(xF[nsteps])
     err_dnn, err_mgl = float(np.mean(err_dnn)), float(np.mean(err_mgl))
     log(f"velocity error (mean over timed steps): DNN-MG {err_dnn:.3e}, MG(L) {err_mgl:.3e}")
+    log(f"functionals at t = {nsteps * args.dt:.3f}: {funcs}")
 
     for name, prof in (("gmg", g_prof), ("dnnmg", d_prof)):
         for key in sorted(prof, key=lambda k: -prof[k][1])[:14]:
@@ -505,6 +528,7 @@ def main():
                    "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
                    "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
                    "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats),
+                   "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
                    "newton_predictor": args.newton_predictor},
         "roofline": roof,

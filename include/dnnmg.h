@@ -281,6 +281,19 @@ int dnnmg_train_step(dnnmg_net *net, const float *X, const float *D, int T, int 
 int dnnmg_train_step_dev(dnnmg_net *net, const float *X_dev, const float *D_dev, int T, int B,
                          int ckpt, float lr, float *loss);
 
+/* Flow functionals of a state (Sec. 3.3, the accuracy comparison): J_div =
+ * int |div v|^2 dx (2x2 Gauss per cell) and, per obstacle k, drag and lift
+ * -int_{Gamma_k} (nu grad v - p I) n . e_{x,y} ds with n the unit normal into
+ * the obstacle (2-point Gauss per boundary edge of the mesh, grad v and p of
+ * the fluid cell).  FP64.  drag / lift: n_obstacles doubles each (caller-
+ * owned; n_obstacles must equal the macro mesh's curve count, else
+ * DNNMG_EINVAL).  Synchronises the stream. */
+int dnnmg_functionals(dnnmg_ctx *ctx, const dnnmg_state *s, double *jdiv, double *drag, double *lift,
+                      int n_obstacles);
+/* The same for a host state vector (3 N doubles, node-interleaved) on level. */
+int dnnmg_functionals_host(dnnmg_ctx *ctx, int level, const double *uvp, double *jdiv, double *drag,
+                           double *lift, int n_obstacles);
+
 /* ------------------------------------------------------------------ batches
  * Many independent simulations of the plain method (Sec. 2: each one the
  * time step of eqs. nonlinearshort/newton on its own mesh and viscosity),

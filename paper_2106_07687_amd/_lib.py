@@ -110,6 +110,8 @@ _SIGS = {
     "dnnmg_profile_enable": (C.c_int, [_P, C.c_int]),
     "dnnmg_profile_select": (C.c_int, [_P, C.c_char_p]),
     "dnnmg_launch_config": (C.c_int, [_P, C.c_int, _IP]),
+    "dnnmg_functionals": (C.c_int, [_P, _P, _DP, _DP, _DP, C.c_int]),
+    "dnnmg_functionals_host": (C.c_int, [_P, C.c_int, _DP, _DP, _DP, _DP, C.c_int]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
@@ -262,6 +264,15 @@ class Context:
             k, n, ms = line.split()
             out[k] = (int(n), float(ms))
         return out
+
+    def functionals(self, level, uvp, n_obstacles):
+        """(J_div, drag[k], lift[k]) of a host state vector on `level`."""
+        uvp = _f64(uvp)
+        j = np.zeros(1)
+        d, l = np.zeros(max(n_obstacles, 1)), np.zeros(max(n_obstacles, 1))
+        self._check(self.lib.dnnmg_functionals_host(self.h, level, _dp(uvp), _dp(j), _dp(d), _dp(l),
+                                                    n_obstacles))
+        return float(j[0]), d[:n_obstacles], l[:n_obstacles]
 
     def launch_config(self, level):
         """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong,
@@ -451,6 +462,14 @@ class State:
         t = C.c_double()
         self.ctx._check(self.ctx.lib.dnnmg_state_get(self.h, _dp(out), C.byref(t)))
         return out, t.value
+
+    def functionals(self, n_obstacles):
+        """(J_div, drag[k], lift[k]) of the state."""
+        j = np.zeros(1)
+        d, l = np.zeros(max(n_obstacles, 1)), np.zeros(max(n_obstacles, 1))
+        self.ctx._check(self.ctx.lib.dnnmg_functionals(self.ctx.h, self.h, _dp(j), _dp(d), _dp(l),
+                                                       n_obstacles))
+        return float(j[0]), d[:n_obstacles], l[:n_obstacles]
 
     def device_ptr(self):
         p = _P()

@@ -275,6 +275,7 @@ int dnnmg_setup_mesh(dnnmg_ctx *ctx, const dnnmg_coarse_mesh *m, int finest_leve
     std::vector<int> q(m->quad, m->quad + 4 * m->n_cell);
     std::vector<int> be(m->bedge, m->bedge + 3 * m->n_bedge);
     std::vector<double> cv(m->curve, m->curve + 5 * m->n_curve);
+    c.n_curve = m->n_curve;
     c.levels.clear();
     for (int l = 0; l <= finest_level; ++l) {
       auto D = std::make_unique<DevLevel>();
@@ -683,6 +684,35 @@ int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len) {
     }
     if (out.size() + 1 > len) return fail(ctx, DNNMG_EINVAL, "profile buffer too small");
     std::memcpy(buf, out.c_str(), out.size() + 1);
+    return DNNMG_OK;
+  });
+}
+
+int dnnmg_functionals(dnnmg_ctx *ctx, const dnnmg_state *s, double *jdiv, double *drag, double *lift,
+                      int n_obstacles) {
+  if (!ctx || !s || s->impl.ctx != &ctx->impl) return DNNMG_EINVAL;
+  if (n_obstacles != ctx->impl.n_curve || (n_obstacles > 0 && (!drag || !lift)))
+    return fail(ctx, DNNMG_EINVAL, "n_obstacles must equal the mesh's obstacle count");
+  return guarded(ctx, [&]() {
+    ctx->impl.functionals(s->impl.level, s->impl.x.p, jdiv, drag, lift);
+    return DNNMG_OK;
+  });
+}
+
+int dnnmg_functionals_host(dnnmg_ctx *ctx, int level, const double *uvp, double *jdiv, double *drag,
+                           double *lift, int n_obstacles) {
+  const int e = check_level(ctx, level);
+  if (e) return e;
+  if (!uvp) return DNNMG_EINVAL;
+  if (n_obstacles != ctx->impl.n_curve || (n_obstacles > 0 && (!drag || !lift)))
+    return fail(ctx, DNNMG_EINVAL, "n_obstacles must equal the mesh's obstacle count");
+  return guarded(ctx, [&]() {
+    Ctx &c = ctx->impl;
+    const size_t n = 3 * static_cast<size_t>(c.levels[level]->h.N);
+    DevBuf<double> xd;
+    xd.alloc(n);
+    check(hipMemcpyAsync(xd.p, uvp, n * sizeof(double), hipMemcpyHostToDevice, c.stream), "H2D");
+    c.functionals(level, xd.p, jdiv, drag, lift);
     return DNNMG_OK;
   });
 }

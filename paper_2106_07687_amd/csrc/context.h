@@ -107,6 +107,11 @@ struct DevLevel {
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
   DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
   DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)
+  // obstacle boundary edges (cell, side) grouped by obstacle (ptr CSR), built
+  // on the first functional evaluation of the level
+  int n_obst = -1;
+  DevBuf<int> obst_edges, obst_ptr;
+  DevBuf<double> obst_vals;
   // batches: simulation of each node and the chunks of per-simulation
   // reductions (starts/lengths in unknowns, grouped by simulation: seg_ptr)
   int nseg = 1, nchunk = 0;
@@ -261,6 +266,9 @@ class Ctx {
   double norm2_max_seg(int l, const double *x);
   DevBuf<double> seg_partial, seg_out;
   std::vector<double> seg_host;
+  int n_curve = 0;                 // obstacles of the mesh
+  // J_div, drag[k], lift[k] of x on level l (synchronising)
+  void functionals(int l, const double *x, double *jdiv, double *drag, double *lift);
   void residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                 double dt, double *R);
 };

@@ -1257,6 +1257,118 @@ __global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
   }
 }
 
+// --------------------------------------------------------- flow functionals
+// J_div = int |div v|^2 (Sec. 3.3): per cell sum over the 2x2 Gauss points of
+// det J (u_x + v_y)^2, reduced per workgroup in a fixed order into partial[].
+__global__ void __launch_bounds__(256) k_jdiv_partial(LevelView L, const double *__restrict__ x,
+                                                      double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (c < L.C) {
+    const int4 cn = L.cells[c];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4], U[4], V[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double2 p = L.xy[nn[a]];
+      X[a] = p.x;
+      Y[a] = p.y;
+      U[a] = x[3 * nn[a]];
+      V[a] = x[3 * nn[a] + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      double d = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) d += gx[a] * U[a] + gy[a] * V[a];
+      s += det * d * d;
+    }
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Drag and lift contributions of each obstacle edge (Sec. 3.3):
+// -int_e (nu grad v - p I) n . e_{x,y} ds with 2-point Gauss quadrature on the
+// edge, grad v and p of the fluid cell, n its outward normal (into the
+// obstacle).  edges[2 e] = cell, edges[2 e + 1] = local side a (corners a,
+// a + 1 counter-clockwise).  out[2 e] = drag part, out[2 e + 1] = lift part.
+__global__ void k_edge_forces(LevelView L, int ne, const int *__restrict__ edges, const double *__restrict__ x,
+                              double nu_const, double *__restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int c = edges[2 * e], a = edges[2 * e + 1], a1 = (a + 1) & 3;
+  const int4 cn = L.cells[c];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  double X[4], Y[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const double2 p = L.xy[nn[b]];
+    X[b] = p.x;
+    Y[b] = p.y;
+  }
+  const double ex = X[a1] - X[a], ey = Y[a1] - Y[a];
+  const double len = sqrt(ex * ex + ey * ey);
+  const double nx = ey / len, ny = -ex / len;
+  const double nu = L.nnu ? L.nnu[nn[a]] : nu_const;
+  const double g = 0.57735026918962576451;
+  double fx = 0.0, fy = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    const double t = k == 0 ? -g : g;
+    const double xi = 0.5 * (1.0 - t) * kVX[a] + 0.5 * (1.0 + t) * kVX[a1];
+    const double eta = 0.5 * (1.0 - t) * kVY[a] + 0.5 * (1.0 + t) * kVY[a1];
+    double N[4], dxi[4], deta[4], j11 = 0, j12 = 0, j21 = 0, j22 = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      N[b] = 0.25 * (1.0 + kVX[b] * xi) * (1.0 + kVY[b] * eta);
+      dxi[b] = 0.25 * kVX[b] * (1.0 + kVY[b] * eta);
+      deta[b] = 0.25 * kVY[b] * (1.0 + kVX[b] * xi);
+      j11 += dxi[b] * X[b];
+      j12 += deta[b] * X[b];
+      j21 += dxi[b] * Y[b];
+      j22 += deta[b] * Y[b];
+    }
+    const double id = 1.0 / (j11 * j22 - j12 * j21);
+    double ux = 0, uy = 0, vx = 0, vy = 0, p = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double gxb = (j22 * dxi[b] - j21 * deta[b]) * id;
+      const double gyb = (-j12 * dxi[b] + j11 * deta[b]) * id;
+      const double u = x[3 * nn[b]], v = x[3 * nn[b] + 1];
+      ux += gxb * u;
+      uy += gyb * u;
+      vx += gxb * v;
+      vy += gyb * v;
+      p += N[b] * x[3 * nn[b] + 2];
+    }
+    const double w = 0.5 * len;
+    fx -= w * (nu * (ux * nx + uy * ny) - p * nx);
+    fy -= w * (nu * (vx * nx + vy * ny) - p * ny);
+  }
+  out[2 * e] = fx;
+  out[2 * e + 1] = fy;
+}
+
+// out[2 k + f] = sum over the edges of obstacle k (ptr CSR) of vals[2 e + f],
+// in edge order (one thread per obstacle and component).
+__global__ void k_sum_ranges(int nk, const int *__restrict__ ptr, const double *__restrict__ vals,
+                             double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nk) return;
+  const int k = t >> 1, f = t & 1;
+  double s = 0.0;
+  for (int e = ptr[k]; e < ptr[k + 1]; ++e) s += vals[2 * e + f];
+  out[t] = s;
+}
+
 // ---------------------------------------------------- per-simulation BLAS-1
 // Batches: the unknowns of one simulation ("segment") form runs of the node
 // order; runs are cut into chunks (start and length in unknowns) listed

@@ -174,6 +174,64 @@ double Ctx::norm2_max_seg(int l, const double *x) {
   return mx;
 }
 
+void Ctx::functionals(int l, const double *x, double *jdiv, double *drag, double *lift) {
+  DevLevel &L = *levels[l];
+  if (L.n_obst < 0) {   // obstacle edges of this level, grouped by obstacle
+    const HostLevel &h = L.h;
+    std::map<std::pair<int, int>, std::pair<int, int>> side;   // (v0, v1) -> (cell, a)
+    for (int c = 0; c < h.C; ++c)
+      for (int a = 0; a < 4; ++a) {
+        const int v0 = h.cells[4 * c + a], v1 = h.cells[4 * c + (a + 1) % 4];
+        side[{std::min(v0, v1), std::max(v0, v1)}] = {c, a};
+      }
+    std::vector<std::vector<int>> per(n_curve);
+    for (int e = 0; e < h.Eb; ++e) {
+      const int v0 = h.bedges[3 * e], v1 = h.bedges[3 * e + 1], tag = h.bedges[3 * e + 2];
+      if (tag < 4 || tag - 4 >= n_curve) continue;
+      const auto it = side.find({std::min(v0, v1), std::max(v0, v1)});
+      if (it == side.end()) throw DnnmgError{DNNMG_EINVAL, "obstacle edge without a cell"};
+      per[tag - 4].push_back(it->second.first);
+      per[tag - 4].push_back(it->second.second);
+    }
+    std::vector<int> ed, ptr(1, 0);
+    for (auto &v : per) {
+      ed.insert(ed.end(), v.begin(), v.end());
+      ptr.push_back(static_cast<int>(ed.size() / 2));
+    }
+    L.obst_edges.upload(ed, stream);
+    L.obst_ptr.upload(ptr, stream);
+    L.obst_vals.alloc(std::max<size_t>(ed.size(), 2) + 2 * static_cast<size_t>(n_curve) + 2);
+    L.n_obst = n_curve;
+  }
+  const int nb = blocks(L.h.C, 256);
+  if (red_partial.n < static_cast<size_t>(nb)) red_partial.alloc(nb);
+  if (!red_out.p) red_out.alloc(64);
+  ProfScope ps(prof, stream, "functionals", l);
+  hipLaunchKernelGGL(k_jdiv_partial, dim3(nb), dim3(256), 0, stream, L.view(), x, red_partial.p);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, stream, nb, 1, red_partial.p, red_out.p);
+  const int ne = static_cast<int>(L.obst_edges.n / 2);
+  double *vals = L.obst_vals.p, *sums = L.obst_vals.p + 2 * static_cast<size_t>(std::max(ne, 1));
+  if (ne > 0) {
+    hipLaunchKernelGGL(k_edge_forces, dim3(blocks(ne, 256)), dim3(256), 0, stream, L.view(), ne,
+                       L.obst_edges.p, x, prm.nu, vals);
+  }
+  if (n_curve > 0)
+    hipLaunchKernelGGL(k_sum_ranges, dim3(blocks(2 * n_curve, 64)), dim3(64), 0, stream, n_curve, L.obst_ptr.p,
+                       vals, sums);
+  LAUNCH_CHECK("functionals");
+  std::vector<double> h(1 + 2 * static_cast<size_t>(n_curve));
+  check(hipMemcpyAsync(h.data(), red_out.p, sizeof(double), hipMemcpyDeviceToHost, stream), "D2H");
+  if (n_curve > 0)
+    check(hipMemcpyAsync(h.data() + 1, sums, sizeof(double) * 2 * n_curve, hipMemcpyDeviceToHost, stream),
+          "D2H");
+  check(hipStreamSynchronize(stream), "functionals sync");
+  if (jdiv) *jdiv = h[0];
+  for (int k = 0; k < n_curve; ++k) {
+    if (drag) drag[k] = h[1 + 2 * k];
+    if (lift) lift[k] = h[2 + 2 * k];
+  }
+}
+
 void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                    double dt, double *Rout) {
   ensure_lps(l, dt);
