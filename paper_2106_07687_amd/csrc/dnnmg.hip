@@ -124,6 +124,11 @@ void net_repack(Net &n) {
                        n.w32.p + n.off_ih[l], kl, n.wih_b[l].p);
     hipLaunchKernelGGL(k_pack_bf16, dim3(blocks(rows * n.H, 256)), dim3(256), 0, s, static_cast<int>(rows),
                        n.H, n.w32.p + n.off_hh[l], n.H, n.whh_b[l].p);
+    hipLaunchKernelGGL(k_pack_bf16_t, dim3(blocks(rows * n.H, 256)), dim3(256), 0, s, static_cast<int>(rows), n.H,
+                       n.w32.p + n.off_hh[l], n.whh_t[l].p);
+    if (l > 0)
+      hipLaunchKernelGGL(k_pack_bf16_t, dim3(blocks(rows * n.H, 256)), dim3(256), 0, s, static_cast<int>(rows),
+                         n.H, n.w32.p + n.off_ih[l], n.wih_t[l].p);
   }
   hipLaunchKernelGGL(k_pack_bf16, dim3(blocks(static_cast<size_t>(n.O) * n.H, 256)), dim3(256), 0, s, n.O,
                      n.H, n.w32.p + n.off_out, n.H, n.wout_b.p);
@@ -151,7 +156,7 @@ void net_forward(Net &n) {
     }
     ProfScope ps(n.ctx->prof, s, ("gru_gates" + lay).c_str(), n.F);
     hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(n.B) * n.H, 256)), dim3(256), 0, s, n.B,
-                       n.H, n.Gi.p, n.Gh.p, n.h[l].p, n.hb[l].p, n.H, nullptr);
+                       n.H, n.Gi.p, n.Gh.p, n.h[l].p, n.h[l].p, n.hb[l].p, n.H, nullptr);
     check(hipGetLastError(), "k_gru_gates");
   }
   ProfScope ps(n.ctx->prof, s, "gru_head", n.F);
@@ -307,11 +312,15 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
     hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, c.stream, n.w32.p, n.w32.n, 0.0f);
     n.wih_b.resize(layers);
     n.whh_b.resize(layers);
+    n.whh_t.resize(layers);
+    n.wih_t.resize(layers);
     n.h.resize(layers);
     n.hb.resize(layers);
     for (int l = 0; l < layers; ++l) {
       n.wih_b[l].alloc(3 * static_cast<size_t>(n.H) * (l == 0 ? n.K0 : n.H));
       n.whh_b[l].alloc(3 * static_cast<size_t>(n.H) * n.H);
+      n.whh_t[l].alloc(3 * static_cast<size_t>(n.H) * n.H);
+      if (l > 0) n.wih_t[l].alloc(3 * static_cast<size_t>(n.H) * n.H);
       n.h[l].alloc(static_cast<size_t>(n.B) * n.H);
       n.hb[l].alloc(static_cast<size_t>(n.B) * n.H);
     }

@@ -28,6 +28,7 @@ struct Net {
   long long off_out = 0;
   DevBuf<float> w32;                           // FP32 master weights (flat)
   std::vector<DevBuf<uint16_t>> wih_b, whh_b;  // BF16 working copies
+  std::vector<DevBuf<uint16_t>> whh_t, wih_t;  // transposed BF16 copies (H x 3H), for the backward GEMMs
   DevBuf<uint16_t> wout_b;
   DevBuf<float> mu, sg, oscale;
   std::vector<DevBuf<float>> h;                // [B x H] per layer

@@ -105,9 +105,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const
 
 // GRU gate update for one layer (gate rows r, z, n):
 // r = s(gi_r + gh_r), z = s(gi_z + gh_z), n = tanh(gi_n + r gh_n),
-// h = (1 - z) n + z h.  Optionally stores r, z, n, gh_n for the backward pass.
+// h_out = (1 - z) n + z h_in (h_out may be h_in).  Optionally stores r, z, n,
+// gh_n for the backward pass.
 __global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const float *__restrict__ Gh,
-                            float *__restrict__ h, uint16_t *__restrict__ hb, int ldhb,
+                            const float *hin, float *h, uint16_t *__restrict__ hb, int ldhb,
                             float *__restrict__ save) {
   const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<size_t>(B) * H) return;
@@ -117,7 +118,7 @@ __global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const fl
   const float r = sigmoidf_(gi[j] + gh[j]);
   const float z = sigmoidf_(gi[H + j] + gh[H + j]);
   const float n = tanhf(gi[2 * H + j] + r * gh[2 * H + j]);
-  const float hp = h[t];
+  const float hp = hin[t];
   const float hn = (1.0f - z) * n + z * hp;
   h[t] = hn;
   hb[static_cast<size_t>(b) * ldhb + j] = f2bf(hn);
@@ -308,9 +309,10 @@ __global__ void k_reduce_split(int M, int N, int ld, int Z, long zstride, const 
 // (r, z, n, gh_n) and h_{t-1}.  Out: dgi = dL/d(W_ih x) (3H), dgh =
 // dL/d(W_hh h_{t-1}) (3H) as FP32 and BF16, dhp = g * z (the direct part of
 // dL/dh_{t-1}; the GEMM dgh W_hh is added to it afterwards).
-__global__ void k_gru_gates_bwd(int B, int H, const float *__restrict__ g, const float *__restrict__ save,
+// g: dL/dh_t in; dhp: the z-path of dL/dh_{t-1} out (elementwise, may be g).
+__global__ void k_gru_gates_bwd(int B, int H, const float *g, const float *__restrict__ save,
                                 const float *__restrict__ hprev, uint16_t *__restrict__ dgi_b,
-                                uint16_t *__restrict__ dgh_b, float *__restrict__ dhp) {
+                                uint16_t *__restrict__ dgh_b, float *dhp) {
   const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<size_t>(B) * H) return;
   const int b = static_cast<int>(t / H), j = static_cast<int>(t % H);
@@ -387,6 +389,14 @@ __global__ void k_f32_to_bf16(size_t n, const float *__restrict__ a, uint16_t *_
 
 // Copy of a row-major [rows x cols] FP32 matrix into a BF16 matrix with
 // leading dimension ld >= cols (padding columns zero).
+// b (cols x rows) = BF16 of the transpose of a (rows x cols, row-major).
+__global__ void k_pack_bf16_t(int rows, int cols, const float *__restrict__ a, uint16_t *__restrict__ b) {
+  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<size_t>(rows) * cols) return;
+  const int c = static_cast<int>(t / rows), r = static_cast<int>(t % rows);
+  b[t] = f2bf(a[static_cast<size_t>(r) * cols + c]);
+}
+
 __global__ void k_pack_bf16(int rows, int cols, const float *__restrict__ a, int ld,
                             uint16_t *__restrict__ b) {
   const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;

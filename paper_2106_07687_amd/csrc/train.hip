@@ -12,9 +12,9 @@ using namespace dnnmg;
 namespace {
 
 void gemm_nt(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
-             float *C, int ldc) {
+             float *C, int ldc, bool acc = false) {
   dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
-  hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0);
+  hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, acc ? 1 : 0);
   check(hipGetLastError(), "k_gemm_nt_bf16");
 }
 
@@ -86,15 +86,15 @@ void ensure(Net &n, Trainer &tr, int T, int Bt, int seg) {
   tr.Yseg.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.dYb.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.grad.alloc(static_cast<size_t>(n.nparam));
-  tr.lpart.alloc(1024);
+  tr.lpart.alloc(static_cast<size_t>(T) * 1024);
 }
 
-// One forward GRU step for all layers.  hin32/hin16: state before the step
-// (per layer), hout32/hout16: state after (may alias hin for in-place);
+// One forward GRU step for all layers.  h32_in/h16_in: state before the step
+// (per layer), h32/h16_out: state after (may alias the inputs: in place);
 // save: gate storage per layer (or null); Y: head output (or null).
-void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector<float *> &h32,
-              std::vector<uint16_t *> &h16_in, std::vector<uint16_t *> &h16_out, std::vector<float *> &save,
-              float *Y) {
+void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector<float *> &h32_in,
+              std::vector<float *> &h32, std::vector<uint16_t *> &h16_in, std::vector<uint16_t *> &h16_out,
+              std::vector<float *> &save, float *Y) {
   const int H3 = 3 * n.H;
   for (int l = 0; l < n.layers; ++l) {
     const uint16_t *in = l == 0 ? x : h16_out[l - 1];
@@ -102,7 +102,7 @@ void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector
     gemm_nt(s, tr.Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
     gemm_nt(s, tr.Bt, H3, n.H, h16_in[l], n.H, n.whh_b[l].p, n.H, tr.Gh.p, H3);
     hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(tr.Bt) * n.H, 256)), dim3(256), 0, s, tr.Bt,
-                       n.H, tr.Gi.p, tr.Gh.p, h32[l], h16_out[l], n.H, save[l]);
+                       n.H, tr.Gi.p, tr.Gh.p, h32_in[l], h32[l], h16_out[l], n.H, save[l]);
   }
   if (Y) gemm_nt(s, tr.Bt, n.O, n.H, h16_out[n.layers - 1], n.H, n.wout_b.p, n.H, Y, n.O);
   check(hipGetLastError(), "fwd_step");
@@ -132,7 +132,7 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
         check(hipMemcpyAsync(tr.hck[l].p + static_cast<size_t>(t / seg) * bh, h32[l], bh * sizeof(float),
                              hipMemcpyDeviceToDevice, s),
               "checkpoint");
-    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h16, h16, sv_null, nullptr);
+    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h32, h16, h16, sv_null, nullptr);
   }
   for (int l = 0; l < L; ++l)
     hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.dh[l].p, bh, 0.0f);
@@ -149,30 +149,26 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
       hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks(bh, 256)), dim3(256), 0, s, bh, tr.hs32[l].p, tr.hs16[l].p);
     }
     for (int k = 0; k < ns; ++k) {
-      std::vector<float *> hk(L), svk(L);
+      std::vector<float *> hk_in(L), hk(L), svk(L);
       std::vector<uint16_t *> hin(L), hout(L);
       for (int l = 0; l < L; ++l) {
-        check(hipMemcpyAsync(tr.hs32[l].p + (k + 1) * bh, tr.hs32[l].p + k * bh, bh * sizeof(float),
-                             hipMemcpyDeviceToDevice, s),
-              "state copy");
+        hk_in[l] = tr.hs32[l].p + k * bh;
         hk[l] = tr.hs32[l].p + (k + 1) * bh;
         hin[l] = tr.hs16[l].p + k * bh;
         hout[l] = tr.hs16[l].p + (k + 1) * bh;
         svk[l] = tr.sv[l].p + static_cast<size_t>(k) * 4 * bh;
       }
-      fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t0 + k) * Bt * n.K0, hk, hin, hout, svk,
+      fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t0 + k) * Bt * n.K0, hk_in, hk, hin, hout, svk,
                tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O);
     }
     // backward through the segment
     for (int k = ns - 1; k >= 0; --k) {
       const int t = t0 + k;
       uint16_t *dY = tr.dYb.p + static_cast<size_t>(k) * Bt * n.O;
+      // per-block loss partials of step t stay on the device until the end
       hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, s, Bt, n.O,
                          tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O, D + static_cast<size_t>(t) * Bt * n.O, dY,
-                         tr.lpart.p);
-      check(hipMemcpyAsync(lp.data(), tr.lpart.p, sizeof(double) * lblocks, hipMemcpyDeviceToHost, s), "loss");
-      check(hipStreamSynchronize(s), "loss sync");
-      for (int b = 0; b < lblocks; ++b) loss += lp[b];
+                         tr.lpart.p + static_cast<size_t>(t) * lblocks);
       // dh_top += dY W_out
       gemm_strided(s, Bt, H, n.O, dY, n.O, 1, n.wout_b.p, 1, H, tr.dh[L - 1].p, H, true, tr.part);
       for (int l = L - 1; l >= 0; --l) {
@@ -180,12 +176,18 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
         uint16_t *dgh = tr.dgh[l].p + static_cast<size_t>(k) * 3 * bh;
         hipLaunchKernelGGL(k_gru_gates_bwd, dim3(blocks(bh, 256)), dim3(256), 0, s, Bt, H, tr.dh[l].p,
                            tr.sv[l].p + static_cast<size_t>(k) * 4 * bh, tr.hs32[l].p + k * bh, dgi, dgh,
-                           tr.dhp.p);
-        check(hipMemcpyAsync(tr.dh[l].p, tr.dhp.p, bh * sizeof(float), hipMemcpyDeviceToDevice, s), "dh");
-        // dh_{t-1} = g z + dgh W_hh
-        gemm_strided(s, Bt, H, 3 * H, dgh, 3 * H, 1, n.whh_b[l].p, 1, H, tr.dh[l].p, H, true, tr.part);
-        if (l > 0)   // gradient into the layer below: dgi W_ih
-          gemm_strided(s, Bt, H, 3 * H, dgi, 3 * H, 1, n.wih_b[l].p, 1, H, tr.dh[l - 1].p, H, true, tr.part);
+                           tr.dh[l].p);
+        // dh_{t-1} = g z + dgh W_hh; gradient into the layer below: dgi W_ih.
+        // With the transposed BF16 weights these are NT products (K = 3H,
+        // a multiple of the 32-wide K tile when H is).
+        if (H % 32 == 0) {
+          gemm_nt(s, Bt, H, 3 * H, dgh, 3 * H, n.whh_t[l].p, 3 * H, tr.dh[l].p, H, true);
+          if (l > 0) gemm_nt(s, Bt, H, 3 * H, dgi, 3 * H, n.wih_t[l].p, 3 * H, tr.dh[l - 1].p, H, true);
+        } else {
+          gemm_strided(s, Bt, H, 3 * H, dgh, 3 * H, 1, n.whh_b[l].p, 1, H, tr.dh[l].p, H, true, tr.part);
+          if (l > 0)
+            gemm_strided(s, Bt, H, 3 * H, dgi, 3 * H, 1, n.wih_b[l].p, 1, H, tr.dh[l - 1].p, H, true, tr.part);
+        }
       }
     }
     // weight gradients of the segment: K = ns * Bt rows at once
@@ -200,6 +202,12 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
       gemm_strided(s, 3 * H, H, Ks, tr.dgh[l].p, 1, 3 * H, tr.hs16[l].p, 1, H, g + n.off_hh[l], H, true, tr.part);
     }
   }
+  // loss: the per-step partials, summed in the order of the backward sweep
+  lp.resize(static_cast<size_t>(T) * lblocks);
+  check(hipMemcpyAsync(lp.data(), tr.lpart.p, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, s), "loss");
+  check(hipStreamSynchronize(s), "loss sync");
+  for (int t = T - 1; t >= 0; --t)
+    for (int b = 0; b < lblocks; ++b) loss += lp[static_cast<size_t>(t) * lblocks + b];
   return loss / Bt;
 }
 
