@@ -150,6 +150,14 @@ void net_forward(Net &n) {
       ProfScope ps(n.ctx->prof, s, ("gru_gemm_in" + lay).c_str(), n.F);
       gemm(s, n.B, H3, K, in, K, n.wih_b[l].p, K, n.Gi.p, H3, false);
     }
+    if (n.H % 32 == 0) {   // recurrent product and gate update in one kernel
+      ProfScope ps(n.ctx->prof, s, ("gru_step" + lay).c_str(), n.F);
+      hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(n.B, 64)), dim3(256), 0, s, n.B, n.H, n.Gi.p,
+                         n.hb[l].p, n.h[l].p, n.whh_b[l].p, n.h[l].p, n.hb_next[l].p, nullptr);
+      check(hipGetLastError(), "k_gru_step_fused");
+      std::swap(n.hb[l], n.hb_next[l]);
+      continue;
+    }
     {
       ProfScope ps(n.ctx->prof, s, ("gru_gemm_hh" + lay).c_str(), n.F);
       gemm(s, n.B, H3, n.H, n.hb[l].p, n.H, n.whh_b[l].p, n.H, n.Gh.p, H3, false);
@@ -316,6 +324,7 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
     n.wih_t.resize(layers);
     n.h.resize(layers);
     n.hb.resize(layers);
+    n.hb_next.resize(layers);
     for (int l = 0; l < layers; ++l) {
       n.wih_b[l].alloc(3 * static_cast<size_t>(n.H) * (l == 0 ? n.K0 : n.H));
       n.whh_b[l].alloc(3 * static_cast<size_t>(n.H) * n.H);
@@ -323,6 +332,7 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
       if (l > 0) n.wih_t[l].alloc(3 * static_cast<size_t>(n.H) * n.H);
       n.h[l].alloc(static_cast<size_t>(n.B) * n.H);
       n.hb[l].alloc(static_cast<size_t>(n.B) * n.H);
+      n.hb_next[l].alloc(static_cast<size_t>(n.B) * n.H);
     }
     n.wout_b.alloc(static_cast<size_t>(n.O) * n.H);
     n.mu.alloc(10);

@@ -32,7 +32,7 @@ struct Net {
   DevBuf<uint16_t> wout_b;
   DevBuf<float> mu, sg, oscale;
   std::vector<DevBuf<float>> h;                // [B x H] per layer
-  std::vector<DevBuf<uint16_t>> hb;
+  std::vector<DevBuf<uint16_t>> hb, hb_next;   // BF16 state; the fused step writes hb_next, then they swap
   DevBuf<uint16_t> X;
   DevBuf<float> Xf, Gi, Gh, Y;
   // fine-level vectors (FP64)

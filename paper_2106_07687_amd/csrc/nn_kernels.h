@@ -131,6 +131,92 @@ __global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const fl
   }
 }
 
+// Recurrent product fused with the gate update: Gh = h_in W_hh^T for a tile of
+// 64 rows x 32 hidden units and all three gates (MFMA 16x16x16 BF16, the K
+// loop in 32-wide chunks as in k_gemm_nt_bf16, so the accumulators hold the
+// values that kernel would store), then the gate update of k_gru_gates on the
+// accumulators: bitwise the pair k_gemm_nt_bf16 + k_gru_gates without the
+// FP32 Gh round trip.  Wave w owns rows 16w..16w+15 of the tile, both
+// 16-unit halves and the three gates, so each lane holds r, z, n inputs of
+// the same (row, unit).  H must be a multiple of 32.
+__global__ void __launch_bounds__(256) k_gru_step_fused(int B, int H, const float *__restrict__ Gi,
+                                                        const uint16_t *__restrict__ hb_in,
+                                                        const float *hin, const uint16_t *__restrict__ Whh,
+                                                        float *h, uint16_t *__restrict__ hb_out,
+                                                        float *__restrict__ save) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[96][GBK + GPAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.y * 64, u0 = blockIdx.x * 32;
+  f32x4 acc[3][2];
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[g][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < H; k0 += GBK) {
+    // loaders: 64 A rows x 4 chunks of 8; 96 B rows x 4 chunks (threads 0..383 -> two passes)
+    uint4 va = make_uint4(0, 0, 0, 0), vb0 = make_uint4(0, 0, 0, 0), vb1 = make_uint4(0, 0, 0, 0);
+    const int lr = tid >> 2, lc = (tid & 3) * 8;
+    if (r0 + lr < B) va = *reinterpret_cast<const uint4 *>(hb_in + static_cast<size_t>(r0 + lr) * H + k0 + lc);
+    {   // B rows 0..63 of the tile: gate lr / 32, unit lr % 32
+      const int g = lr >> 5, u = lr & 31;
+      if (u0 + u < H) vb0 = *reinterpret_cast<const uint4 *>(Whh + static_cast<size_t>(g * H + u0 + u) * H + k0 + lc);
+    }
+    if (lr < 32) {   // B rows 64..95: gate 2
+      const int u = lr;
+      if (u0 + u < H) vb1 = *reinterpret_cast<const uint4 *>(Whh + static_cast<size_t>(2 * H + u0 + u) * H + k0 + lc);
+    }
+    __syncthreads();
+    *reinterpret_cast<uint4 *>(&As[lr][lc]) = va;
+    *reinterpret_cast<uint4 *>(&Bs[lr][lc]) = vb0;
+    if (lr < 32) *reinterpret_cast<uint4 *>(&Bs[64 + lr][lc]) = vb1;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
+      const uint16_t *pa = &As[wave * 16 + (lane & 15)][kq];
+      const bf16x4 a = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
+                              static_cast<short>(pa[3])};
+#pragma unroll
+      for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const uint16_t *pb = &Bs[g * 32 + j * 16 + (lane & 15)][kq];
+          const bf16x4 b = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]),
+                                  static_cast<short>(pb[2]), static_cast<short>(pb[3])};
+          acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[g][j], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int unit = u0 + j * 16 + (lane & 15);
+    if (unit >= H) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = r0 + wave * 16 + 4 * (lane >> 4) + i;
+      if (row >= B) continue;
+      const float *gi = Gi + static_cast<size_t>(row) * 3 * H;
+      const float ghr = acc[0][j][i], ghz = acc[1][j][i], ghn = acc[2][j][i];
+      const float r = sigmoidf_(gi[unit] + ghr);
+      const float z = sigmoidf_(gi[H + unit] + ghz);
+      const float n = tanhf(gi[2 * H + unit] + r * ghn);
+      const size_t t = static_cast<size_t>(row) * H + unit;
+      const float hp = hin[t];
+      const float hn = (1.0f - z) * n + z * hp;
+      h[t] = hn;
+      hb_out[t] = f2bf(hn);
+      if (save) {
+        float *s = save + static_cast<size_t>(row) * 4 * H;
+        s[unit] = r;
+        s[H + unit] = z;
+        s[2 * H + unit] = n;
+        s[3 * H + unit] = ghn;
+      }
+    }
+  }
+}
+
 // Patch gather (Algorithm 1, the network inputs): one workgroup per patch writes the
 // standardised input row [u, v, p, r_u, r_v, r_p at the S2 patch nodes;
 // aspect, skew, h_rel, Peclet] as BF16 into X (ld = ldx, padding zeroed).

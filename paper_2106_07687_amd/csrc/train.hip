@@ -100,6 +100,11 @@ void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector
     const uint16_t *in = l == 0 ? x : h16_out[l - 1];
     const int K = l == 0 ? n.K0 : n.H;
     gemm_nt(s, tr.Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
+    if (n.H % 32 == 0 && h16_in[l] != h16_out[l]) {   // recurrent product + gates fused
+      hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(tr.Bt, 64)), dim3(256), 0, s, tr.Bt, n.H, tr.Gi.p,
+                         h16_in[l], h32_in[l], n.whh_b[l].p, h32[l], h16_out[l], save[l]);
+      continue;
+    }
     gemm_nt(s, tr.Bt, H3, n.H, h16_in[l], n.H, n.whh_b[l].p, n.H, tr.Gh.p, H3);
     hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(tr.Bt) * n.H, 256)), dim3(256), 0, s, tr.Bt,
                        n.H, tr.Gi.p, tr.Gh.p, h32_in[l], h32[l], h16_out[l], n.H, save[l]);
@@ -126,13 +131,16 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
     hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, h32[l], bh, 0.0f);
     hipLaunchKernelGGL(k_fill<uint16_t>, dim3(1024), dim3(256), 0, s, h16[l], bh, uint16_t(0));
   }
+  std::vector<uint16_t *> h16b(L);   // BF16 state alternates between slots 0 and 1
+  for (int l = 0; l < L; ++l) h16b[l] = tr.hs16[l].p + bh;
   for (int t = 0; t < T; ++t) {
     if (t % seg == 0)
       for (int l = 0; l < L; ++l)
         check(hipMemcpyAsync(tr.hck[l].p + static_cast<size_t>(t / seg) * bh, h32[l], bh * sizeof(float),
                              hipMemcpyDeviceToDevice, s),
               "checkpoint");
-    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h32, h16, h16, sv_null, nullptr);
+    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h32, h16, h16b, sv_null, nullptr);
+    std::swap(h16, h16b);
   }
   for (int l = 0; l < L; ++l)
     hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.dh[l].p, bh, 0.0f);
