@@ -323,6 +323,9 @@ def main():
                          "directly (no graphs; events add launch overhead to the timings)")
     ap.add_argument("--newton-predictor", type=int, default=1, choices=(0, 1),
                     help="1: Newton starts from the linear extrapolation of the last two states")
+    ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
+                    help="keep Newton's Jacobians across iterations and steps while the "
+                         "residual contracts by 0.1 or better (0: rebuild every step)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured graphs")
     ap.add_argument("--batch-sims", type=int, default=64,
@@ -353,7 +356,8 @@ def main():
         del src, dst
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
-                    use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor)
+                    use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
+                    jacobian_reuse=args.jacobian_reuse)
     F = args.level
     if args.profile == "all":
         gmg_keys = dnn_keys = None
@@ -526,11 +530,15 @@ def main():
                    "gmg_dof_updates_per_s": round(3 * nF * args.steps / g_sec, 1),
                    "gmg_newton_iters": sum(s_["newton_iters"] for s_ in g_stats),
                    "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
+                   "gmg_jacobian_builds": sum(s_["jacobian_builds"] for s_ in g_stats),
                    "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
+                   "dnnmg_gmres_iters": sum(s_["gmres_iters"] for s_ in d_stats),
+                   "dnnmg_jacobian_builds": sum(s_["jacobian_builds"] for s_ in d_stats),
                    "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats),
                    "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
-                   "newton_predictor": args.newton_predictor},
+                   "newton_predictor": args.newton_predictor,
+                   "jacobian_reuse": args.jacobian_reuse},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

@@ -89,6 +89,19 @@ typedef struct {
                              extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
                              x_{n-2}) once a state has taken a step (the
                              converged x_n is the same to the tolerance)      */
+  int jacobian_reuse;     /* 0: every step rebuilds the multigrid hierarchy at
+                             its first Newton iterate and re-assembles the
+                             finest Jacobian at later ones; 1: Newton keeps the
+                             Jacobians, Vanka inverses and level-0 inverse it
+                             last built for the same state, level and time step
+                             (across iterations and steps) while the residual
+                             contracts by reuse_contraction or better per
+                             iteration, and rebuilds everything at the current
+                             iterate otherwise; a step that fails with a kept
+                             hierarchy is redone with fresh ones (the converged
+                             x_n is the same to the tolerance)               */
+  double reuse_contraction; /* largest ||R_k|| / ||R_{k-1}|| that keeps a
+                             Jacobian, in (0, 1); default 0.1                 */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 
@@ -116,6 +129,8 @@ typedef struct {
   double res_final;       /* ||R|| at the returned state                        */
   int converged;          /* 1 if ||R|| <= newton_tol                           */
   int fallback;           /* DNN-MG: 1 if the correction was switched off       */
+  int jacobian_builds;    /* multigrid hierarchies (all levels' Jacobians,
+                             Vanka and level-0 inverses) built in this step  */
 } dnnmg_step_stats;
 
 typedef struct {

@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int), ("gmres_max", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vanka_omega", C.c_double),
                 ("precision", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
-                ("newton_predictor", C.c_int),
+                ("newton_predictor", C.c_int), ("jacobian_reuse", C.c_int),
+                ("reuse_contraction", C.c_double),
                 ("stream", C.c_void_p)]
 
 
@@ -52,7 +53,8 @@ class SimDesc(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int), ("gmres_iters", C.c_int),
                 ("gmres_iters_max", C.c_int), ("res_initial", C.c_double),
-                ("res_final", C.c_double), ("converged", C.c_int), ("fallback", C.c_int)]
+                ("res_final", C.c_double), ("converged", C.c_int), ("fallback", C.c_int),
+                ("jacobian_builds", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -178,9 +180,16 @@ def _params(precision, kw):
     p = Params()
     lib.dnnmg_params_default(C.byref(p))
     p.precision = precision
-    for k, v in kw.items():
-        setattr(p, k, v)
+    _set_fields(p, kw)
     return p
+
+
+def _set_fields(p, kw):
+    names = {k for k, _ in p._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver parameter {k!r}")
+        setattr(p, k, v)
 
 
 class Context:
@@ -191,8 +200,7 @@ class Context:
         p = Params()
         self.lib.dnnmg_params_default(C.byref(p))
         p.precision = precision
-        for k, v in kw.items():
-            setattr(p, k, v)
+        _set_fields(p, kw)
         if stream is not None:
             p.stream = stream
         self.params = p
@@ -218,8 +226,7 @@ class Context:
             pass
 
     def set_params(self, **kw):
-        for k, v in kw.items():
-            setattr(self.params, k, v)
+        _set_fields(self.params, kw)
         self._check(self.lib.dnnmg_set_params(self.h, C.byref(self.params)))
 
     def setup_mesh(self, macro, finest_level):

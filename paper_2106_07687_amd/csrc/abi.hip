@@ -39,7 +39,9 @@ bool params_ok(const dnnmg_params *p) {
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
-         (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1);
+         (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1) &&
+         (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && p->reuse_contraction > 0 &&
+         p->reuse_contraction < 1;
 }
 
 void upload_level(DevLevel &D, hipStream_t s) {
@@ -97,13 +99,19 @@ int step_impl(Ctx &c, State &st, double dt, dnnmg_step_stats *stats) {
   bool ok = false;
   OpLevel<T> &o = S.op(l);
   bool use_pending = st.has_pending;
+  const bool reuse = c.prm.jacobian_reuse != 0;
+  bool fresh_only = !reuse;   // set when an attempt with kept Jacobians failed
   if (c.prm.newton_predictor && st.has_prev && st.dt_prev > 0.0) {
     // Newton starts from x_{n-1} + (k_n / k_{n-1}) (x_{n-1} - x_{n-2})
     hipLaunchKernelGGL(k_extrapolate, dim3(blocks(n, 256)), dim3(256), 0, s, n, dt / st.dt_prev, st.xprev.p,
                        st.x.p);
     check(hipGetLastError(), "predictor");
   }
+  bool kept_used;   // this attempt iterated with a hierarchy built before its first iterate
+  double nr_prev;
 retry:
+  kept_used = false;
+  nr_prev = 0.0;
   hipLaunchKernelGGL(k_impose_bc, dim3(blocks(N, 256)), dim3(256), 0, s, c.levels[l]->view(),
                      c.phys(dt, t_new), st.x.p);
   for (int it = 0; it <= c.prm.newton_max; ++it) {
@@ -118,10 +126,23 @@ retry:
       ok = true;
       break;
     }
+    if (it > 0) st.reuse_ok = nr <= c.prm.reuse_contraction * nr_prev;
+    nr_prev = nr;
     if (it == c.prm.newton_max) break;
-    // the multigrid preconditioner is refreshed at the first Newton iteration
-    // of a step; later iterations re-assemble only the finest Jacobian
-    S.linearize(st.x.p, l, dt, it == 0);
+    if (fresh_only) {
+      // the multigrid preconditioner is refreshed at the first Newton
+      // iteration of a step; later iterations re-assemble only the finest
+      // Jacobian
+      S.linearize(st.x.p, l, dt, it == 0);
+      if (it == 0) ++loc.jacobian_builds;
+    } else if (S.jacobian_kept(st.key, l, dt) && st.reuse_ok) {
+      kept_used = true;   // chord iteration with the kept hierarchy
+    } else {
+      S.linearize(st.x.p, l, dt, true);
+      S.keep_jacobian(st.key, l, dt);
+      st.reuse_ok = true;
+      ++loc.jacobian_builds;
+    }
     hipLaunchKernelGGL((k_convert<double, T>), dim3(blocks(n, 256)), dim3(256), 0, s, n, c.R.p, o.b.p);
     double r0, r1;
     const int k = S.gmres(l, o.b.p, o.x.p, c.prm.gmres_rtol, c.prm.gmres_restart, c.prm.gmres_max,
@@ -130,6 +151,17 @@ retry:
     loc.gmres_iters_max = std::max(loc.gmres_iters_max, k);
     hipLaunchKernelGGL(k_add_to_f64<T>, dim3(blocks(n, 256)), dim3(256), 0, s, n, o.x.p, st.x.p);
     check(hipGetLastError(), "newton update");
+  }
+  if (!ok && kept_used) {
+    // the kept Jacobians did not carry Newton to the tolerance: redo the step
+    // from x_{n-1} with a fresh hierarchy at every step's first iterate
+    check(hipMemcpyAsync(st.x.p, c.xo_save.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s),
+          "reuse restore");
+    S.forget_jacobian();
+    st.reuse_ok = false;
+    fresh_only = true;
+    loc.gmres_iters_max = 0;
+    goto retry;
   }
   if (!ok && use_pending) {
     // switch-off of the network for this step (Sec. 3.3): redo the step with
@@ -214,6 +246,8 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->use_graphs = 1;
   p->autotune = 1;
   p->newton_predictor = 1;
+  p->jacobian_reuse = 0;
+  p->reuse_contraction = 0.1;
   p->stream = nullptr;
   return DNNMG_OK;
 }
@@ -248,6 +282,7 @@ int dnnmg_set_params(dnnmg_ctx *ctx, const dnnmg_params *p) {
   ctx->impl.prm.precision = prec;
   ctx->impl.stream = static_cast<hipStream_t>(p->stream);
   ++ctx->impl.graph_gen;   // captured graphs hold the old Vanka damping and sweep counts
+  ctx->impl.forget_jacobians();   // viscosity or stabilisation may have changed
   return DNNMG_OK;
 }
 
@@ -392,6 +427,7 @@ int dnnmg_state_create(dnnmg_ctx *ctx, int level, dnnmg_state **out) {
     auto *s = new dnnmg_state();
     s->impl.ctx = &ctx->impl;
     s->impl.level = level;
+    s->impl.key = ++ctx->impl.state_keys;
     const size_t n = 3 * static_cast<size_t>(ctx->impl.levels[level]->h.N);
     try {
       s->impl.x.alloc(n);
@@ -426,6 +462,8 @@ int dnnmg_state_set(dnnmg_state *s, const double *uvp, double t) {
     s->impl.t = t;
     s->impl.has_pending = false;
     s->impl.has_prev = false;
+    s->impl.key = ++c.state_keys;   // a Jacobian built from the old values is not reused
+    s->impl.reuse_ok = false;
     return DNNMG_OK;
   });
 }

@@ -143,6 +143,18 @@ class Solver {
   // J on `level` (and, if full, on all coarser levels with the Vanka inverses
   // and the level-0 inverse: the multigrid preconditioner)
   void linearize(const double *x_dev, int level, double dt, bool full = true);
+  // Jacobian reuse: after linearize(.., full = true) from state `key` the
+  // hierarchy is marked as kept for (key, level, dt); any other linearize
+  // or forget_jacobian() drops the mark
+  void keep_jacobian(unsigned long long key, int level, double dt) {
+    kept_key_ = key;
+    kept_level_ = level;
+    kept_dt_ = dt;
+  }
+  bool jacobian_kept(unsigned long long key, int level, double dt) const {
+    return key != 0 && kept_key_ == key && kept_level_ == level && kept_dt_ == dt;
+  }
+  void forget_jacobian() { kept_key_ = 0; }
   void vanka_sweep(int l, T *x, const T *b, bool zero_start);
   void vcycle(int l, const T *b, T *x);                         // x = V(b), zero start
   int gmres(int level, const T *b, T *x, double rtol, int restart, int maxit, double *res0,
@@ -173,6 +185,9 @@ class Solver {
  private:
   Ctx *ctx_;
   int lin_level_ = -1;
+  unsigned long long kept_key_ = 0;
+  int kept_level_ = -1;
+  double kept_dt_ = 0.0;
   int small_top_ = 0;
   SmallCycle<T> small_params(int top, const T *b, T *x);
   void launch_small(int top, const T *b, T *x);
@@ -233,6 +248,7 @@ class Ctx {
   std::string last_error;
   Profiler prof;
   long graph_gen = 0;              // bumped when captured graphs go stale
+  unsigned long long state_keys = 0;   // last key handed to a state (Jacobian reuse)
   // simulation batches (empty otherwise): macro cell -> simulation, its
   // viscosity, and level-0 node -> simulation (the coarse solve's blocks)
   std::vector<int> macro_blk;
@@ -245,6 +261,10 @@ class Ctx {
   int finest = -1;
   std::unique_ptr<Solver<float>> s32;
   std::unique_ptr<Solver<double>> s64;
+  void forget_jacobians() {
+    if (s32) s32->forget_jacobian();
+    if (s64) s64->forget_jacobian();
+  }
   // FP64 scratch for residual evaluation / Newton on the finest used level
   DevBuf<double> R, xo_save, tmp64a, tmp64b;
   DevBuf<double> red_partial, red_out;
@@ -283,6 +303,8 @@ struct State {
   DevBuf<double> xprev;         // state before the last step (Newton predictor)
   bool has_prev = false;
   double dt_prev = 0.0;
+  unsigned long long key = 0;   // identifies the values a kept Jacobian was built from
+  bool reuse_ok = false;        // the last Newton iteration contracted well enough to keep J
 };
 
 inline int blocks(size_t n, int bs) { return static_cast<int>((n + bs - 1) / bs); }

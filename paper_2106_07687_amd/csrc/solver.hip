@@ -492,6 +492,7 @@ void Solver<T>::autotune() {
 template <typename T>
 void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) {
   hipStream_t s = ctx_->stream;
+  kept_key_ = 0;
   if (lin_level_ < level) full = true;   // never factorised at this depth
   for (int l = full ? 0 : level; l <= level; ++l) {
     ctx_->ensure_lps(l, dt);

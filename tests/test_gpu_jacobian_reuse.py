@@ -1,0 +1,149 @@
+"""Newton with kept Jacobians (jacobian_reuse = 1) on the GPU.
+
+The converged x_n of a step does not depend on which Jacobian Newton iterates
+with (defect correction on the FP64 residual, eq. newton), so a trajectory
+with kept Jacobians must match the one that rebuilds the hierarchy every step
+to the Newton tolerance: FP64 mode at tolerance 1e-13 to 1e-10 relative L2
+per field (the FP64 parity bar), also against the oracle's direct-solve Newton
+steps; mixed mode to 1e-5.  Also checked: the hierarchy is kept (fewer builds
+than steps), a new state value, a new time step size or new parameters force
+a build, and a kept Jacobian made stale behind the library's back (values
+written through the device pointer) still gives the right step.
+Inputs: channel with one obstacle, seed 0, level 3 (the FP64 parity
+workload), from rest with the ramped inflow.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import fem, mesh, solver
+from synthetic import channel_obstacle
+
+pytestmark = pytest.mark.gpu
+
+DT = 0.01
+LEVEL = 3
+
+
+def _fields(a, b):
+    a, b = a.reshape(-1, 3), b.reshape(-1, 3)
+    return max(np.linalg.norm(a[:, f] - b[:, f]) / max(np.linalg.norm(b[:, f]), 1e-300)
+               for f in range(3))
+
+
+def _pair(precision, tol, **kw):
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    out = []
+    for reuse in (0, 1):
+        ctx = P.Context(precision=precision, nu=macro.nu, newton_tol=tol, jacobian_reuse=reuse, **kw)
+        ctx.setup_mesh(macro, LEVEL)
+        out.append((ctx, ctx.state(LEVEL)))
+    return macro, out
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-13, 1e-10), (1, 1e-10, 1e-5)])
+def test_kept_jacobians_give_the_same_trajectory(precision, tol, bar):
+    _, ((ca, sa), (cb, sb)) = _pair(precision, tol)
+    builds_a, builds_b = [], []
+    for k in range(12):
+        ra, rb = ca.step(sa, DT), cb.step(sb, DT)
+        assert ra["converged"] == 1 and rb["converged"] == 1
+        builds_a.append(ra["jacobian_builds"])
+        builds_b.append(rb["jacobian_builds"])
+        err = _fields(sb.get()[0], sa.get()[0])
+        print(f"[reuse] precision {precision} step {k}: newton {ra['newton_iters']}/{rb['newton_iters']} "
+              f"builds {ra['jacobian_builds']}/{rb['jacobian_builds']} rel {err:.2e}", flush=True)
+        assert err <= bar, (k, err)
+    assert all(b == 1 for b in builds_a)
+    assert sum(builds_b) < len(builds_b), builds_b
+    for c, s in ((ca, sa), (cb, sb)):
+        s.close()
+        c.close()
+
+
+def test_kept_jacobians_match_oracle():
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    L = mesh.hierarchy(macro, LEVEL)[LEVEL]
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    # residual tolerances of the step parity test: the 1e-10 bar on x_n needs
+    # ||R|| near 1e-14 at this level (the pressure of the first steps is small)
+    ctx = P.Context(precision=0, nu=macro.nu, newton_tol=1e-14, jacobian_reuse=1)
+    ctx.setup_mesh(macro, LEVEL)
+    st = ctx.state(LEVEL)
+    x = np.zeros(3 * L.n_nodes)
+    kept = 0
+    for k in range(4):
+        kept += ctx.step(st, DT)["jacobian_builds"] == 0
+        x = solver.newton_step(L, prob, x, (k + 1) * DT, tol=1e-15)
+        err = _fields(st.get()[0], x)
+        print(f"[reuse] oracle step {k}: rel {err:.2e}", flush=True)
+        assert err <= 1e-10
+    assert kept >= 1
+    st.close()
+    ctx.close()
+
+
+def test_new_values_dt_or_params_force_a_build():
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    ctx = P.Context(precision=1, nu=macro.nu, jacobian_reuse=1)
+    ctx.setup_mesh(macro, LEVEL)
+    st = ctx.state(LEVEL)
+    kept = 0
+    for _ in range(4):
+        kept += ctx.step(st, DT)["jacobian_builds"] == 0
+    assert kept >= 1
+    x, t = st.get()
+    st.set(x, t)                                   # new values: a new key
+    assert ctx.step(st, DT)["jacobian_builds"] >= 1
+    r = ctx.step(st, 0.5 * DT)                     # another time step size
+    assert r["jacobian_builds"] >= 1 and r["converged"] == 1
+    ctx.set_params(alpha0=0.25)                    # new stabilisation
+    assert ctx.step(st, 0.5 * DT)["jacobian_builds"] >= 1
+    other = ctx.state(LEVEL)                       # another state of the same context
+    other.set(x, t)
+    assert ctx.step(other, 0.5 * DT)["jacobian_builds"] >= 1
+    assert ctx.step(st, 0.5 * DT)["jacobian_builds"] >= 1
+    other.close()
+    st.close()
+    ctx.close()
+
+
+def test_stale_jacobian_behind_the_library_still_converges():
+    """Values replaced through the device pointer keep the state's key, so the
+    kept Jacobian belongs to other values; the contraction test (or the redo
+    with fresh Jacobians) must still reach the step of the new values."""
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    ref = P.Context(precision=0, nu=macro.nu, newton_tol=1e-13)
+    ref.setup_mesh(macro, LEVEL)
+    sr = ref.state(LEVEL)
+    for _ in range(15):                            # a developed state
+        ref.step(sr, DT)
+    x15, _ = sr.get()
+    ctx = P.Context(precision=0, nu=macro.nu, newton_tol=1e-13, jacobian_reuse=1,
+                    reuse_contraction=0.9)
+    ctx.setup_mesh(macro, LEVEL)
+    st = ctx.state(LEVEL)
+    for _ in range(2):                             # keeps a Jacobian of the start-up flow
+        ctx.step(st, DT)
+    t = st.get()[1]
+    hip = C.CDLL("/opt/rocm/lib/libamdhip64.so.7")
+    src = np.ascontiguousarray(x15)
+    rc = hip.hipMemcpy(C.c_void_p(st.device_ptr()), C.c_void_p(src.ctypes.data),
+                       C.c_size_t(src.nbytes), 1)  # host to device, synchronous
+    assert rc == 0
+    sr.set(x15, t)                                 # the same step without kept Jacobians
+    ref.step(sr, DT)
+    r = ctx.step(st, DT)
+    assert r["converged"] == 1
+    err = _fields(st.get()[0], sr.get()[0])
+    print(f"[reuse] stale: newton {r['newton_iters']} builds {r['jacobian_builds']} rel {err:.2e}",
+          flush=True)
+    assert err <= 1e-10
+    for c, s in ((ref, sr), (ctx, st)):
+        s.close()
+        c.close()
