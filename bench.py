@@ -227,20 +227,23 @@ def roofline_from(prof, ctx, level, kernels_with_bytes, log=None):
             "launches": cnt, "bytes_per_launch": b}
 
 
-def train_dnnmg(ctx, net, xF, args, log):
-    """Trains the patch network on the GPU (untimed): teacher-forced coarse
-    steps (the coarse right-hand side restricted from the fine velocity of
-    the previous step) give inputs and targets d* = v^F_n - P^m v^L_n; BPTT
-    with Adam; then DAgger rounds add the states of free DNN-MG runs."""
+def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
+    """Trains the patch network on the GPU (untimed in the step benchmark):
+    teacher-forced coarse steps (the coarse right-hand side restricted from
+    the fine velocity of the previous step) give inputs and targets
+    d* = v^F_n - P^m v^L_n; BPTT with Adam; then DAgger rounds add the states
+    of free DNN-MG runs.  Returns a summary with the wall time of the BPTT
+    iterations alone."""
     import numpy as np
     import torch
 
     from synthetic import gru_weights
-    L, dt = args.coarse_level, args.dt
     nL = ctx.level_info(L)[0]
     N = len(xF) - 1
     S2 = net.n_out // 2
-    net.set_weights(None, mu=np.zeros(10), sigma=np.ones(10), out_scale=np.ones(2))
+    nch = (net.n_in - net.n_stats) // (S2 - 1)        # nodal channels (6 block, 5 cell)
+    nft = net.n_stats - nch
+    net.set_weights(None, mu=np.zeros(net.n_stats), sigma=np.ones(net.n_stats), out_scale=np.ones(2))
     sl = ctx.state(L)
     Xr, Dr = [], []
     for n in range(1, N + 1):
@@ -251,34 +254,39 @@ def train_dnnmg(ctx, net, xF, args, log):
         Dr.append(net.targets(sl, xF[n]))
     sl.close()
     Xr, Dr = np.stack(Xr), np.stack(Dr)
-    mu = np.array([Xr[..., c * S2:(c + 1) * S2].mean() for c in range(6)] +
-                  [Xr[..., 6 * S2 + k].mean() for k in range(4)])
-    sg = np.array([Xr[..., c * S2:(c + 1) * S2].std() for c in range(6)] +
-                  [Xr[..., 6 * S2 + k].std() for k in range(4)])
+    mu = np.array([Xr[..., c * S2:(c + 1) * S2].mean() for c in range(nch)] +
+                  [Xr[..., nch * S2 + k].mean() for k in range(nft)])
+    sg = np.array([Xr[..., c * S2:(c + 1) * S2].std() for c in range(nch)] +
+                  [Xr[..., nch * S2 + k].std() for k in range(nft)])
     sg = np.where(sg > 1e-30, sg, 1.0)
     osc = np.array([Dr[..., :S2].std(), Dr[..., S2:].std()])
     osc = np.where(osc > 1e-30, osc, 1.0)
-    mu_f = np.concatenate([np.repeat(mu[:6], S2), mu[6:]]).astype(np.float32)
-    sg_f = np.concatenate([np.repeat(sg[:6], S2), sg[6:]]).astype(np.float32)
+    mu_f = np.concatenate([np.repeat(mu[:nch], S2), mu[nch:]]).astype(np.float32)
+    sg_f = np.concatenate([np.repeat(sg[:nch], S2), sg[nch:]]).astype(np.float32)
     os_f = np.concatenate([np.repeat(osc[0], S2), np.repeat(osc[1], S2)]).astype(np.float32)
-    w0 = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
+    w0 = gru_weights(net.n_in, net.hidden, net.layers, net.n_out, seed=seed, scale=0.5)
     net.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
     X = torch.from_numpy((Xr - mu_f) / sg_f).cuda()
     D = torch.from_numpy(Dr / os_f).cuda()
     del Xr, Dr
     ck = min(8, N)
+    bptt = {"iters": 0, "sec": 0.0}
 
-    def fit(iters, lr):
+    def fit(n_it, lr):
         loss = None
-        for it in range(iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(n_it):
             loss = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1],
-                                      lr=lr if it < 0.75 * iters else 0.3 * lr, ckpt=ck)
+                                      lr=lr if it < 0.75 * n_it else 0.3 * lr, ckpt=ck)
+        bptt["sec"] += time.perf_counter() - t0     # each call returns its loss: synchronous
+        bptt["iters"] += n_it
         return loss
 
     first = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1], lr=2e-3, ckpt=ck)
-    loss = fit(args.train_net_iters, 2e-3)
+    loss = fit(iters, 2e-3)
     log(f"net training (teacher forcing): loss {first:.1f} -> {loss:.1f}, {X.shape[1]} sequences")
-    for rnd in range(args.dagger):
+    for rnd in range(dagger):
         st = ctx.state(L)
         net.reset(st)
         Xc, Dc = [], []
@@ -289,12 +297,79 @@ def train_dnnmg(ctx, net, xF, args, log):
         st.close()
         X = torch.cat([X, torch.from_numpy(np.stack(Xc)).cuda()], dim=1).contiguous()
         D = torch.cat([D, torch.from_numpy(np.stack(Dc)).cuda()], dim=1).contiguous()
-        loss = fit(args.train_net_iters // 2, 1e-3)
+        loss = fit(iters // 2, 1e-3)
         log(f"net training (DAgger round {rnd}): loss {loss:.1f}, {X.shape[1]} sequences")
     del X, D
     torch.cuda.empty_cache()
-    return {"sequences_per_round": net.n_patches, "steps": N, "rounds": 1 + args.dagger,
-            "final_loss": round(float(loss), 3)}
+    return {"sequences_per_round": net.n_patches, "steps": N, "rounds": 1 + dagger,
+            "final_loss": round(float(loss), 3), "bptt_iters": bptt["iters"],
+            "bptt_sec": round(bptt["sec"], 3)}
+
+
+TABLE1_SHAPES = ((32, 1), (64, 1), (32, 2), (64, 2), (32, 3), (64, 3))
+
+
+def run_table1(P, args, log):
+    """The network-size sweep of Table 1 / Table 2 on one MI355X: cell
+    patches (one level-L element, I = 51, O = 18) correcting level L + 1, the
+    six GRU shapes; per shape the BPTT training time and DNN-MG steps/s and
+    velocity error against MG(L+1), beside plain MG(L) and MG(L+1)."""
+    import numpy as np
+    import torch
+
+    from synthetic import channel_obstacle
+    macro = channel_obstacle(args.seed)
+    F = args.t1_level
+    L = F - 1
+    dt, n_tr, n_ev = args.t1_dt, args.t1_train_steps, args.t1_steps
+    ctx = P.Context(precision=1, nu=macro.nu, jacobian_reuse=args.jacobian_reuse)
+    ctx.setup_mesh(macro, F)
+    sf = ctx.state(F)
+    xF = [sf.get()[0]]
+    for _ in range(n_ev):
+        ctx.step(sf, dt)
+        xF.append(sf.get()[0])
+    sf.close()
+
+    def timed(level, net=None):
+        st = ctx.state(level)
+        if net is not None:
+            net.reset(st)
+        t0 = time.perf_counter()
+        run_steps(ctx, st, n_ev, dt, net)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st.close()
+        return n_ev / sec
+
+    def errors(net=None):
+        st = ctx.state(L)
+        if net is not None:
+            net.reset(st)
+        e = []
+        for n in range(1, n_ev + 1):
+            ctx.step(st, dt)
+            corr = net.correct(st, dt, debug=True)["correction"] if net is not None else None
+            e.append(velocity_error(ctx, st.get()[0], L, F, xF[n], corr))
+        st.close()
+        return float(np.mean(e[n_tr:])) if n_ev > n_tr else float(np.mean(e))
+
+    out = {"coarse_level": L, "fine_level": F, "dt": dt, "train_steps": n_tr, "eval_steps": n_ev,
+           "coarse_dofs": 3 * ctx.level_info(L)[0], "fine_dofs": 3 * ctx.level_info(F)[0],
+           "mg_fine_steps_per_s": round(timed(F), 2), "mg_coarse_steps_per_s": round(timed(L), 2),
+           "mg_coarse_err": round(errors(), 6), "nets": []}
+    for H, layers in TABLE1_SHAPES:
+        net = P.Net(ctx, L, 1, H, layers, patch="cell")
+        info = train_dnnmg(ctx, net, xF[:n_tr + 1], L, dt, args.t1_iters, 1, args.seed, log)
+        row = {"hidden": H, "layers": layers, "params": net.n_params, "n_in": net.n_in, "n_out": net.n_out,
+               "bptt_ms_per_iter": round(1e3 * info["bptt_sec"] / info["bptt_iters"], 3),
+               "bptt_sec": info["bptt_sec"], "final_loss": info["final_loss"],
+               "dnnmg_steps_per_s": round(timed(L, net), 2), "dnnmg_err": round(errors(net), 6)}
+        log(f"table1 {H}x{layers}: {row}")
+        out["nets"].append(row)
+        net.close()
+    ctx.close()
+    return out
 
 
 def main():
@@ -323,6 +398,13 @@ def main():
                          "directly (no graphs; events add launch overhead to the timings)")
     ap.add_argument("--newton-predictor", type=int, default=1, choices=(0, 1),
                     help="1: Newton starts from the linear extrapolation of the last two states")
+    ap.add_argument("--table1", type=int, default=1, choices=(0, 1),
+                    help="network-size sweep (Table 1 shapes on cell patches, untimed leg)")
+    ap.add_argument("--t1-level", type=int, default=3)
+    ap.add_argument("--t1-dt", type=float, default=0.01)
+    ap.add_argument("--t1-train-steps", type=int, default=32)
+    ap.add_argument("--t1-steps", type=int, default=64)
+    ap.add_argument("--t1-iters", type=int, default=200)
     ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
                     help="keep Newton's Jacobians across iterations and steps while the "
                          "residual contracts by 0.1 or better (0: rebuild every step)")
@@ -408,7 +490,8 @@ def main():
     sfr.close()
     train_info = None
     if args.train_net:
-        train_info = train_dnnmg(ctx, net, xF, args, log)
+        train_info = train_dnnmg(ctx, net, xF, args.coarse_level, args.dt, args.train_net_iters,
+                                 args.dagger, args.seed, log)
     else:
         w = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
         net.set_weights(w, mu=np.zeros(10), sigma=np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
@@ -475,6 +558,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5), "avg_us": round(1e3 * ms / cnt, 2)}
     # ---- batched plain solves
     batch_info = run_batch(P, args, log) if args.batch_sims > 0 else None
+    # ---- network-size sweep (Table 1 / Table 2 analogue)
+    table1 = run_table1(P, args, log) if args.table1 else None
     # ---- BPTT training throughput at the training batch shape (synthetic rows)
     train = None
     if args.train_iters > 0:
@@ -543,6 +628,7 @@ def main():
         "mfma": mfma,
         "train": train,
         "batch": batch_info,
+        "table1": table1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)

@@ -224,13 +224,30 @@ int dnnmg_restrict(dnnmg_ctx *ctx, int level, const double *fine, double *coarse
  * hidden a multiple of 32.  Weights start at zero. */
 int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers,
                      dnnmg_net **out);
+
+#define DNNMG_PATCH_BLOCK 0   /* the 2x2 level-L cells of one level-(L-1) cell  */
+#define DNNMG_PATCH_CELL 1    /* one level-L cell                                */
+/* As dnnmg_net_create with a choice of patch.  DNNMG_PATCH_CELL is the patch
+ * of the paper's own experiments (Sec. 2.2: a mesh element on level L): S =
+ * 2^m_levels + 1 fine nodes per side, input size I = 5 S^2 + 6 ([u, v, r_u,
+ * r_v, r_p] at the patch nodes, channel-major: the pressure enters through
+ * the residual only; then aspect ratio, mid-line skew, h_P / mean h_P, the
+ * Peclet number, cos 2phi and sin 2phi of the angle phi of the left -> right
+ * mid-line), O = 2 S^2; with m_levels = 1, I = 51 and O = 18 (Table 1);
+ * coarse_level >= 0.  DNNMG_PATCH_BLOCK is dnnmg_net_create. */
+int dnnmg_net_create_patch(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers,
+                           int patch, dnnmg_net **out);
 int dnnmg_net_destroy(dnnmg_net *net);
 int dnnmg_net_info(const dnnmg_net *net, int *n_in, int *n_out, int *n_patches,
                    long long *n_params);
+/* Patch kind, fine nodes per patch side S and the number of standardisation
+ * pairs (10 for block patches, 11 for cell patches); NULL outputs skipped. */
+int dnnmg_net_patch_info(const dnnmg_net *net, int *patch, int *nodes_per_side, int *n_stats);
 /* Host FP32 weights in the order: per layer W_ih (3H x I_l, gate rows r, z, n)
  * then W_hh (3H x H); then W_out (O x H), all row-major.  mu / sigma: the
- * 10 standardisation pairs (6 nodal channels, 4 features), x^ = (x - mu) /
- * sigma; out_scale: scales of the predicted u and v.  NULL leaves a part
+ * standardisation pairs, nodal channels then features (10 for block
+ * patches: 6 + 4; 11 for cell patches: 5 + 6), x^ = (x - mu) / sigma;
+ * out_scale: scales of the predicted u and v.  NULL leaves a part
  * unchanged.  The device keeps FP32 masters and BF16 working copies. */
 int dnnmg_net_set_weights(dnnmg_net *net, const float *w, const float *mu, const float *sigma,
                           const float *out_scale);

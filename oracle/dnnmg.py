@@ -28,6 +28,13 @@ h_P = sqrt(area of the corner quadrilateral), and the patch Peclet number
 max_P |v~| h_P / nu; channel standardisation x^ = (x - mu) / sigma with the
 net's 10 (mu, sigma) pairs; the prediction is scaled by the net's 2 output
 scales.
+
+Cell patches (the patch of the paper's own experiments, Sec. 2.2: one
+level-L element): (2^m + 1)^2 fine nodes; reading N16 inputs
+[v~1, v~2, r1, r2, rp] at the nodes (the pressure enters through the
+residual only) and six features, the four above plus cos 2phi and sin 2phi
+of the angle phi of the left -> right mid-line; 11 (mu, sigma) pairs.  At
+m = 1 this is I = 5 * 9 + 6 = 51 inputs and O = 18 outputs.
 """
 from __future__ import annotations
 
@@ -38,10 +45,14 @@ import numpy as np
 from . import fem, gru
 from .mesh import Level
 
+PATCH_BLOCK, PATCH_CELL = 0, 1
 
-def patch_grid(levels, L: int, m: int) -> np.ndarray:
-    """(P, S*S) fine-level node ids of every level-L patch, S = 2^(m+1) + 1,
-    lexicographic (i along the parent's first edge, j along its last edge)."""
+
+def patch_grid(levels, L: int, m: int, kind: int = PATCH_BLOCK) -> np.ndarray:
+    """(P, S*S) fine-level node ids of every patch, lexicographic (i along
+    the root cell's first edge, j along its last edge).  Block patches: the
+    root is a level-(L-1) cell, S = 2^(m+1) + 1; cell patches: the root is a
+    level-L cell, S = 2^m + 1."""
     # level-(L-1) cell c refined j times covers a (2^j + 1)^2 grid on level L-1+j
     def grid(lvl, j):
         # lvl: level whose cells are the roots; returns (C_lvl, 2^j+1, 2^j+1)
@@ -58,7 +69,7 @@ def patch_grid(levels, L: int, m: int) -> np.ndarray:
         for k, (ox, oy) in off.items():
             out[:, oy:oy + s, ox:ox + s] = sub[:, k]
         return out
-    g = grid(L - 1, m + 1)
+    g = grid(L - 1, m + 1) if kind == PATCH_BLOCK else grid(L, m)
     return g.reshape(g.shape[0], -1)
 
 
@@ -88,6 +99,15 @@ def static_features(xyF, grid, S):
     return aspect, skew, h
 
 
+def orientation(xyF, grid, S):
+    """(cos 2 phi, sin 2 phi) of the left -> right mid-line of each patch."""
+    c00, c10 = xyF[grid[:, 0]], xyF[grid[:, S - 1]]
+    c01, c11 = xyF[grid[:, S * (S - 1)]], xyF[grid[:, S * S - 1]]
+    a = 0.5 * (c10 + c11) - 0.5 * (c00 + c01)
+    phi = np.arctan2(a[:, 1], a[:, 0])
+    return np.cos(2 * phi), np.sin(2 * phi)
+
+
 def rhs_rows(level: Level, prob: fem.Problem, v):
     """(N, 2) explicit velocity rows of f_n (eq. varformv) for the velocity
     field v: 1/k (v, phi) - (1 - theta)((v.grad) v, phi)
@@ -111,8 +131,8 @@ class NetSpec:
     weights: np.ndarray      # flat, gru.unpack order
     hidden: int
     layers: int
-    mu: np.ndarray           # (10,) channel means (6 nodal channels, 4 features)
-    sigma: np.ndarray        # (10,) channel scales
+    mu: np.ndarray           # channel means: nodal channels, then features
+    sigma: np.ndarray        # channel scales (same order)
     out_scale: np.ndarray    # (2,) scale of the predicted u, v corrections
 
 
@@ -120,14 +140,17 @@ class DnnmgOracle:
     """Prolongation, fine residual, patch network and restricted rhs of
     Algorithm 1 for one geometry (levels 0..F)."""
 
-    def __init__(self, levels, prob: fem.Problem, L: int, m: int):
-        self.levels, self.prob, self.L, self.m = levels, prob, L, m
+    def __init__(self, levels, prob: fem.Problem, L: int, m: int, kind: int = PATCH_BLOCK):
+        self.levels, self.prob, self.L, self.m, self.kind = levels, prob, L, m, kind
         self.F = L + m
-        self.S = 2 ** (m + 1) + 1
-        self.grid = patch_grid(levels, L, m)
+        self.S = 2 ** (m + 1) + 1 if kind == PATCH_BLOCK else 2 ** m + 1
+        self.n_ch = 6 if kind == PATCH_BLOCK else 5
+        self.n_feat = 4 if kind == PATCH_BLOCK else 6
+        self.grid = patch_grid(levels, L, m, kind)
         LF = levels[self.F]
         self.mass = lumped_mass(LF)
         self.aspect, self.skew, self.h = static_features(LF.xy, self.grid, self.S)
+        self.c2, self.s2 = orientation(LF.xy, self.grid, self.S)
         self.hrel = self.h / self.h.mean()
         self.dir_f = LF.dirichlet_nodes()
         self.P = [None] + [levels[l].prolongation() for l in range(1, len(levels))]
@@ -141,7 +164,11 @@ class DnnmgOracle:
 
     @property
     def n_in(self):
-        return 6 * self.S * self.S + 4
+        return self.n_ch * self.S * self.S + self.n_feat
+
+    @property
+    def n_stats(self):
+        return self.n_ch + self.n_feat
 
     @property
     def n_out(self):
@@ -167,16 +194,21 @@ class DnnmgOracle:
         r = r / self.mass[:, None]
         X3 = xt.reshape(-1, 3)
         g = self.grid
-        nodal = np.concatenate([X3[g, 0], X3[g, 1], X3[g, 2], r[g, 0], r[g, 1], r[g, 2]], axis=1)
+        chans = [X3[g, 0], X3[g, 1], X3[g, 2], r[g, 0], r[g, 1], r[g, 2]]
+        if self.kind == PATCH_CELL:
+            del chans[2]                                # no prolongated pressure
+        nodal = np.concatenate(chans, axis=1)
         speed = np.sqrt(X3[:, 0] ** 2 + X3[:, 1] ** 2)
         pe = speed[g].max(axis=1) * self.h / self.prob.nu
-        feats = np.stack([self.aspect, self.skew, self.hrel, pe], axis=1)
-        return np.concatenate([nodal, feats], axis=1), r
+        feats = [self.aspect, self.skew, self.hrel, pe]
+        if self.kind == PATCH_CELL:
+            feats += [self.c2, self.s2]
+        return np.concatenate([nodal, np.stack(feats, axis=1)], axis=1), r
 
     def standardise(self, X, net: NetSpec):
-        n = self.S * self.S
-        mu = np.concatenate([np.repeat(net.mu[:6], n), net.mu[6:]])
-        sg = np.concatenate([np.repeat(net.sigma[:6], n), net.sigma[6:]])
+        n, c = self.S * self.S, self.n_ch
+        mu = np.concatenate([np.repeat(net.mu[:c], n), net.mu[c:]])
+        sg = np.concatenate([np.repeat(net.sigma[:c], n), net.sigma[c:]])
         return (X - mu) / sg
 
     def scatter(self, Y, net: NetSpec):

@@ -97,6 +97,9 @@ _SIGS = {
     "dnnmg_prolong": (C.c_int, [_P, C.c_int, _DP, _DP]),
     "dnnmg_restrict": (C.c_int, [_P, C.c_int, _DP, _DP]),
     "dnnmg_net_create": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_P)]),
+    "dnnmg_net_create_patch": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(_P)]),
+    "dnnmg_net_patch_info": (C.c_int, [_P, _IP, _IP, _IP]),
     "dnnmg_net_destroy": (C.c_int, [_P]),
     "dnnmg_net_info": (C.c_int, [_P, _IP, _IP, _IP, C.POINTER(C.c_longlong)]),
     "dnnmg_net_set_weights": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
@@ -360,14 +363,20 @@ def _fp(a):
 class Net:
     """Owner of one dnnmg_net (patch GRU network of one simulation)."""
 
-    def __init__(self, ctx: Context, coarse_level: int, m_levels: int, hidden: int, layers: int):
+    PATCH = {"block": 0, "cell": 1}
+
+    def __init__(self, ctx: Context, coarse_level: int, m_levels: int, hidden: int, layers: int,
+                 patch: str = "block"):
         self.ctx = ctx
         h = _P()
-        ctx._check(ctx.lib.dnnmg_net_create(ctx.h, coarse_level, m_levels, hidden, layers, C.byref(h)))
+        ctx._check(ctx.lib.dnnmg_net_create_patch(ctx.h, coarse_level, m_levels, hidden, layers,
+                                                  self.PATCH[patch], C.byref(h)))
         self.h = h
         a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_longlong()
         ctx._check(ctx.lib.dnnmg_net_info(h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         self.n_in, self.n_out, self.n_patches, self.n_params = a.value, b.value, c.value, d.value
+        ctx._check(ctx.lib.dnnmg_net_patch_info(h, None, C.byref(a), C.byref(b)))
+        self.patch, self.nodes_per_side, self.n_stats = patch, a.value, b.value
         self.hidden, self.layers = hidden, layers
         self.coarse_level, self.m_levels = coarse_level, m_levels
 

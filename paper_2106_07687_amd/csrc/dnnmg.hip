@@ -32,12 +32,14 @@ void fill_grid(const std::vector<std::unique_ptr<DevLevel>> &lv, int lvl, int c,
 
 void build_patch_tables(Net &n) {
   Ctx &c = *n.ctx;
-  const HostLevel &hp = c.levels[n.L - 1]->h;   // patch roots
+  // patch roots: level-(L-1) cells (block patches) or level-L cells
+  const int root = n.patch == DNNMG_PATCH_CELL ? n.L : n.L - 1;
+  const HostLevel &hp = c.levels[root]->h;
   const HostLevel &hf = c.levels[n.F]->h;
   n.B = hp.C;
   std::vector<int> grid(static_cast<size_t>(n.B) * n.S2, -1);
   for (int p = 0; p < n.B; ++p)
-    fill_grid(c.levels, n.L - 1, p, n.m + 1, 0, 0, n.S - 1, n.S, &grid[static_cast<size_t>(p) * n.S2]);
+    fill_grid(c.levels, root, p, n.F - root, 0, 0, n.S - 1, n.S, &grid[static_cast<size_t>(p) * n.S2]);
   for (int v : grid)
     if (v < 0 || v >= hf.N) throw DnnmgError{DNNMG_EDEVICE, "patch grid construction failed"};
   std::vector<int> ptr(hf.N + 1, 0);
@@ -72,7 +74,8 @@ void build_patch_tables(Net &n) {
   std::vector<double> inv(hf.N);
   for (int i = 0; i < hf.N; ++i) inv[i] = 1.0 / mass[i];
   // static features from the patch corners
-  std::vector<double> feat(static_cast<size_t>(4) * n.B);
+  const int nf = n.nfeat;
+  std::vector<double> feat(static_cast<size_t>(nf) * n.B, 0.0);
   double hsum = 0.0;
   for (int p = 0; p < n.B; ++p) {
     const int *gp = &grid[static_cast<size_t>(p) * n.S2];
@@ -92,13 +95,19 @@ void build_patch_tables(Net &n) {
     double area = 0.0;
     for (int k = 0; k < 4; ++k) area += X[k] * Y[(k + 1) % 4] - X[(k + 1) % 4] * Y[k];
     const double h = std::sqrt(0.5 * std::fabs(area));
-    feat[4 * p] = aspect;
-    feat[4 * p + 1] = skew;
-    feat[4 * p + 3] = h;
+    double *f = &feat[static_cast<size_t>(nf) * p];
+    f[0] = aspect;
+    f[1] = skew;
+    f[3] = h;
+    if (nf == 6) {   // direction of the left -> right mid-line, as (cos 2phi, sin 2phi)
+      const double a2 = ax * ax + ay * ay;
+      f[4] = (ax * ax - ay * ay) / a2;
+      f[5] = 2.0 * ax * ay / a2;
+    }
     hsum += h;
   }
   const double hmean = hsum / n.B;
-  for (int p = 0; p < n.B; ++p) feat[4 * p + 2] = feat[4 * p + 3] / hmean;
+  for (int p = 0; p < n.B; ++p) feat[static_cast<size_t>(nf) * p + 2] = feat[static_cast<size_t>(nf) * p + 3] / hmean;
   n.grid.upload(grid, c.stream);
   n.nadj_ptr.upload(ptr, c.stream);
   n.nadj.upload(adj, c.stream);
@@ -281,10 +290,17 @@ int dnnmg_rhs_from_fine(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, con
 
 int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers,
                      dnnmg_net **out) {
+  return dnnmg_net_create_patch(ctx, coarse_level, m_levels, hidden, layers, DNNMG_PATCH_BLOCK, out);
+}
+
+int dnnmg_net_create_patch(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden, int layers, int patch,
+                           dnnmg_net **out) {
   if (!ctx || !out) return DNNMG_EINVAL;
   if (ctx->impl.finest < 0) return DNNMG_ESTATE;
-  if (coarse_level < 1 || m_levels < 1 || coarse_level + m_levels > ctx->impl.finest || hidden < 32 ||
-      hidden % 32 != 0 || hidden > 1024 || layers < 1 || layers > 8) {
+  if ((patch != DNNMG_PATCH_BLOCK && patch != DNNMG_PATCH_CELL) ||
+      coarse_level < (patch == DNNMG_PATCH_BLOCK ? 1 : 0) || m_levels < 1 ||
+      coarse_level + m_levels > ctx->impl.finest || hidden < 32 || hidden % 32 != 0 || hidden > 1024 ||
+      layers < 1 || layers > 8) {
     ctx->impl.last_error = "invalid network / level configuration";
     return DNNMG_EINVAL;
   }
@@ -297,9 +313,13 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
     n.L = coarse_level;
     n.m = m_levels;
     n.F = coarse_level + m_levels;
-    n.S = (1 << (m_levels + 1)) + 1;
+    n.patch = patch;
+    n.S = (1 << (patch == DNNMG_PATCH_CELL ? m_levels : m_levels + 1)) + 1;
     n.S2 = n.S * n.S;
-    n.I = 6 * n.S2 + 4;
+    n.nch = patch == DNNMG_PATCH_CELL ? 5 : 6;
+    n.nfeat = patch == DNNMG_PATCH_CELL ? 6 : 4;
+    n.nstat = n.nch + n.nfeat;
+    n.I = n.nch * n.S2 + n.nfeat;
     n.O = 2 * n.S2;
     n.H = hidden;
     n.layers = layers;
@@ -335,10 +355,10 @@ int dnnmg_net_create(dnnmg_ctx *ctx, int coarse_level, int m_levels, int hidden,
       n.hb_next[l].alloc(static_cast<size_t>(n.B) * n.H);
     }
     n.wout_b.alloc(static_cast<size_t>(n.O) * n.H);
-    n.mu.alloc(10);
-    n.sg.alloc(10);
+    n.mu.alloc(n.nstat);
+    n.sg.alloc(n.nstat);
     n.oscale.alloc(2);
-    std::vector<float> zeros(10, 0.0f), ones(10, 1.0f);
+    std::vector<float> zeros(n.nstat, 0.0f), ones(n.nstat, 1.0f);
     n.mu.upload(zeros, c.stream);
     n.sg.upload(ones, c.stream);
     n.oscale.upload(std::vector<float>{1.0f, 1.0f}, c.stream);
@@ -389,13 +409,22 @@ int dnnmg_net_info(const dnnmg_net *net, int *n_in, int *n_out, int *n_patches, 
   return DNNMG_OK;
 }
 
+int dnnmg_net_patch_info(const dnnmg_net *net, int *patch, int *nodes_per_side, int *n_stats) {
+  if (!net) return DNNMG_EINVAL;
+  const Net &n = net->impl;
+  if (patch) *patch = n.patch;
+  if (nodes_per_side) *nodes_per_side = n.S;
+  if (n_stats) *n_stats = n.nstat;
+  return DNNMG_OK;
+}
+
 int dnnmg_net_set_weights(dnnmg_net *net, const float *w, const float *mu, const float *sigma,
                           const float *out_scale) {
   if (!net) return DNNMG_EINVAL;
   Net &n = net->impl;
   Ctx &c = *n.ctx;
   if (sigma)
-    for (int k = 0; k < 10; ++k)
+    for (int k = 0; k < n.nstat; ++k)
       if (!(sigma[k] > 0.0f)) {
         c.last_error = "sigma must be positive";
         return DNNMG_EINVAL;
@@ -403,8 +432,9 @@ int dnnmg_net_set_weights(dnnmg_net *net, const float *w, const float *mu, const
   try {
     if (w)
       check(hipMemcpyAsync(n.w32.p, w, sizeof(float) * n.nparam, hipMemcpyHostToDevice, c.stream), "w H2D");
-    if (mu) check(hipMemcpyAsync(n.mu.p, mu, sizeof(float) * 10, hipMemcpyHostToDevice, c.stream), "mu");
-    if (sigma) check(hipMemcpyAsync(n.sg.p, sigma, sizeof(float) * 10, hipMemcpyHostToDevice, c.stream), "sg");
+    if (mu) check(hipMemcpyAsync(n.mu.p, mu, sizeof(float) * n.nstat, hipMemcpyHostToDevice, c.stream), "mu");
+    if (sigma)
+      check(hipMemcpyAsync(n.sg.p, sigma, sizeof(float) * n.nstat, hipMemcpyHostToDevice, c.stream), "sg");
     if (out_scale)
       check(hipMemcpyAsync(n.oscale.p, out_scale, sizeof(float) * 2, hipMemcpyHostToDevice, c.stream), "os");
     net_repack(n);

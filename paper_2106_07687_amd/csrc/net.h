@@ -22,6 +22,8 @@ struct TrainStateHolder {
 struct Net {
   Ctx *ctx = nullptr;
   int L = 0, m = 0, F = 0, S = 0, S2 = 0, B = 0;
+  int patch = 0;                               // DNNMG_PATCH_BLOCK or DNNMG_PATCH_CELL
+  int nch = 6, nfeat = 4, nstat = 10;          // nodal channels, features, (mu, sigma) pairs
   int I = 0, H = 0, layers = 0, O = 0, K0 = 0;   // K0: padded input width
   long long nparam = 0;
   std::vector<long long> off_ih, off_hh;       // offsets in the flat weight vector
@@ -46,7 +48,7 @@ struct Net {
   TrainStateHolder train;
   PatchView view() const {
     const DevLevel &LF = *ctx->levels[F];
-    return PatchView{B, S2, LF.h.N, grid.p, nadj_ptr.p, nadj.p, inv_mass.p, feat.p, LF.flag.p};
+    return PatchView{B, S2, LF.h.N, grid.p, nadj_ptr.p, nadj.p, inv_mass.p, feat.p, LF.flag.p, nch, nfeat};
   }
 };
 

@@ -18,8 +18,10 @@ struct PatchView {
   const int *grid;    // B * S2 fine node ids (lexicographic in the parent frame)
   const int *nadj_ptr, *nadj;   // fine node -> (patch * S2 + q)
   const double *inv_mass;       // NF, 1 / lumped mass
-  const double *feat;           // 4 * B: aspect, skew, h_rel, h
+  const double *feat;           // nfeat * B: aspect, skew, h_rel, h[, cos 2phi, sin 2phi]
   const uint8_t *flag;          // NF fine node flags
+  int nch;                      // nodal input channels: 6 (block patches) or 5 (cell patches, no p)
+  int nfeat;                    // patch features: 4 or 6
 };
 
 namespace {
@@ -218,10 +220,11 @@ __global__ void __launch_bounds__(256) k_gru_step_fused(int B, int H, const floa
 }
 
 // Patch gather (Algorithm 1, the network inputs): one workgroup per patch writes the
-// standardised input row [u, v, p, r_u, r_v, r_p at the S2 patch nodes;
-// aspect, skew, h_rel, Peclet] as BF16 into X (ld = ldx, padding zeroed).
-// Residual rows are divided by the lumped mass; Dirichlet velocity residual
-// rows are zero.
+// standardised input row as BF16 into X (ld = ldx, padding zeroed): block
+// patches [u, v, p, r_u, r_v, r_p at the S2 patch nodes; aspect, skew,
+// h_rel, Peclet], cell patches [u, v, r_u, r_v, r_p; aspect, skew, h_rel,
+// Peclet, cos 2phi, sin 2phi].  Residual rows are divided by the lumped
+// mass; Dirichlet velocity residual rows are zero.
 __global__ void __launch_bounds__(128) k_patch_gather(PatchView pv, const double *__restrict__ xt,
                                                       const double *__restrict__ R, const float *__restrict__ mu,
                                                       const float *__restrict__ sg, double nu,
@@ -240,12 +243,15 @@ __global__ void __launch_bounds__(128) k_patch_gather(PatchView pv, const double
     const bool dir = pv.flag[i] & 1;
     const double ru = dir ? 0.0 : R[3 * i] * im, rv = dir ? 0.0 : R[3 * i + 1] * im;
     const double rp = R[3 * i + 2] * im;
-    const double vals[6] = {u, v, pr, ru, rv, rp};
+    const bool no_p = pv.nch == 5;
+    const double vals[6] = {u, v, no_p ? ru : pr, no_p ? rv : ru, no_p ? rp : rv, rp};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const float s = static_cast<float>((vals[c] - mu[c]) / sg[c]);
-      row[c * S2 + q] = f2bf(s);
-      if (rowf) rowf[c * S2 + q] = s;
+      if (c < pv.nch) {
+        const float s = static_cast<float>((vals[c] - mu[c]) / sg[c]);
+        row[c * S2 + q] = f2bf(s);
+        if (rowf) rowf[c * S2 + q] = s;
+      }
     }
     sp = fmax(sp, sqrt(u * u + v * v));
   }
@@ -255,13 +261,13 @@ __global__ void __launch_bounds__(128) k_patch_gather(PatchView pv, const double
     if (tid < off) smax[tid] = fmax(smax[tid], smax[tid + off]);
     __syncthreads();
   }
-  const int I = 6 * S2 + 4;
-  if (tid < 4) {
-    const double *f = pv.feat + static_cast<size_t>(p) * 4;
-    const double val = tid < 3 ? f[tid] : smax[0] * f[3] / nu;
-    const float s = static_cast<float>((val - mu[6 + tid]) / sg[6 + tid]);
-    row[6 * S2 + tid] = f2bf(s);
-    if (rowf) rowf[6 * S2 + tid] = s;
+  const int nch = pv.nch, I = nch * S2 + pv.nfeat;
+  if (tid < pv.nfeat) {
+    const double *f = pv.feat + static_cast<size_t>(p) * pv.nfeat;
+    const double val = tid == 3 ? smax[0] * f[3] / nu : f[tid];
+    const float s = static_cast<float>((val - mu[nch + tid]) / sg[nch + tid]);
+    row[nch * S2 + tid] = f2bf(s);
+    if (rowf) rowf[nch * S2 + tid] = s;
   }
   for (int c = I + tid; c < ldx; c += blockDim.x) {
     row[c] = 0;

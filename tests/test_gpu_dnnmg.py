@@ -88,15 +88,28 @@ def _net_spec(w, hidden, layers, mu, sg, osc):
     return dnnmg.NetSpec(weights=w, hidden=hidden, layers=layers, mu=mu, sigma=sg, out_scale=osc)
 
 
-def test_correct_matches_oracle(setup):
+# (mu, sigma) per patch kind: nodal channels, then features
+_STATS = {
+    "block": ([0.3, 0.0, 0.1, 0.0, 0.0, 0.0, 1.5, 0.3, 1.0, 5.0],
+              [0.5, 0.3, 0.4, 1.0, 1.0, 2.0, 1.0, 0.3, 0.5, 10.0]),
+    "cell": ([0.3, 0.0, 0.0, 0.0, 0.0, 1.5, 0.3, 1.0, 5.0, 0.1, -0.2],
+             [0.5, 0.3, 1.0, 1.0, 2.0, 1.0, 0.3, 0.5, 10.0, 0.7, 0.9]),
+}
+
+
+@pytest.mark.parametrize("L,m,patch", [(1, 2, "block"), (2, 1, "cell"), (1, 2, "cell")])
+def test_correct_matches_oracle(setup, L, m, patch):
     P, macro, lev, ctx, prob = setup
-    L, m = 1, 2
-    D = dnnmg.DnnmgOracle(lev, prob, L, m)
-    net = P.Net(ctx, L, m, hidden=32, layers=2)
+    kind = dnnmg.PATCH_BLOCK if patch == "block" else dnnmg.PATCH_CELL
+    D = dnnmg.DnnmgOracle(lev, prob, L, m, kind)
+    net = P.Net(ctx, L, m, hidden=32, layers=2, patch=patch)
+    assert (net.n_in, net.n_out, net.n_patches, net.n_stats) == (D.n_in, D.n_out, D.n_patches, D.n_stats)
+    print(f"[correct] {patch} patches L={L} m={m}: I={net.n_in} O={net.n_out} B={net.n_patches}",
+          flush=True)
     dims = (net.n_in, 32, 2, net.n_out)
     w = gru_weights(*dims, seed=3, scale=0.5).astype(np.float32).astype(np.float64)
-    mu = np.array([0.3, 0.0, 0.1, 0.0, 0.0, 0.0, 1.5, 0.3, 1.0, 5.0], dtype=np.float32)
-    sg = np.array([0.5, 0.3, 0.4, 1.0, 1.0, 2.0, 1.0, 0.3, 0.5, 10.0], dtype=np.float32)
+    mu = np.array(_STATS[patch][0], dtype=np.float32)
+    sg = np.array(_STATS[patch][1], dtype=np.float32)
     osc = np.array([1e-3, 5e-4], dtype=np.float32)
     net.set_weights(w, mu, sg, osc)
     spec = _net_spec(w, 32, 2, mu.astype(np.float64), sg.astype(np.float64), osc.astype(np.float64))
@@ -129,6 +142,18 @@ def test_correct_matches_oracle(setup):
     np.testing.assert_array_equal(bL_g[:, 2], 0.0)
     st.close()
     net.close()
+
+
+def test_cell_patch_networks_have_table1_sizes(setup):
+    """The six shapes of Table 1 on cell patches at m = 1 (I = 51, O = 18)."""
+    import os
+    P, macro, lev, ctx, prob = setup
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table1_params.txt"),
+                      dtype=np.int64)
+    for hidden, layers, count in gold:
+        net = P.Net(ctx, 2, 1, hidden=int(hidden), layers=int(layers), patch="cell")
+        assert (net.n_in, net.n_out, net.n_params) == (51, 18, count)
+        net.close()
 
 
 def test_zero_network_dnnmg_equals_plain_on_parallelograms():
@@ -198,13 +223,17 @@ def test_dnnmg_trajectory_matches_oracle(setup):
     net.close()
 
 
-def test_bptt_gradient_matches_oracle(setup):
+@pytest.mark.parametrize("L,m,patch,hidden,layers", [(1, 2, "block", 64, 2), (2, 1, "cell", 32, 3),
+                                                      (2, 1, "cell", 64, 1)])
+def test_bptt_gradient_matches_oracle(setup, L, m, patch, hidden, layers):
     """Hand-written BPTT (BF16 MFMA GEMMs, FP32 gates, checkpoints every 8
     steps) against the FP64 oracle gradient on a 64-sequence batch: relative
-    L2 <= 3e-2 and cosine >= 0.999 (BF16 bar); the loss to 1e-2."""
+    L2 <= 3e-2 and cosine >= 0.999 (BF16 bar); the loss to 1e-2.  Shapes: the
+    block-patch net and two of Table 1's cell-patch nets (I = 51, O = 18)."""
     P, macro, lev, ctx, prob = setup
-    net = P.Net(ctx, 1, 2, hidden=64, layers=2)
-    dims = (net.n_in, 64, 2, net.n_out)
+    net = P.Net(ctx, L, m, hidden=hidden, layers=layers, patch=patch)
+    dims = (net.n_in, hidden, layers, net.n_out)
+    print(f"[bptt] {patch} I={net.n_in} H={hidden} layers={layers} O={net.n_out}", flush=True)
     w = gru_weights(*dims, seed=21).astype(np.float32).astype(np.float64)
     net.set_weights(w)
     rng = np.random.default_rng(5)

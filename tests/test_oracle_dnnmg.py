@@ -105,3 +105,66 @@ def test_dnnmg_residual_with_plain_rhs_equals_plain_residual():
     R1 = dnnmg.dnnmg_residual(lev, prob, 2, x, xo, b.reshape(-1), 0.4)
     R2 = fem.residual(L, prob, x, xo, 0.4)
     np.testing.assert_allclose(R1, R2, rtol=1e-12, atol=1e-13)
+
+
+# ---- cell patches (one level-L element, the patch of the paper's experiments)
+
+def test_cell_patches_are_the_level_L_cells():
+    m = channel_obstacle(0)
+    lev = mesh.hierarchy(m, 3)
+    D = dnnmg.DnnmgOracle(lev, fem.Problem(nu=m.nu, dt=0.01), L=2, m=1, kind=dnnmg.PATCH_CELL)
+    assert (D.S, D.n_in, D.n_out, D.n_stats) == (3, 51, 18, 11)      # Table 1's I and O
+    assert D.n_patches == lev[2].n_cells
+    g = D.grid
+    # corners in the cell's own vertex order (c00, c10, c11, c01)
+    np.testing.assert_array_equal(g[:, [0, 2, 8, 6]], lev[2].cells)
+    # the nine nodes are the vertices of the cell's four children
+    for c in range(0, lev[2].n_cells, 37):
+        assert set(g[c].tolist()) == set(lev[3].cells[4 * c:4 * c + 4].reshape(-1).tolist())
+    # the patches tile the fine mesh
+    assert D.n_patches * (D.S - 1) ** 2 == lev[3].n_cells
+    # m = 2: 5 x 5 nodes whose corners are still the level-L cell's vertices
+    D2 = dnnmg.DnnmgOracle(lev, fem.Problem(nu=m.nu, dt=0.01), L=1, m=2, kind=dnnmg.PATCH_CELL)
+    assert (D2.S, D2.n_in, D2.n_out) == (5, 131, 50)
+    np.testing.assert_array_equal(D2.grid[:, [0, 4, 24, 20]], lev[1].cells)
+
+
+def test_cell_patch_grid_is_lexicographic_and_orientation_feature():
+    base = rectangle(3, 2, 1.5, 1.0)
+    lev = mesh.hierarchy(base, 2)
+    D = dnnmg.DnnmgOracle(lev, fem.Problem(nu=0.01, dt=0.01), L=1, m=1, kind=dnnmg.PATCH_CELL)
+    xy = lev[2].xy[D.grid].reshape(-1, 3, 3, 2)
+    assert np.all(np.diff(xy[..., 0], axis=2) > 0) and np.all(np.diff(xy[..., 1], axis=1) > 0)
+    np.testing.assert_allclose(D.c2, 1.0, atol=1e-15)
+    np.testing.assert_allclose(D.s2, 0.0, atol=1e-15)
+    # the same mesh rotated by theta: the mid-line turns by theta
+    th = 0.3
+    rot = rectangle(3, 2, 1.5, 1.0)
+    rot.xy = base.xy @ np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]])
+    levr = mesh.hierarchy(rot, 2)
+    Dr = dnnmg.DnnmgOracle(levr, fem.Problem(nu=0.01, dt=0.01), L=1, m=1, kind=dnnmg.PATCH_CELL)
+    np.testing.assert_allclose(Dr.c2, np.cos(2 * th), atol=1e-13)
+    np.testing.assert_allclose(Dr.s2, np.sin(2 * th), atol=1e-13)
+    np.testing.assert_allclose(Dr.aspect, D.aspect, rtol=1e-13)
+
+
+def test_cell_patch_inputs_channels_and_peclet():
+    """Channels [u, v, r_u, r_v, r_p] (no pressure) and, for a uniform flow
+    (1, 0), the Peclet feature h_P / nu."""
+    base = rectangle(3, 2, 1.5, 1.0)
+    lev = mesh.hierarchy(base, 2)
+    prob = fem.Problem(nu=0.01, dt=0.01)
+    D = dnnmg.DnnmgOracle(lev, prob, L=1, m=1, kind=dnnmg.PATCH_CELL)
+    N = lev[2].n_nodes
+    rng = np.random.default_rng(4)
+    x = np.zeros((N, 3))
+    x[:, 0] = 1.0
+    x[:, 2] = rng.uniform(-1, 1, N)             # pressure must not appear as a channel
+    X, r = D.inputs(x.reshape(-1), x.reshape(-1), 0.5)
+    n = 9
+    np.testing.assert_array_equal(X[:, :n], 1.0)
+    np.testing.assert_array_equal(X[:, n:2 * n], 0.0)
+    for k, f in enumerate((0, 1, 2)):
+        np.testing.assert_array_equal(X[:, (2 + k) * n:(3 + k) * n], r[D.grid, f])
+    np.testing.assert_allclose(X[:, 5 * n + 3], D.h / prob.nu, rtol=1e-14)
+    assert X.shape[1] == 5 * n + 6 == 51
