@@ -227,33 +227,34 @@ def roofline_from(prof, ctx, level, kernels_with_bytes, log=None):
             "launches": cnt, "bytes_per_launch": b}
 
 
-def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
-    """Trains the patch network on the GPU (untimed in the step benchmark):
-    teacher-forced coarse steps (the coarse right-hand side restricted from
-    the fine velocity of the previous step) give inputs and targets
-    d* = v^F_n - P^m v^L_n; BPTT with Adam; then DAgger rounds add the states
-    of free DNN-MG runs.  Returns a summary with the wall time of the BPTT
-    iterations alone."""
+def teacher_data(ctx, net, xF, L, dt, n0=1, t0=0.0):
+    """Teacher-forced coarse steps n = n0 .. len(xF) - 1 (xF[k] is the fine
+    state at t0 + k dt; the coarse right-hand side is restricted from the
+    fine velocity of the previous step): raw network inputs (T, B, I) and
+    targets d* = v^F_n - P^m v^L_n (T, B, O).  Inputs and targets do not
+    depend on the network's weights, only on its patches."""
     import numpy as np
-    import torch
-
-    from synthetic import gru_weights
     nL = ctx.level_info(L)[0]
-    N = len(xF) - 1
-    S2 = net.n_out // 2
-    nch = (net.n_in - net.n_stats) // (S2 - 1)        # nodal channels (6 block, 5 cell)
-    nft = net.n_stats - nch
     net.set_weights(None, mu=np.zeros(net.n_stats), sigma=np.ones(net.n_stats), out_scale=np.ones(2))
     sl = ctx.state(L)
     Xr, Dr = [], []
-    for n in range(1, N + 1):
-        sl.set(xF[n - 1][:3 * nL], (n - 1) * dt)
+    for n in range(n0, len(xF)):
+        sl.set(xF[n - 1][:3 * nL], t0 + (n - 1) * dt)
         net.rhs_from_fine(sl, xF[n - 1], dt)
         ctx.step(sl, dt)
         Xr.append(net.correct(sl, dt, debug=True)["inputs"])
         Dr.append(net.targets(sl, xF[n]))
     sl.close()
-    Xr, Dr = np.stack(Xr), np.stack(Dr)
+    return np.stack(Xr), np.stack(Dr)
+
+
+def standardisation(net, Xr, Dr):
+    """Per-channel (mu, sigma) of the raw inputs and the two output scales,
+    and their per-column expansions."""
+    import numpy as np
+    S2 = net.n_out // 2
+    nch = (net.n_in - net.n_stats) // (S2 - 1)        # nodal channels (6 block, 5 cell)
+    nft = net.n_stats - nch
     mu = np.array([Xr[..., c * S2:(c + 1) * S2].mean() for c in range(nch)] +
                   [Xr[..., nch * S2 + k].mean() for k in range(nft)])
     sg = np.array([Xr[..., c * S2:(c + 1) * S2].std() for c in range(nch)] +
@@ -264,26 +265,50 @@ def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
     mu_f = np.concatenate([np.repeat(mu[:nch], S2), mu[nch:]]).astype(np.float32)
     sg_f = np.concatenate([np.repeat(sg[:nch], S2), sg[nch:]]).astype(np.float32)
     os_f = np.concatenate([np.repeat(osc[0], S2), np.repeat(osc[1], S2)]).astype(np.float32)
+    return (mu, sg, osc), (mu_f, sg_f, os_f)
+
+
+class Fitter:
+    """BPTT + Adam on device-resident sequences; keeps the wall time of the
+    training iterations alone (each call returns its loss: synchronous)."""
+
+    def __init__(self, net, X, D, ckpt=8):
+        self.net, self.X, self.D = net, X, D
+        self.ckpt = min(ckpt, X.shape[0])
+        self.iters, self.sec = 0, 0.0
+
+    def __call__(self, n_it, lr):
+        import torch
+        loss = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, B = self.X.shape[0], self.X.shape[1]
+        for it in range(n_it):
+            loss = self.net.train_step_dev(self.X.data_ptr(), self.D.data_ptr(), T, B,
+                                           lr=lr if it < 0.75 * n_it else 0.3 * lr, ckpt=self.ckpt)
+        self.sec += time.perf_counter() - t0
+        self.iters += n_it
+        return loss
+
+
+def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
+    """Trains the patch network on the GPU (untimed in the step benchmark):
+    teacher-forced inputs and targets, BPTT with Adam, then DAgger rounds that
+    add the states of free DNN-MG runs."""
+    import numpy as np
+    import torch
+
+    from synthetic import gru_weights
+    N = len(xF) - 1
+    Xr, Dr = teacher_data(ctx, net, xF, L, dt)
+    (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net, Xr, Dr)
     w0 = gru_weights(net.n_in, net.hidden, net.layers, net.n_out, seed=seed, scale=0.5)
     net.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
     X = torch.from_numpy((Xr - mu_f) / sg_f).cuda()
     D = torch.from_numpy(Dr / os_f).cuda()
     del Xr, Dr
-    ck = min(8, N)
-    bptt = {"iters": 0, "sec": 0.0}
-
-    def fit(n_it, lr):
-        loss = None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for it in range(n_it):
-            loss = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1],
-                                      lr=lr if it < 0.75 * n_it else 0.3 * lr, ckpt=ck)
-        bptt["sec"] += time.perf_counter() - t0     # each call returns its loss: synchronous
-        bptt["iters"] += n_it
-        return loss
-
-    first = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1], lr=2e-3, ckpt=ck)
+    fit = Fitter(net, X, D)
+    first = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1], lr=2e-3, ckpt=fit.ckpt)
     loss = fit(iters, 2e-3)
     log(f"net training (teacher forcing): loss {first:.1f} -> {loss:.1f}, {X.shape[1]} sequences")
     for rnd in range(dagger):
@@ -295,79 +320,137 @@ def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
             Xc.append(net.correct(st, dt, debug=True)["inputs"])
             Dc.append(net.targets(st, xF[n]))
         st.close()
-        X = torch.cat([X, torch.from_numpy(np.stack(Xc)).cuda()], dim=1).contiguous()
-        D = torch.cat([D, torch.from_numpy(np.stack(Dc)).cuda()], dim=1).contiguous()
+        fit.X = torch.cat([fit.X, torch.from_numpy(np.stack(Xc)).cuda()], dim=1).contiguous()
+        fit.D = torch.cat([fit.D, torch.from_numpy(np.stack(Dc)).cuda()], dim=1).contiguous()
         loss = fit(iters // 2, 1e-3)
-        log(f"net training (DAgger round {rnd}): loss {loss:.1f}, {X.shape[1]} sequences")
-    del X, D
+        log(f"net training (DAgger round {rnd}): loss {loss:.1f}, {fit.X.shape[1]} sequences")
+    del fit
     torch.cuda.empty_cache()
     return {"sequences_per_round": net.n_patches, "steps": N, "rounds": 1 + dagger,
-            "final_loss": round(float(loss), 3), "bptt_iters": bptt["iters"],
-            "bptt_sec": round(bptt["sec"], 3)}
+            "final_loss": round(float(loss), 3)}
 
 
 TABLE1_SHAPES = ((32, 1), (64, 1), (32, 2), (64, 2), (32, 3), (64, 3))
 
 
 def run_table1(P, args, log):
-    """The network-size sweep of Table 1 / Table 2 on one MI355X: cell
-    patches (one level-L element, I = 51, O = 18) correcting level L + 1, the
-    six GRU shapes; per shape the BPTT training time and DNN-MG steps/s and
-    velocity error against MG(L+1), beside plain MG(L) and MG(L+1)."""
+    """The network-size sweep of Table 1 / Table 2 and the lift comparison of
+    Sec. 3.3 on one MI355X: cell patches (one level-L element, I = 51, O = 18)
+    correcting level F = L + 1, the six GRU shapes.  A fine run MG(F) from
+    rest to t_end gives the reference; each network trains on teacher-forced
+    32-step sequences from [t_train, t_start); MG(L) and every DNN-MG run
+    restart from the fine state at t_start (injected to level L) and run to
+    t_end.  Per run: steps/s, velocity error and the lift's period and phase
+    offset against MG(F) over the last time unit (dnnmg_oscillation)."""
     import numpy as np
     import torch
 
-    from synthetic import channel_obstacle
+    from synthetic import channel_obstacle, gru_weights
     macro = channel_obstacle(args.seed)
     F = args.t1_level
     L = F - 1
-    dt, n_tr, n_ev = args.t1_dt, args.t1_train_steps, args.t1_steps
+    dt = args.t1_dt
+    n_end = int(round(args.t1_end / dt))
+    n_start = int(round(args.t1_start / dt))
+    n_train = int(round(args.t1_train_from / dt))
+    seq = 32
+    n_train = n_start - (n_start - n_train) // seq * seq           # whole sequences
+    w0 = n_end - int(round(1.0 / dt))                              # analysis window [t_end - 1, t_end]
     ctx = P.Context(precision=1, nu=macro.nu, jacobian_reuse=args.jacobian_reuse)
     ctx.setup_mesh(macro, F)
-    sf = ctx.state(F)
-    xF = [sf.get()[0]]
-    for _ in range(n_ev):
-        ctx.step(sf, dt)
-        xF.append(sf.get()[0])
-    sf.close()
+    nL = ctx.level_info(L)[0]
 
-    def timed(level, net=None):
-        st = ctx.state(level)
+    def lift_of(st):
+        return float(st.functionals(1)[2][0])
+
+    sf = ctx.state(F)
+    xF, liftF = [sf.get()[0]], [0.0]
+    fine_sec = 0.0
+    for _ in range(n_end):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(sf, dt)
+        torch.cuda.synchronize()
+        fine_sec += time.perf_counter() - t0
+        xF.append(sf.get()[0])
+        liftF.append(lift_of(sf))
+    sf.close()
+    osc_F = P.oscillation(liftF[w0:], w0 * dt, dt)
+
+    def restart(net):
+        st = ctx.state(L)
+        st.set(xF[n_start][:3 * nL], n_start * dt)
         if net is not None:
             net.reset(st)
+            net.rhs_from_fine(st, xF[n_start], dt)
+        return st
+
+    def coarse_run(net=None):
+        """Restart at t_start from the fine state: a timed pass (steps and
+        corrections only), then a pass that also reads the states back; (steps/s,
+        mean velocity error over the window, lift oscillation)."""
+        st = restart(net)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        run_steps(ctx, st, n_ev, dt, net)
+        run_steps(ctx, st, n_end - n_start, dt, net)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         st.close()
-        return n_ev / sec
-
-    def errors(net=None):
-        st = ctx.state(L)
-        if net is not None:
-            net.reset(st)
-        e = []
-        for n in range(1, n_ev + 1):
+        st = restart(net)
+        lift, err = [], []
+        for n in range(n_start + 1, n_end + 1):
             ctx.step(st, dt)
             corr = net.correct(st, dt, debug=True)["correction"] if net is not None else None
-            e.append(velocity_error(ctx, st.get()[0], L, F, xF[n], corr))
+            xl = st.get()[0]
+            if n >= w0:
+                err.append(velocity_error(ctx, xl, L, F, xF[n], corr))
+                lift.append(float(ctx.functionals(F, fine_state(ctx, xl, L, F, corr), 1)[2][0]))
         st.close()
-        return float(np.mean(e[n_tr:])) if n_ev > n_tr else float(np.mean(e))
+        return (n_end - n_start) / sec, float(np.mean(err)), P.oscillation(lift, w0 * dt, dt)
 
-    out = {"coarse_level": L, "fine_level": F, "dt": dt, "train_steps": n_tr, "eval_steps": n_ev,
-           "coarse_dofs": 3 * ctx.level_info(L)[0], "fine_dofs": 3 * ctx.level_info(F)[0],
-           "mg_fine_steps_per_s": round(timed(F), 2), "mg_coarse_steps_per_s": round(timed(L), 2),
-           "mg_coarse_err": round(errors(), 6), "nets": []}
+    def phase(osc):
+        """(period, first-maximum offset against MG(F) in periods of MG(F))."""
+        off = (osc[0] - osc_F[0]) / osc_F[1]
+        return round(osc[1], 5), round(float(off - np.round(off)), 4)
+
+    sps_L, err_L, osc_L = coarse_run()
+    out = {"coarse_level": L, "fine_level": F, "dt": dt, "t_train": [n_train * dt, n_start * dt],
+           "t_run": [n_start * dt, n_end * dt], "window": [w0 * dt, n_end * dt],
+           "coarse_dofs": 3 * nL, "fine_dofs": 3 * ctx.level_info(F)[0],
+           "mg_fine": {"steps_per_s": round(n_end / fine_sec, 2), "lift_period": round(osc_F[1], 5)},
+           "mg_coarse": {"steps_per_s": round(sps_L, 2), "vel_err": round(err_L, 6),
+                         "lift_period": phase(osc_L)[0], "lift_phase_offset": phase(osc_L)[1]},
+           "nets": []}
+    log(f"table1 MG(F): {out['mg_fine']}; MG(L): {out['mg_coarse']}")
+    probe = P.Net(ctx, L, 1, 32, 1, patch="cell")
+    Xr, Dr = teacher_data(ctx, probe, xF[n_train - 1:n_start + 1], L, dt, t0=(n_train - 1) * dt)
+    probe.close()
+    nseq = Xr.shape[0] // seq
+    Xr = Xr[:nseq * seq].reshape(nseq, seq, *Xr.shape[1:]).transpose(1, 0, 2, 3).reshape(seq, -1, Xr.shape[2])
+    Dr = Dr[:nseq * seq].reshape(nseq, seq, *Dr.shape[1:]).transpose(1, 0, 2, 3).reshape(seq, -1, Dr.shape[2])
     for H, layers in TABLE1_SHAPES:
         net = P.Net(ctx, L, 1, H, layers, patch="cell")
-        info = train_dnnmg(ctx, net, xF[:n_tr + 1], L, dt, args.t1_iters, 1, args.seed, log)
+        (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net, Xr, Dr)
+        net.set_weights(gru_weights(net.n_in, H, layers, net.n_out, seed=args.seed, scale=0.5),
+                        mu=mu, sigma=sg, out_scale=osc)
+        X = torch.from_numpy(np.ascontiguousarray((Xr - mu_f) / sg_f)).cuda()
+        D = torch.from_numpy(np.ascontiguousarray(Dr / os_f)).cuda()
+        fit = Fitter(net, X, D)
+        loss = fit(args.t1_iters, 2e-3)
+        bptt_ms = 1e3 * fit.sec / fit.iters
+        del fit, X, D
+        sps, err, osc_d = coarse_run(net)
+        per, off = phase(osc_d)
         row = {"hidden": H, "layers": layers, "params": net.n_params, "n_in": net.n_in, "n_out": net.n_out,
-               "bptt_ms_per_iter": round(1e3 * info["bptt_sec"] / info["bptt_iters"], 3),
-               "bptt_sec": info["bptt_sec"], "final_loss": info["final_loss"],
-               "dnnmg_steps_per_s": round(timed(L, net), 2), "dnnmg_err": round(errors(net), 6)}
+               "sequences": Xr.shape[1], "seq": seq, "bptt_iters": args.t1_iters,
+               "bptt_ms_per_iter": round(bptt_ms, 3), "train_sec": round(bptt_ms * args.t1_iters / 1e3, 2),
+               "final_loss": round(float(loss), 3),
+               "steps_per_s": round(sps, 2), "vel_err": round(err, 6), "lift_period": per,
+               "lift_phase_offset": off}
         log(f"table1 {H}x{layers}: {row}")
         out["nets"].append(row)
         net.close()
+        torch.cuda.empty_cache()
     ctx.close()
     return out
 
@@ -402,9 +485,10 @@ def main():
                     help="network-size sweep (Table 1 shapes on cell patches, untimed leg)")
     ap.add_argument("--t1-level", type=int, default=3)
     ap.add_argument("--t1-dt", type=float, default=0.01)
-    ap.add_argument("--t1-train-steps", type=int, default=32)
-    ap.add_argument("--t1-steps", type=int, default=64)
-    ap.add_argument("--t1-iters", type=int, default=200)
+    ap.add_argument("--t1-train-from", type=float, default=4.0)
+    ap.add_argument("--t1-start", type=float, default=7.0)
+    ap.add_argument("--t1-end", type=float, default=10.0)
+    ap.add_argument("--t1-iters", type=int, default=600)
     ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
                     help="keep Newton's Jacobians across iterations and steps while the "
                          "residual contracts by 0.1 or better (0: rebuild every step)")

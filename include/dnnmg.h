@@ -388,6 +388,21 @@ int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 int dnnmg_level_stats(const dnnmg_ctx *ctx, int level, long long *q_blocks, long long *x_entries,
                       long long *q_slots, long long *x_slots);
 
+/* ------------------------------------------------------- diagnostics
+ * Oscillation of a sampled functional f[i] = J(t0 + i dt), i < n (Sec. 3.3:
+ * the lift over the periodic limit cycle, where runs are compared after
+ * aligning their first maximum in the window).  One maximum per excursion
+ * above the series mean (a maximal run of samples above the mean, with a
+ * sample at or below the mean on both sides inside the window) whose largest
+ * sample exceeds the midpoint of the mean and the largest sample of the
+ * series; its time comes from the parabola through that sample and its two
+ * neighbours.  Outputs (NULL skipped): time of the first maximum (NaN if
+ * none), mean period = (last - first) / (count - 1) (NaN if fewer than two),
+ * and the number of maxima.  Host arrays only; no device work.  DNNMG_EINVAL
+ * for n < 3, dt <= 0 or non-finite samples. */
+int dnnmg_oscillation(const double *f, int n, double t0, double dt, double *t_first_max,
+                      double *period, int *n_max);
+
 #ifdef __cplusplus
 }
 #endif

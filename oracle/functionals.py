@@ -10,11 +10,22 @@ networks' accuracy), FP64 numpy.  Test infrastructure only.
   fluid), nu the kinematic viscosity of the problem (the paper writes 1/Re),
   grad v the full velocity gradient, (grad v n)_i = sum_j dv_i/dx_j n_j.
 
+* Oscillation of a sampled functional (Sec. 3.3 compares the lift of the
+  runs over the periodic limit cycle after aligning their first maximum in
+  the window): reading F3 below.
+
 Readings (paper silent): F1 the boundary integral is taken over the polygonal
 boundary of the mesh, each boundary edge with 2-point Gauss quadrature, grad v
 and p from the Q1 fields of the fluid cell the edge belongs to (a line
 integral of the discrete fields, not a residual-based evaluation); F2 the
-normal of an edge is the outward normal of its cell.
+normal of an edge is the outward normal of its cell; F3 a series has one
+maximum per excursion above its mean (a maximal run of samples above the
+mean, bounded inside the window by samples at or below it) that peaks above
+the midpoint of the mean and the series maximum (small wiggles of a noisy
+signal do not count); it sits at the vertex of the parabola through the
+excursion's largest sample and its two neighbours; the shedding period is the
+mean spacing of the maxima, the phase offset of two runs the difference of
+their first maxima.
 """
 from __future__ import annotations
 
@@ -80,3 +91,33 @@ def drag_lift(level: Level, x: np.ndarray, nu, n_obstacles: int):
             drag[k] -= w * tx
             lift[k] -= w * ty
     return drag, lift
+
+
+def oscillation(f, t0: float, dt: float):
+    """(time of the first maximum, mean period, number of maxima) of
+    f[i] = J(t0 + i dt) under reading F3; NaN where undefined."""
+    f = np.asarray(f, dtype=np.float64)
+    mean = f.mean()
+    high = 0.5 * (mean + f.max())
+    above = f > mean
+    times = []
+    # excursions: runs of `above`, kept when bounded on both sides
+    starts = [i for i in range(1, len(f)) if above[i] and not above[i - 1]]
+    for b in starts:
+        e = b
+        while e < len(f) and above[e]:
+            e += 1
+        if e == len(f):
+            break
+        k = b + int(np.argmax(f[b:e]))
+        if f[k] <= high:
+            continue
+        y0, y1, y2 = f[k - 1], f[k], f[k + 1]
+        # vertex of the parabola through (-1, y0), (0, y1), (1, y2)
+        curv = y0 - 2 * y1 + y2
+        s = (y0 - y2) / (2 * curv) if curv < 0 else 0.0
+        times.append(t0 + (k + s) * dt)
+    if not times:
+        return float("nan"), float("nan"), 0
+    period = (times[-1] - times[0]) / (len(times) - 1) if len(times) > 1 else float("nan")
+    return times[0], period, len(times)

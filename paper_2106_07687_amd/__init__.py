@@ -3,6 +3,8 @@
 The numerical work runs in libdnnmg.so (hand-written gfx950 HIP kernels).  This
 package holds only the ctypes binding (`_lib`) and the build script (`build`).
 """
-from ._lib import (Context, State, Net, Batch, DnnmgError, load, header_symbols, LIB_PATH)
+from ._lib import (Context, State, Net, Batch, DnnmgError, load, header_symbols, LIB_PATH,
+                   oscillation)
 
-__all__ = ["Context", "State", "Net", "Batch", "DnnmgError", "load", "header_symbols", "LIB_PATH"]
+__all__ = ["Context", "State", "Net", "Batch", "DnnmgError", "load", "header_symbols", "LIB_PATH",
+           "oscillation"]

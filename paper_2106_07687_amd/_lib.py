@@ -101,6 +101,7 @@ _SIGS = {
                                          C.POINTER(_P)]),
     "dnnmg_net_patch_info": (C.c_int, [_P, _IP, _IP, _IP]),
     "dnnmg_net_destroy": (C.c_int, [_P]),
+    "dnnmg_oscillation": (C.c_int, [_DP, C.c_int, C.c_double, C.c_double, _DP, _DP, _IP]),
     "dnnmg_net_info": (C.c_int, [_P, _IP, _IP, _IP, C.POINTER(C.c_longlong)]),
     "dnnmg_net_set_weights": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
     "dnnmg_net_get_weights": (C.c_int, [_P, _FP]),
@@ -193,6 +194,18 @@ def _set_fields(p, kw):
         if k not in names:
             raise TypeError(f"unknown solver parameter {k!r}")
         setattr(p, k, v)
+
+
+def oscillation(f, t0, dt):
+    """(time of the first maximum, mean period, number of maxima) of the
+    sampled functional f[i] = J(t0 + i dt) (dnnmg_oscillation)."""
+    lib = load()
+    f = _f64(f)
+    a, b, n = C.c_double(), C.c_double(), C.c_int()
+    rc = lib.dnnmg_oscillation(_dp(f), f.size, t0, dt, C.byref(a), C.byref(b), C.byref(n))
+    if rc != OK:
+        raise DnnmgError(rc, "dnnmg_oscillation: invalid series")
+    return a.value, b.value, n.value
 
 
 class Context:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdnnmg.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["mesh.cpp", "solver.hip", "abi.hip", "dnnmg.hip", "train.hip", "batch.hip"]
+SOURCES = ["mesh.cpp", "diagnostics.cpp", "solver.hip", "abi.hip", "dnnmg.hip", "train.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{SRC}"]

@@ -55,3 +55,21 @@ def test_calls_out_of_order_and_bad_mesh_are_rejected_without_device_work():
     with pytest.raises(P.DnnmgError):
         ctx.setup_mesh(bad2, 1)
     ctx.close()
+
+
+def test_oscillation_entry_point_matches_oracle():
+    """dnnmg_oscillation is host code: callable without a GPU."""
+    from oracle import functionals as F
+    rng = np.random.default_rng(11)
+    t = 9.0 + 0.005 * np.arange(400)
+    y = 0.2 + np.sin(2 * np.pi * 3.3 * t + 0.4) + 1e-3 * rng.standard_normal(t.size)
+    got = P.oscillation(y, 9.0, 0.005)
+    ref = F.oscillation(y, 9.0, 0.005)
+    assert got[2] == ref[2] and got[2] >= 6
+    assert abs(got[0] - ref[0]) < 1e-12 and abs(got[1] - ref[1]) < 1e-12
+    flat = P.oscillation(np.zeros(10), 0.0, 0.1)
+    assert flat[2] == 0 and np.isnan(flat[0]) and np.isnan(flat[1])
+    for bad in (dict(f=np.zeros(2), dt=0.1), dict(f=np.zeros(5), dt=0.0),
+                dict(f=np.array([0.0, np.nan, 1.0, 0.0]), dt=0.1)):
+        with pytest.raises(P.DnnmgError):
+            P.oscillation(bad["f"], 0.0, bad["dt"])

@@ -88,3 +88,53 @@ def test_viscous_drag_converges_to_divergence_theorem_value():
         errs.append(max(abs(d[0] - exact_drag), abs(lft[0] - exact_lift)))
     assert errs[0] > errs[1] > errs[2], errs
     assert errs[1] / errs[2] > 1.6, errs
+
+
+# ---- oscillation diagnostics (reading F3)
+
+def _wave(f0, phase, t0, dt, n, offset=0.3, harmonic=0.0):
+    t = t0 + dt * np.arange(n)
+    return offset + np.sin(2 * np.pi * f0 * t + phase) + harmonic * np.sin(4 * np.pi * f0 * t)
+
+
+def test_oscillation_of_a_sinusoid():
+    """Maxima of sin(2 pi f t + phase) sit at t = (1/4 - phase / 2 pi + k) / f;
+    the parabola locates them to O((omega dt)^2 dt)."""
+    f0, phase, t0, dt = 3.1, -1.0, 9.0, 0.005       # three whole excursions in [9, 10]
+    y = _wave(f0, phase, t0, dt, 201)
+    t1, per, cnt = F.oscillation(y, t0, dt)
+    k = np.ceil((t0 - (0.25 - phase / (2 * np.pi)) / f0) * f0)
+    exact = (0.25 - phase / (2 * np.pi) + k) / f0
+    assert cnt == 3
+    assert abs(t1 - exact) < 1e-5
+    assert abs(per - 1 / f0) < 1e-6
+
+
+def test_oscillation_phase_shift_and_degenerate_series():
+    f0, dt = 2.0, 0.01
+    a = F.oscillation(_wave(f0, 0.0, 0.0, dt, 300), 0.0, dt)
+    b = F.oscillation(_wave(f0, -0.5, 0.0, dt, 300), 0.0, dt)
+    assert abs((b[0] - a[0]) - 0.5 / (2 * np.pi * f0)) < 1e-5      # a lag of phase / omega
+    # a harmonic that does not create extra maxima above the mean
+    h = F.oscillation(_wave(f0, 0.0, 0.0, dt, 300, harmonic=0.1), 0.0, dt)
+    assert h[2] == a[2] and abs(h[1] - a[1]) < 1e-3
+    t1, per, cnt = F.oscillation(np.full(50, 0.4), 0.0, dt)      # no maxima
+    assert cnt == 0 and np.isnan(t1) and np.isnan(per)
+    t1, per, cnt = F.oscillation(np.sin(np.linspace(-np.pi / 2, 3 * np.pi / 2, 41)), 0.0, 0.1)
+    assert cnt == 1 and abs(t1 - 2.0) < 1e-12 and np.isnan(per)           # one maximum
+    # maxima cut by the window's ends do not count
+    t1, per, cnt = F.oscillation(np.cos(np.linspace(0, 2 * np.pi, 81)), 0.0, 0.1)
+    assert cnt == 0
+
+
+def test_oscillation_ignores_wiggles():
+    """A fast small ripple adds local maxima but no excursions that peak
+    above the mean/maximum midpoint: the shedding period is unchanged."""
+    f0, dt = 3.0, 0.002
+    t = dt * np.arange(1000)
+    clean = -np.cos(2 * np.pi * f0 * t)              # the window starts at a trough
+    rippled = clean + 0.05 * np.sin(2 * np.pi * 40 * f0 * t + 0.3)
+    a = F.oscillation(clean, 0.0, dt)
+    b = F.oscillation(rippled, 0.0, dt)
+    assert a[2] == b[2] == 6
+    assert abs(a[1] - 1 / f0) < 1e-6 and abs(b[1] - 1 / f0) < 2e-3
