@@ -13,6 +13,7 @@ Inputs: channel with one obstacle, seed 0, level 3 (the FP64 parity
 workload), from rest with the ramped inflow.
 """
 import ctypes as C
+import os
 
 import numpy as np
 import pytest
@@ -131,7 +132,8 @@ def test_stale_jacobian_behind_the_library_still_converges():
     for _ in range(2):                             # keeps a Jacobian of the start-up flow
         ctx.step(st, DT)
     t = st.get()[1]
-    hip = C.CDLL("/opt/rocm/lib/libamdhip64.so.7")
+    # the HIP runtime the library already runs on (never a second copy)
+    hip = C.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | os.RTLD_LAZY)
     src = np.ascontiguousarray(x15)
     rc = hip.hipMemcpy(C.c_void_p(st.device_ptr()), C.c_void_p(src.ctypes.data),
                        C.c_size_t(src.nbytes), 1)  # host to device, synchronous
