@@ -267,6 +267,14 @@ class Ctx {
   }
   // FP64 scratch for residual evaluation / Newton on the finest used level
   DevBuf<double> R, xo_save, tmp64a, tmp64b;
+  DevBuf<double> cellvec;   // element vectors of the residual / Rhs (12 per cell), then
+                            // the LPS vectors of the patches (9 per patch)
+  // cellvec sized for level l (allocated on first use)
+  double *cell_vectors(int l) {
+    const size_t need = 12 * static_cast<size_t>(levels[l]->h.C) + 9 * static_cast<size_t>(levels[l]->h.NP);
+    if (cellvec.n < need) cellvec.alloc(need);
+    return cellvec.p;
+  }
   DevBuf<double> red_partial, red_out;
 
   Phys phys(double dt, double t) const {

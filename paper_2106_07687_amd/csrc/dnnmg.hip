@@ -216,9 +216,11 @@ void rhs_and_restrict(Net &n, State &st, double dt) {
   {
     ProfScope ps(c.prof, s, "dnnmg_rhs", n.F);
     c.ensure_lps(n.F, dt);
-    hipLaunchKernelGGL(k_rhs, dim3(blocks(LF.h.N, 128)), dim3(128), 0, s, LF.view(), c.phys(dt, st.t + dt),
-                       n.vc.p, n.bF.p);
-    check(hipGetLastError(), "k_rhs");
+    double *E = c.cell_vectors(n.F);
+    hipLaunchKernelGGL(k_cell_vectors<1>, dim3(blocks(LF.h.C, 256)), dim3(256), 0, s, LF.view(),
+                       c.phys(dt, st.t + dt), n.vc.p, nullptr, 0, E);
+    hipLaunchKernelGGL(k_rhs_nodes, dim3(blocks(LF.h.N, 256)), dim3(256), 0, s, LF.view(), E, n.bF.p);
+    check(hipGetLastError(), "rhs");
   }
   const double *src = n.bF.p;
   for (int l = n.F; l > n.L; --l) {

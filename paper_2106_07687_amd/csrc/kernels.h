@@ -170,70 +170,146 @@ __global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *
 }
 
 // -------------------------------------------------------------- residual
-// R = f_n - A_n(x) for every node (eqs. varform, varformv), gathered per node
-// over the node's cells (row a of each element) and patches; Dirichlet
-// velocity rows hold g(t_new) - x.  FP64 throughout.
-__global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const double *__restrict__ x,
-                           const double *__restrict__ xo, const double *__restrict__ rhs,
-                           const double *__restrict__ sP, double *__restrict__ R) {
+// R = f_n - A_n(x) for every node (eqs. varform, varformv) and the Rhs of
+// Algorithm 1; Dirichlet velocity rows hold g(t_new) - x.  FP64 throughout.
+//
+// Element vectors of the nonlinear residual and of Rhs (eqs. varform,
+// varformv; 2x2 Gauss): one thread per cell evaluates each quadrature point
+// once and writes the cell's contribution to the rows of its 4 vertices a as
+// E[12 c + 3a + f] (f = u, v, p), so that a node reads 24 contiguous bytes per
+// cell; a node pass then sums its cells' entries in its adjacency order (no
+// atomics).  The
+// viscosity of row a is that of vertex a (per-node viscosity of batches).
+// kKind 0: the A_n(x) part of the residual rows, with the old-state terms
+// (old_terms = 1, x_old = xo) or without them (old_terms = 0: a DNN-MG
+// right-hand side replaces them); kKind 1: the explicit velocity rows of f_n
+// for v = x (Rhs of Algorithm 1; p entries not written).
+// Launched with 256 threads per workgroup.
+template <int kKind>
+__global__ void __launch_bounds__(256) k_cell_vectors(LevelView L, Phys ph, const double *__restrict__ x,
+                                                      const double *__restrict__ xo, int old_terms,
+                                                      double *__restrict__ E) {
+  __shared__ double stage[256 * 12];
+  const int c0 = blockIdx.x * 256, t = threadIdx.x;
+  const int c = c0 + t;
+  const bool live = c < L.C;
+  const int4 cn = L.cells[live ? c : 0];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  const double th = ph.theta, idt = ph.inv_dt;
+  const double tho = kKind == 1 ? 1.0 - th : (old_terms ? 1.0 - th : 0.0);
+  double X[4], Y[4], U[4], V[4], P[4], Uo[4], Vo[4], nu[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const double2 pt = L.xy[nn[b]];
+    X[b] = pt.x;
+    Y[b] = pt.y;
+    U[b] = x[3 * nn[b]];
+    V[b] = x[3 * nn[b] + 1];
+    P[b] = kKind == 0 ? x[3 * nn[b] + 2] : 0.0;
+    Uo[b] = kKind == 0 && old_terms ? xo[3 * nn[b]] : 0.0;
+    Vo[b] = kKind == 0 && old_terms ? xo[3 * nn[b] + 1] : 0.0;
+    nu[b] = L.nnu ? L.nnu[nn[b]] : ph.nu;
+  }
+  double Au[4] = {0, 0, 0, 0}, Av[4] = {0, 0, 0, 0}, Ap[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double N[4], gx[4], gy[4], det;
+    q1_point(X, Y, q, N, gx, gy, det);
+    double u = 0, v = 0, p = 0, uo = 0, vo = 0;
+    double ux = 0, uy = 0, vx = 0, vy = 0, uox = 0, uoy = 0, vox = 0, voy = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      u += N[b] * U[b];
+      v += N[b] * V[b];
+      p += N[b] * P[b];
+      uo += N[b] * Uo[b];
+      vo += N[b] * Vo[b];
+      ux += gx[b] * U[b];
+      uy += gy[b] * U[b];
+      vx += gx[b] * V[b];
+      vy += gy[b] * V[b];
+      uox += gx[b] * Uo[b];
+      uoy += gy[b] * Uo[b];
+      vox += gx[b] * Vo[b];
+      voy += gy[b] * Vo[b];
+    }
+    if (kKind == 0) {
+      const double mu = idt * (u - uo) + th * (u * ux + v * uy) + tho * (uo * uox + vo * uoy);
+      const double mv = idt * (v - vo) + th * (u * vx + v * vy) + tho * (uo * vox + vo * voy);
+      const double su = th * ux + tho * uox, tu = th * uy + tho * uoy;
+      const double sv = th * vx + tho * vox, tv = th * vy + tho * voy;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        Au[a] += det * (mu * N[a] + nu[a] * (su * gx[a] + tu * gy[a]) - p * gx[a]);
+        Av[a] += det * (mv * N[a] + nu[a] * (sv * gx[a] + tv * gy[a]) - p * gy[a]);
+        Ap[a] += det * (ux + vy) * N[a];
+      }
+    } else {
+      const double mu = idt * u - tho * (u * ux + v * uy), mv = idt * v - tho * (u * vx + v * vy);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        Au[a] += det * (mu * N[a] - tho * nu[a] * (ux * gx[a] + uy * gy[a]));
+        Av[a] += det * (mv * N[a] - tho * nu[a] * (vx * gx[a] + vy * gy[a]));
+      }
+    }
+  }
+  // the block's 256 x 12 values are contiguous in E: stage them in LDS and
+  // write them with consecutive lanes on consecutive addresses
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    stage[12 * t + 3 * a] = Au[a];
+    stage[12 * t + 3 * a + 1] = Av[a];
+    stage[12 * t + 3 * a + 2] = kKind == 0 ? Ap[a] : 0.0;
+  }
+  __syncthreads();
+  const size_t base = 12 * static_cast<size_t>(c0), end = 12 * static_cast<size_t>(L.C);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const size_t idx = base + k * 256 + t;
+    if (idx < end) E[idx] = stage[k * 256 + t];
+  }
+}
+
+// LPS rows of the pressure equation per patch: S[q NP + P] = sum_m
+// s_P(q, m) p_m over the patch's 9 nodes (one thread per patch; the sums of
+// the node rows then add these in the node's patch order).
+__global__ void __launch_bounds__(256) k_lps_vectors(LevelView L, const double *__restrict__ sP,
+                                                     const double *__restrict__ x, double *__restrict__ S) {
+  const int P = blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= L.NP) return;
+  double p[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) p[m] = x[3 * L.patch_nodes[9 * P + m] + 2];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) s += sP[(9 * q + m) * L.NP + P] * p[m];
+    S[q * static_cast<size_t>(L.NP) + P] = s;
+  }
+}
+
+// Residual rows R = f_n - A_n(x) (eq. nonlinearshort) from the element
+// vectors of k_cell_vectors<0> and the patch vectors of k_lps_vectors: per
+// node the sum of its cells' entries, then of its patches' LPS entries, the
+// DNN-MG right-hand side if given, and the Dirichlet rows R = g - x.
+__global__ void __launch_bounds__(256) k_residual_nodes(LevelView L, Phys ph, const double *__restrict__ x,
+                                                        const double *__restrict__ rhs,
+                                                        const double *__restrict__ S,
+                                                        const double *__restrict__ E, double *__restrict__ R) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
-  const double th = ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
   double Au = 0.0, Av = 0.0, Ap = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
-    const int4 cn = L.cells[c];
-    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
-    double X[4], Y[4], U[4], V[4], P[4], Uo[4], Vo[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double2 p = L.xy[nn[b]];
-      X[b] = p.x;
-      Y[b] = p.y;
-      U[b] = x[3 * nn[b]];
-      V[b] = x[3 * nn[b] + 1];
-      P[b] = x[3 * nn[b] + 2];
-      Uo[b] = rhs ? 0.0 : xo[3 * nn[b]];
-      Vo[b] = rhs ? 0.0 : xo[3 * nn[b] + 1];
-    }
-    const double tho = rhs ? 0.0 : 1.0 - th;   // old-state terms only without rhs
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double N[4], gx[4], gy[4], det;
-      q1_point(X, Y, q, N, gx, gy, det);
-      double u = 0, v = 0, p = 0, uo = 0, vo = 0;
-      double ux = 0, uy = 0, vx = 0, vy = 0, uox = 0, uoy = 0, vox = 0, voy = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        u += N[b] * U[b];
-        v += N[b] * V[b];
-        p += N[b] * P[b];
-        uo += N[b] * Uo[b];
-        vo += N[b] * Vo[b];
-        ux += gx[b] * U[b];
-        uy += gy[b] * U[b];
-        vx += gx[b] * V[b];
-        vy += gy[b] * V[b];
-        uox += gx[b] * Uo[b];
-        uoy += gy[b] * Uo[b];
-        vox += gx[b] * Vo[b];
-        voy += gy[b] * Vo[b];
-      }
-      const double mu = idt * (u - uo) + th * (u * ux + v * uy) + tho * (uo * uox + vo * uoy);
-      const double mv = idt * (v - vo) + th * (u * vx + v * vy) + tho * (uo * vox + vo * voy);
-      const double Na = N[a], ga = gx[a], ha = gy[a];
-      Au += det * (mu * Na + nu * ((th * ux + tho * uox) * ga + (th * uy + tho * uoy) * ha) - p * ga);
-      Av += det * (mv * Na + nu * ((th * vx + tho * vox) * ga + (th * vy + tho * voy) * ha) - p * ha);
-      Ap += det * (ux + vy) * Na;
-    }
+    const double *ec = E + 12 * static_cast<size_t>(c) + 3 * a;
+    Au += ec[0];
+    Av += ec[1];
+    Ap += ec[2];
   }
   for (int e = L.padj_ptr[i]; e < L.padj_ptr[i + 1]; ++e) {
     const int Pp = L.padj[e] / 9, q = L.padj[e] % 9;
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < 9; ++m)
-      s += sP[(9 * q + m) * L.NP + Pp] * x[3 * L.patch_nodes[9 * Pp + m] + 2];
-    Ap += s;
+    Ap += S[q * static_cast<size_t>(L.NP) + Pp];
   }
   double ru = -Au, rv = -Av;
   if (rhs) {
@@ -252,46 +328,17 @@ __global__ void __launch_bounds__(128) k_residual(LevelView L, Phys ph, const do
   R[3 * i + 2] = -Ap;
 }
 
-// Explicit part of the velocity rows of f_n (eq. varformv) for a given
-// velocity field v: 1/k (v, phi) - (1 - theta)((v.grad) v, phi)
-// - (1 - theta) nu (grad v, grad phi); pressure rows 0.  This is Rhs() of
-// Algorithm 1 without external force.
-__global__ void __launch_bounds__(128) k_rhs(LevelView L, Phys ph, const double *__restrict__ xv, double *__restrict__ out) {
+// Rhs rows from the element vectors of k_cell_vectors<1>; pressure rows 0.
+__global__ void __launch_bounds__(256) k_rhs_nodes(LevelView L, const double *__restrict__ E,
+                                                   double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.N) return;
-  const double tho = 1.0 - ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
   double fu = 0.0, fv = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
-    const int4 cn = L.cells[c];
-    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
-    double X[4], Y[4], U[4], V[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double2 p = L.xy[nn[b]];
-      X[b] = p.x;
-      Y[b] = p.y;
-      U[b] = xv[3 * nn[b]];
-      V[b] = xv[3 * nn[b] + 1];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double N[4], gx[4], gy[4], det;
-      q1_point(X, Y, q, N, gx, gy, det);
-      double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        u += N[b] * U[b];
-        v += N[b] * V[b];
-        ux += gx[b] * U[b];
-        uy += gy[b] * U[b];
-        vx += gx[b] * V[b];
-        vy += gy[b] * V[b];
-      }
-      const double Na = N[a], ga = gx[a], ha = gy[a];
-      fu += det * ((idt * u - tho * (u * ux + v * uy)) * Na - tho * nu * (ux * ga + uy * ha));
-      fv += det * ((idt * v - tho * (u * vx + v * vy)) * Na - tho * nu * (vx * ga + vy * ha));
-    }
+    const double *ec = E + 12 * static_cast<size_t>(c) + 3 * a;
+    fu += ec[0];
+    fv += ec[1];
   }
   out[3 * i] = fu;
   out[3 * i + 1] = fv;

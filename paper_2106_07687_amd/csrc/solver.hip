@@ -236,10 +236,15 @@ void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, 
                    double dt, double *Rout) {
   ensure_lps(l, dt);
   DevLevel &L = *levels[l];
+  double *E = cell_vectors(l);
+  double *S = E + 12 * static_cast<size_t>(L.h.C);
   ProfScope ps(prof, stream, "residual", l);
-  hipLaunchKernelGGL(k_residual, dim3(blocks(L.h.N, 128)), dim3(128), 0, stream, L.view(),
-                     phys(dt, t_new), x, xo, rhs, L.sP.p, Rout);
-  LAUNCH_CHECK("k_residual");
+  hipLaunchKernelGGL(k_cell_vectors<0>, dim3(blocks(L.h.C, 256)), dim3(256), 0, stream, L.view(),
+                     phys(dt, t_new), x, xo, rhs ? 0 : 1, E);
+  hipLaunchKernelGGL(k_lps_vectors, dim3(blocks(L.h.NP, 256)), dim3(256), 0, stream, L.view(), L.sP.p, x, S);
+  hipLaunchKernelGGL(k_residual_nodes, dim3(blocks(L.h.N, 256)), dim3(256), 0, stream, L.view(),
+                     phys(dt, t_new), x, rhs, S, E, Rout);
+  LAUNCH_CHECK("residual");
 }
 
 // ------------------------------------------------------------------ Solver
