@@ -69,3 +69,67 @@ def test_mixed_precision_at_full_size(level):
     st.close()
     c32.close()
     c64.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_dnnmg_correction_at_full_size():
+    """One DNN-MG correction at the size of the inference workload (coarse
+    level 5, fine level 7, 21,504 block patches, GRU 128 x 2, BF16 MFMA) in
+    the mixed-precision context the benchmark uses, against the oracle's
+    correction (Algorithm 1) on a developed flow state: network inputs to
+    1e-6 (FP32), network output to 3e-2 with cosine >= 0.999 (the BF16 bar),
+    and everything downstream of the network output, fed the GPU's output,
+    to 1e-12 (FP64)."""
+    import paper_2106_07687_amd as P
+    from oracle import dnnmg
+    from synthetic import gru_weights
+    macro = channel_obstacle(0)
+    L, m, H = 5, 2, 128
+    ctx = P.Context(precision=1, nu=macro.nu, jacobian_reuse=1)
+    ctx.setup_mesh(macro, L + m)
+    lev = mesh.hierarchy(macro, L + m)
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    D = dnnmg.DnnmgOracle(lev, prob, L, m)
+    net = P.Net(ctx, L, m, hidden=H, layers=2)
+    assert (net.n_in, net.n_out, net.n_patches) == (D.n_in, D.n_out, D.n_patches) == (490, 162, 21504)
+    dims = (net.n_in, H, 2, net.n_out)
+    w = gru_weights(*dims, seed=11, scale=0.5).astype(np.float32).astype(np.float64)
+    mu = np.zeros(10, dtype=np.float32)
+    sg = np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0], dtype=np.float32)
+    osc = np.array([1e-3, 1e-3], dtype=np.float32)
+    net.set_weights(w, mu, sg, osc)
+    spec = dnnmg.NetSpec(weights=w, hidden=H, layers=2, mu=mu.astype(np.float64),
+                         sigma=sg.astype(np.float64), out_scale=osc.astype(np.float64))
+    st = ctx.state(L)
+    for _ in range(6):                               # a flow state, not a random field
+        ctx.step(st, DT)
+    x0, t0 = st.get()
+    net.reset(st)                                    # v_prev = P^m x0, h = 0
+    ctx.step(st, DT)
+    xL, t = st.get()
+    out = net.correct(st, DT, debug=True)
+    print(f"[full] dnnmg correction at L={L} F={L + m}: {net.n_patches} patches", flush=True)
+    bL, vc, h1, ex = D.correct(xL, D.prolong(x0), np.zeros((2, D.n_patches, H)), spec, t)
+    e_in = _rel(out["inputs"], ex["Xn"])
+    e_out = _rel(out["outputs"], ex["Y"])
+    Y, Yr = out["outputs"].ravel(), ex["Y"].ravel()
+    cos = float(Y @ Yr / (np.linalg.norm(Y) * np.linalg.norm(Yr)))
+    print(f"[full] inputs {e_in:.2e}, network output {e_out:.2e} (cos {cos:.6f})", flush=True)
+    assert e_in < 1e-6 and e_out < 3e-2 and cos >= 0.999
+    d_ref = D.scatter(out["outputs"].astype(np.float64), spec)
+    assert _rel(out["correction"], d_ref) < 1e-12
+    vc_g = ex["xt"].reshape(-1, 3).copy()
+    vc_g[:, :2] += d_ref
+    vc_g[:, 2] = 0.0
+    bL_ref = D.restrict(D.rhs(vc_g.reshape(-1))).reshape(-1, 3)
+    bL_g = out["rhs_coarse"].reshape(-1, 3)
+    free = ~lev[L].dirichlet_nodes()
+    e_b = _rel(bL_g[free], bL_ref[free])
+    print(f"[full] restricted right-hand side {e_b:.2e}", flush=True)
+    assert e_b < 1e-12
+    st.close()
+    net.close()
+    ctx.close()
