@@ -7,7 +7,7 @@ network evaluation), so the oracle and the HIP path can both consume it
 without sharing any code of the method.
 """
 from .channel import (MacroMesh, channel_obstacle, channel_obstacles, rectangle,
-                      random_state, gru_weights, WORKLOADS)
+                      random_state, gru_weights, training_channel, WORKLOADS)
 
 __all__ = ["MacroMesh", "channel_obstacle", "channel_obstacles", "rectangle",
-           "random_state", "gru_weights", "WORKLOADS"]
+           "random_state", "gru_weights", "training_channel", "WORKLOADS"]

@@ -118,6 +118,16 @@ def channel_obstacle(seed: int, Re: float = 100.0, box: float = 0.1,
                      info=dict(seed=seed, Re=Re, cx=cx, cy=cy, r=r))
 
 
+def training_channel(seed: int, re_range=(80.0, 120.0)) -> MacroMesh:
+    """Geometry of the training workload: channel_obstacle's draws (centre x,
+    centre y, radius) followed by Re ~ U[re_range] from the same PCG64
+    stream."""
+    rng = np.random.default_rng(seed)
+    rng.uniform(size=3)                      # the geometry draws of channel_obstacle
+    Re = rng.uniform(*re_range)
+    return channel_obstacle(seed, Re=Re)
+
+
 def _strip_mesh(obs, n_downstream):
     """Macro mesh of the channel with one or more obstacles in x-disjoint
     strips.  `obs` rows (cx, cy, a, b, phi, w), sorted by cx; w is the
@@ -306,5 +316,6 @@ WORKLOADS = {
     "c4_dnnmg_inference": dict(seeds=(0,), coarse_level=5, fine_level=7, dt=0.005,
                                hidden=128, layers=2, n_in=490, n_out=162),
     "c5_training": dict(seeds=tuple(range(200, 216)), batch=8192, seq=32,
-                        hidden=(64, 128, 256), layers=2, ckpt=8),
+                        hidden=(64, 128, 256), layers=2, ckpt=8, generator="training_channel",
+                        Re=(80.0, 120.0), held_out=(300, 301, 302, 303)),
 }
