@@ -492,6 +492,8 @@ def main():
     ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
                     help="keep Newton's Jacobians across iterations and steps while the "
                          "residual contracts by 0.1 or better (0: rebuild every step)")
+    ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
+                    help="0: additive cell-Vanka, 1: coloured multiplicative cell-Vanka")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured graphs")
     ap.add_argument("--batch-sims", type=int, default=64,
@@ -523,7 +525,7 @@ def main():
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
                     use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
-                    jacobian_reuse=args.jacobian_reuse)
+                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother)
     F = args.level
     if args.profile == "all":
         gmg_keys = dnn_keys = None
@@ -707,7 +709,7 @@ def main():
                    "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
                    "newton_predictor": args.newton_predictor,
-                   "jacobian_reuse": args.jacobian_reuse},
+                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

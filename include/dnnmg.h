@@ -102,6 +102,13 @@ typedef struct {
                              x_n is the same to the tolerance)               */
   double reuse_contraction; /* largest ||R_k|| / ||R_{k-1}|| that keeps a
                              Jacobian, in (0, 1); default 0.1                 */
+  int smoother;           /* 0: additive cell-Vanka (every cell's correction,
+                             averaged over the cells of a node, omega times);
+                             1: coloured multiplicative cell-Vanka (greedy cell
+                             colouring in cell order, no two cells of a colour
+                             share a node; per colour the residual is
+                             recomputed and each cell of the colour adds omega
+                             times its correction); same vanka_omega          */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 

@@ -11,7 +11,12 @@
   application), in the paper's terms plus the readings N3 (V(2,2), additive
   averaged cell-Vanka, omega = 0.6, coarse operators re-discretised at the
   injected iterate, dense LU on level 0):
-  `vanka_sweep`, `vcycle`, `gmres`.
+  `vanka_sweep`, `vcycle`, `gmres`; and the coloured multiplicative variant
+  of the cell-Vanka sweep (`cell_colours`, `vanka_sweep_coloured`): cells in
+  index order take the smallest colour no cell sharing a node has taken
+  (reading N17); per colour the residual is recomputed and every cell of the
+  colour adds omega times its local correction (the cells of a colour share
+  no node).
 """
 from __future__ import annotations
 
@@ -77,15 +82,49 @@ def vanka_sweep(J, blocks, cells, x, b, omega=0.6):
     return x + omega * acc / np.repeat(mult, 3)
 
 
+def cell_colours(cells) -> np.ndarray:
+    """Greedy colouring in cell order: the smallest colour not taken by an
+    earlier cell that shares a node with the cell."""
+    cells = np.asarray(cells)
+    node_cells = {}
+    for c, cell in enumerate(cells):
+        for v in cell:
+            node_cells.setdefault(int(v), []).append(c)
+    colour = np.full(len(cells), -1, dtype=np.int64)
+    for c, cell in enumerate(cells):
+        taken = {int(colour[o]) for v in cell for o in node_cells[int(v)] if o < c}
+        k = 0
+        while k in taken:
+            k += 1
+        colour[c] = k
+    return colour
+
+
+def vanka_sweep_coloured(J, blocks, cells, colours, x, b, omega=0.6):
+    """Multiplicative cell-Vanka over the colours: for each colour in turn,
+    r = b - J x, then each cell of the colour adds omega times the solution
+    of its 12x12 system (LU with partial pivoting) to its unknowns."""
+    d = cell_dofs(cells)
+    x = x.copy()
+    for k in range(int(colours.max()) + 1):
+        sel = np.nonzero(colours == k)[0]
+        r = b - J @ x
+        delta = np.linalg.solve(blocks[sel], r[d[sel]][:, :, None])[:, :, 0]
+        x[d[sel]] += omega * delta                 # no two cells of a colour share an unknown
+    return x
+
+
 class MGHierarchy:
     """Operators of all levels at one linearisation point (the fine iterate
     injected to each level: coarse vertices keep their ids, so injection is
     the prefix of the fine vector)."""
 
-    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6):
+    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive"):
         self.levels = levels
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
+        self.smoother = smoother
+        self.colours = [cell_colours(L.cells) for L in levels] if smoother == "coloured" else None
         self.J = []
         self.blocks = []
         for L in levels:
@@ -105,19 +144,24 @@ class MGHierarchy:
         rc[self.dmask[l - 1], :2] = 0.0
         return rc.reshape(-1)
 
+    def sweep(self, l, x, b):
+        L = self.levels[l]
+        if self.smoother == "coloured":
+            return vanka_sweep_coloured(self.J[l], self.blocks[l], L.cells, self.colours[l], x, b, self.omega)
+        return vanka_sweep(self.J[l], self.blocks[l], L.cells, x, b, self.omega)
+
     def vcycle(self, l, b, x=None):
         """One V(nu1, nu2) cycle on level l for J_l x = b."""
         if l == 0:
             return sla.lu_solve(self.lu0, b)
-        L = self.levels[l]
         x = np.zeros_like(b) if x is None else x.copy()
         for _ in range(self.nu1):
-            x = vanka_sweep(self.J[l], self.blocks[l], L.cells, x, b, self.omega)
+            x = self.sweep(l, x, b)
         r = b - self.J[l] @ x
         e = self.vcycle(l - 1, self._restrict(l, r))
         x = x + self._prolong(l, e)
         for _ in range(self.nu2):
-            x = vanka_sweep(self.J[l], self.blocks[l], L.cells, x, b, self.omega)
+            x = self.sweep(l, x, b)
         return x
 
 
@@ -181,7 +225,7 @@ def gmres(A, b, precond, rtol=1e-2, restart=30, maxit=100):
 
 
 def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1e-2,
-                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6):
+                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6, smoother="additive"):
     """Newton's method (eq. newton) with GMRES + V-cycle linear solves, as in
     the coarse solve of Algorithm 1 (full steps, reading N1)."""
     fine = levels[-1]
@@ -196,7 +240,7 @@ def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1
             return x, stats
         if it == maxit:
             break
-        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega)
+        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother)
         w, k, _ = gmres(mg.J[-1], R, lambda v: mg.vcycle(len(levels) - 1, v),
                         gmres_rtol, restart, gmres_max)
         stats["gmres"].append(k)

@@ -40,7 +40,8 @@ bool params_ok(const dnnmg_params *p) {
          p->nu_pre + p->nu_post >= 1 && p->vanka_omega > 0 && p->vanka_omega <= 2 &&
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
          (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1) &&
-         (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && p->reuse_contraction > 0 &&
+         (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && (p->smoother == 0 || p->smoother == 1) &&
+         p->reuse_contraction > 0 &&
          p->reuse_contraction < 1;
 }
 
@@ -56,6 +57,7 @@ void upload_level(DevLevel &D, hipStream_t s) {
   D.flag.upload(h.flag, s);
   D.cadj_ptr.upload(h.cadj_ptr, s);
   D.cadj.upload(h.cadj, s);
+  D.colour_cells.upload(h.colour_cells, s);
   D.cslot.upload(h.cslot, s);
   D.padj_ptr.upload(h.padj_ptr, s);
   D.padj.upload(h.padj, s);
@@ -248,6 +250,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->newton_predictor = 1;
   p->jacobian_reuse = 0;
   p->reuse_contraction = 0.1;
+  p->smoother = 0;
   p->stream = nullptr;
   return DNNMG_OK;
 }

@@ -104,6 +104,7 @@ struct DevLevel {
   DevBuf<int4> cells;
   DevBuf<uint8_t> flag, cslot, pslot, vslot;
   DevBuf<int> cadj_ptr, cadj, padj_ptr, padj, patch_nodes, wq, wx, oq, ox, colq, colx;
+  DevBuf<int> colour_cells;            // cells grouped by colour (h.colour_ptr)
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
   DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
   DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)

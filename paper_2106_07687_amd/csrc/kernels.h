@@ -704,6 +704,34 @@ constexpr int kCadj = 8;
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Coloured multiplicative cell-Vanka, one colour: the cells of a colour
+// share no node, so each adds omega times its correction inv_c r|_c to its
+// own unknowns (no averaging, no write conflicts).  The products are summed
+// as in apply_item.
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_colour(LevelView L, const T *__restrict__ inv,
+                                                      const T *__restrict__ r, const int *__restrict__ cells_k,
+                                                      int n, T omega, T *__restrict__ x) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int c = cells_k[k];
+  const int4 cn = L.cells[c];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  T rc[12];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
+    T *xi = x + 3 * nn[i / 3] + i % 3;
+    *xi = fma_t(omega, s, *xi);
+  }
+}
+
 // set: x is zero on entry (first sweep from a zero iterate): store instead of add.
 template <typename T>
 __device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,

@@ -266,6 +266,37 @@ bool build_tables(HostLevel &L, std::string *err) {
     for (int c = 0; c < Cc; ++c)
       for (int k = 0; k < 4; ++k) L.ridx[fill[L.coarse_cells[4 * c + k]]++] = Nc + Ec + c;
   }
+  // greedy colouring in cell order: a cell takes the smallest colour not taken
+  // by an earlier cell that shares one of its nodes
+  {
+    std::vector<int> colour(static_cast<size_t>(C), -1);
+    int ncol = 0;
+    for (int c = 0; c < C; ++c) {
+      uint64_t taken = 0;
+      for (int a = 0; a < 4; ++a) {
+        const int v = L.cells[4 * c + a];
+        for (int e = L.cadj_ptr[v]; e < L.cadj_ptr[v + 1]; ++e) {
+          const int o = L.cadj[e] >> 2;
+          if (o < c) taken |= uint64_t(1) << colour[o];
+        }
+      }
+      int k = 0;
+      while (k < 64 && ((taken >> k) & 1)) ++k;
+      if (k == 64) {
+        if (err) *err = "cell colouring needs more than 64 colours";
+        return false;
+      }
+      colour[c] = k;
+      ncol = std::max(ncol, k + 1);
+    }
+    L.ncolour = ncol;
+    L.colour_ptr.assign(static_cast<size_t>(ncol) + 1, 0);
+    for (int c = 0; c < C; ++c) L.colour_ptr[colour[c] + 1]++;
+    for (int k = 0; k < ncol; ++k) L.colour_ptr[k + 1] += L.colour_ptr[k];
+    L.colour_cells.assign(static_cast<size_t>(C), 0);
+    std::vector<int> fill(L.colour_ptr.begin(), L.colour_ptr.end() - 1);
+    for (int c = 0; c < C; ++c) L.colour_cells[fill[colour[c]]++] = c;
+  }
   return true;
 }
 

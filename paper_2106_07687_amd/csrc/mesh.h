@@ -48,6 +48,10 @@ struct HostLevel {
   std::vector<uint8_t> vslot;       // 16 per cell: slot of node b in node a's Q1 row
   // restriction to the coarser level: fine nodes contributing to coarse node j
   std::vector<int> rptr, ridx;
+  // greedy cell colouring in cell order (no two cells of a colour share a
+  // node): cells of colour k are colour_cells[colour_ptr[k] .. colour_ptr[k+1])
+  int ncolour = 0;
+  std::vector<int> colour_ptr, colour_cells;
 };
 
 // Refines (xy, cells, bedges) once; numbering: old vertices keep ids, then one

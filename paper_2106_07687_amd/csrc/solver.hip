@@ -579,6 +579,20 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
   DevLevel &L = *ctx_->levels[l];
   OpLevel<T> &o = ops_[l];
   hipStream_t s = ctx_->stream;
+  if (ctx_->prm.smoother == 1) {   // coloured multiplicative: colour by colour
+    if (zero_start) hipLaunchKernelGGL(k_fill<T>, dim3(blocks(3 * static_cast<size_t>(L.h.N), 256)), dim3(256), 0, s,
+                                       x, 3 * static_cast<size_t>(L.h.N), T(0));
+    const T omega = static_cast<T>(ctx_->prm.vanka_omega);
+    for (int k = 0; k < L.h.ncolour; ++k) {
+      spmv(l, x, b, o.r.p);
+      const int c0 = L.h.colour_ptr[k], n = L.h.colour_ptr[k + 1] - c0;
+      ProfScope ps(ctx_->prof, s, "vanka_colour", l);
+      hipLaunchKernelGGL(k_vanka_colour<T>, dim3(blocks(n, 256)), dim3(256), 0, s, L.view(), o.inv.p, o.r.p,
+                         L.colour_cells.p + c0, n, omega, x);
+    }
+    LAUNCH_CHECK("coloured vanka");
+    return;
+  }
   const T *r = b;
   if (!zero_start && o.bs_smooth > 0) {
     ProfScope ps(ctx_->prof, s, "vanka_smooth", l);
@@ -665,7 +679,7 @@ void Solver<T>::launch_small(int top, const T *b, T *x) {
 
 template <typename T>
 void Solver<T>::vcycle(int l, const T *b, T *x) {
-  if (l >= 1 && l <= small_top_) {
+  if (l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0) {   // the one-workgroup cycle is additive
     launch_small(l, b, x);
     return;
   }

@@ -69,7 +69,16 @@ def test_vcycle_replays_are_bitwise_equal(precision):
     assert np.array_equal(vg, ve)
     for ctx in (cg, ce):
         ctx.set_params(vanka_omega=0.6)
-    assert not np.array_equal(vg, ce.vcycle(LEVEL, b))
+    va = ce.vcycle(LEVEL, b)
+    assert not np.array_equal(vg, va)
+    # the coloured multiplicative smoother: captured and eager cycles agree
+    for ctx in (cg, ce):
+        ctx.set_params(smoother=1)
+    vg2, ve2 = cg.vcycle(LEVEL, b), ce.vcycle(LEVEL, b)
+    assert np.array_equal(vg2, ve2) and not np.array_equal(vg2, va)
+    for ctx in (cg, ce):
+        ctx.set_params(smoother=0)
+    assert np.array_equal(cg.vcycle(LEVEL, b), va)
     for st in states:
         st.close()
 

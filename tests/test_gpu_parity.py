@@ -205,3 +205,59 @@ def test_rectangle_without_obstacle():
     xr = solver.newton_step(lev[2], prob, np.zeros(3 * lev[2].n_nodes), DT, tol=1e-15)
     e = float(rel(xg, xr))
     assert e < 1e-10, e
+
+
+def test_coloured_vanka_and_vcycle_parity(c1):
+    """The coloured multiplicative sweep (smoother = 1) and V-cycles built on
+    it against the oracle's (same greedy colouring, FP64): 1e-11 / 1e-10."""
+    macro, lev, ctx, prob = c1
+    x = random_state(lev[3].n_nodes, 16) * 0.3
+    st = ctx.state(3)
+    st.set(x, 0.0)
+    ctx.set_params(smoother=1)
+    try:
+        ctx.linearize(st, 3, DT)
+        mg = solver.MGHierarchy(lev, prob, x, smoother="coloured")
+        b = random_state(lev[3].n_nodes, 17)
+        b.reshape(-1, 3)[lev[3].dirichlet_nodes(), :2] = 0.0
+        x0 = random_state(lev[3].n_nodes, 18) * 0.1
+        x0.reshape(-1, 3)[lev[3].dirichlet_nodes(), :2] = 0.0
+        xs_gpu = ctx.vanka_sweep(3, x0, b)
+        xs_ref = solver.vanka_sweep_coloured(mg.J[3], mg.blocks[3], lev[3].cells, mg.colours[3], x0, b, 0.6)
+        print(f"[coloured] {mg.colours[3].max() + 1} colours on level 3; sweep {rel(xs_gpu, xs_ref):.2e}",
+              flush=True)
+        assert rel(xs_gpu, xs_ref) < 1e-11, rel(xs_gpu, xs_ref)
+        for l in (1, 2, 3):
+            bl = b[:3 * lev[l].n_nodes].copy()
+            bl.reshape(-1, 3)[lev[l].dirichlet_nodes(), :2] = 0.0
+            v_gpu = ctx.vcycle(l, bl)
+            v_ref = mg.vcycle(l, bl)
+            assert rel(v_gpu, v_ref) < 1e-10, (l, rel(v_gpu, v_ref))
+    finally:
+        ctx.set_params(smoother=0)
+        st.close()
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-10), (1, 1e-5)])
+def test_coloured_smoother_steps_match_oracle(precision, bar):
+    """Time steps with the coloured smoother reach the oracle's x_n (FP64
+    1e-10 at Newton 1e-14; mixed 1e-5 per step)."""
+    macro = channel_obstacle(0)
+    lev = mesh.hierarchy(macro, 3)
+    L = lev[3]
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    ctx = _ctx(precision, nu=macro.nu, smoother=1, newton_tol=1e-14 if precision == 0 else 1e-10)
+    ctx.setup_mesh(macro, 3)
+    st = ctx.state(3)
+    x_ref = np.zeros(3 * L.n_nodes)
+    for n in range(1, 4):
+        info = ctx.step(st, DT)
+        x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=1e-15)
+        xg, _ = st.get()
+        e = max(rel(xg.reshape(-1, 3)[:, f], x_ref.reshape(-1, 3)[:, f]) for f in range(3))
+        print(f"[coloured] precision {precision} step {n}: {e:.2e}, gmres {info['gmres_iters']}", flush=True)
+        assert e < bar, (n, e)
+        if precision == 1:
+            st.set(x_ref, n * DT)               # per-step error
+    st.close()
+    ctx.close()

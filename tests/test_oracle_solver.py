@@ -80,3 +80,75 @@ def test_mg_newton_matches_direct_newton():
     xd = solver.newton_step(lev[-1], prob, x0, 0.2, tol=1e-13)
     xm, _ = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13)
     assert np.linalg.norm(xm - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+# ---- coloured multiplicative Vanka (reading N17)
+
+def test_cell_colouring_is_valid_and_greedy():
+    m = channel_obstacle(0)
+    for L in mesh.hierarchy(m, 3)[1:]:
+        col = solver.cell_colours(L.cells)
+        # no two cells of one colour share a node
+        for k in range(col.max() + 1):
+            nodes = L.cells[col == k].reshape(-1)
+            assert np.unique(nodes).size == nodes.size
+        # greedy in cell order: every colour k > 0 of a cell is taken by an
+        # earlier neighbour for each smaller colour
+        node_cells = {}
+        for c, cell in enumerate(L.cells):
+            for v in cell:
+                node_cells.setdefault(int(v), []).append(c)
+        for c in range(0, L.n_cells, 7):
+            earlier = {int(col[o]) for v in L.cells[c] for o in node_cells[int(v)] if o < c}
+            assert all(k in earlier for k in range(col[c]))
+        assert 4 <= col.max() + 1 <= 8            # a quad mesh needs at least 4
+
+
+def test_coloured_sweep_on_one_cell_is_exact():
+    """A single cell: the sweep solves its 12x12 system (special case)."""
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((12, 12)) + 5 * np.eye(12)
+    J = sp.csr_matrix(A)
+    cells = np.array([[0, 1, 2, 3]])
+    b = rng.standard_normal(12)
+    x = solver.vanka_sweep_coloured(J, solver.cell_blocks(J, cells), cells, solver.cell_colours(cells),
+                                    np.zeros(12), b, 1.0)
+    np.testing.assert_allclose(A @ x, b, atol=1e-12)
+
+
+def test_coloured_sweep_is_multiplicative():
+    """Two cells sharing an edge take two colours; with omega = 1 the sweep is
+    block Gauss-Seidel: after it the residual vanishes on the unknowns of the
+    second cell (the additive sweep leaves a residual there)."""
+    rng = np.random.default_rng(8)
+    cells = np.array([[0, 1, 4, 3], [1, 2, 5, 4]])
+    n = 18
+    A = rng.standard_normal((n, n)) * 0.3 + 4 * np.eye(n)
+    d = solver.cell_dofs(cells)
+    mask = np.zeros((n, n), dtype=bool)
+    for c in range(2):
+        mask[np.ix_(d[c], d[c])] = True
+    A = np.where(mask, A, 0.0)                   # couplings only inside a cell
+    J = sp.csr_matrix(A)
+    col = solver.cell_colours(cells)
+    assert list(col) == [0, 1]
+    b = rng.standard_normal(n)
+    blocks = solver.cell_blocks(J, cells)
+    x = solver.vanka_sweep_coloured(J, blocks, cells, col, np.zeros(n), b, 1.0)
+    r = b - A @ x
+    assert np.abs(r[d[1]]).max() < 1e-12
+    xa = solver.vanka_sweep(J, blocks, cells, np.zeros(n), b, 1.0)
+    assert np.abs((b - A @ xa)[d[1]]).max() > 1e-3
+
+
+def test_mg_newton_with_coloured_smoother_matches_direct_newton():
+    m = channel_obstacle(1)
+    lev = mesh.hierarchy(m, 2)
+    prob = fem.Problem(nu=m.nu, dt=0.01)
+    x0 = np.zeros(3 * lev[-1].n_nodes)
+    xd = solver.newton_step(lev[-1], prob, x0, 0.2, tol=1e-13)
+    xm, st = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, smoother="coloured", omega=0.6)
+    np.testing.assert_allclose(xm, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
+    # the multiplicative sweep is the stronger smoother: fewer Krylov steps
+    _, sa = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, smoother="additive", omega=0.6)
+    assert sum(st["gmres"]) < sum(sa["gmres"]), (st["gmres"], sa["gmres"])
