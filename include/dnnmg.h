@@ -102,6 +102,11 @@ typedef struct {
                              x_n is the same to the tolerance)               */
   double reuse_contraction; /* largest ||R_k|| / ||R_{k-1}|| that keeps a
                              Jacobian, in (0, 1); default 0.1                 */
+  int switch_off_newton;  /* DNN-MG switch-off (Sec. 3.3): a step with a pending
+                             network right-hand side whose Newton iteration has
+                             not converged after this many iterations is redone
+                             with the plain right-hand side (stats.fallback =
+                             1); 0: only when Newton fails (newton_max)      */
   int smoother;           /* 0: additive cell-Vanka (every cell's correction,
                              averaged over the cells of a node, omega times);
                              1: coloured multiplicative cell-Vanka (greedy cell

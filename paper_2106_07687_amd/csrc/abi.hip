@@ -41,6 +41,7 @@ bool params_ok(const dnnmg_params *p) {
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
          (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1) &&
          (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && (p->smoother == 0 || p->smoother == 1) &&
+         p->switch_off_newton >= 0 &&
          p->reuse_contraction > 0 &&
          p->reuse_contraction < 1;
 }
@@ -116,7 +117,11 @@ retry:
   nr_prev = 0.0;
   hipLaunchKernelGGL(k_impose_bc, dim3(blocks(N, 256)), dim3(256), 0, s, c.levels[l]->view(),
                      c.phys(dt, t_new), st.x.p);
-  for (int it = 0; it <= c.prm.newton_max; ++it) {
+  // with a network right-hand side, Newton may stop early (switch-off)
+  const int it_max = use_pending && c.prm.switch_off_newton > 0
+                         ? std::min(c.prm.switch_off_newton, c.prm.newton_max)
+                         : c.prm.newton_max;
+  for (int it = 0; it <= it_max; ++it) {
     c.residual(l, st.x.p, c.xo_save.p, use_pending ? st.pending_rhs.p : nullptr, t_new, dt,
                c.R.p);
     const double nr = c.norm2_max_seg(l, c.R.p);   // batches: every simulation's own norm
@@ -130,7 +135,7 @@ retry:
     }
     if (it > 0) st.reuse_ok = nr <= c.prm.reuse_contraction * nr_prev;
     nr_prev = nr;
-    if (it == c.prm.newton_max) break;
+    if (it == it_max) break;
     if (fresh_only) {
       // the multigrid preconditioner is refreshed at the first Newton
       // iteration of a step; later iterations re-assemble only the finest
@@ -251,6 +256,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->jacobian_reuse = 0;
   p->reuse_contraction = 0.1;
   p->smoother = 0;
+  p->switch_off_newton = 0;
   p->stream = nullptr;
   return DNNMG_OK;
 }

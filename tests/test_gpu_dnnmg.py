@@ -277,3 +277,35 @@ def test_adam_first_step_and_training_reduces_loss(setup):
     print(f"[adam] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.2 * losses[0]
     net.close()
+
+
+def test_switch_off_redoes_slow_steps_with_the_plain_rhs(setup):
+    """Sec. 3.3 switch-off: with switch_off_newton = 1 a step whose Newton
+    iteration on the network's right-hand side needs more than one iteration
+    is redone with the plain right-hand side (fallback = 1), and lands on the
+    plain step's x_n; with 0 the same step keeps the network's right-hand side."""
+    P, macro, lev, ctx, prob = setup
+    L, m = 1, 2
+    net = P.Net(ctx, L, m, hidden=32, layers=2)
+    w = gru_weights(net.n_in, 32, 2, net.n_out, seed=5, scale=0.5)
+    net.set_weights(w, out_scale=np.array([1e-2, 1e-2], dtype=np.float32))
+    results = {}
+    for off in (0, 1, None):
+        ctx.set_params(switch_off_newton=off or 0)
+        st = ctx.state(L)
+        net.reset(st)
+        for _ in range(2):
+            ctx.step(st, DT)
+        if off is not None:
+            net.correct(st, DT)                  # a pending network right-hand side
+        stats = ctx.step(st, DT)
+        results[off] = (stats, st.get()[0])
+        st.close()
+    ctx.set_params(switch_off_newton=0)
+    print(f"[switch-off] newton with network rhs {results[0][0]['newton_iters']}, "
+          f"fallback {results[0][0]['fallback']} / {results[1][0]['fallback']}", flush=True)
+    assert results[0][0]["newton_iters"] >= 2 and results[0][0]["fallback"] == 0
+    assert results[1][0]["fallback"] == 1 and results[None][0]["fallback"] == 0
+    assert rel(results[1][1], results[None][1]) < 1e-10
+    assert rel(results[0][1], results[None][1]) > 1e-8     # the network's step differs
+    net.close()
