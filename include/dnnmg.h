@@ -75,15 +75,17 @@ typedef struct {
                              sweep from HIP graphs captured on first use (same
                              kernels, same order, bitwise the same results);
                              0: launch every kernel directly                    */
-  int autotune;           /* 1: at mesh setup, time the SpMV, Vanka and transfer
-                             kernels of every level at workgroup sizes 64, 128
-                             and 256, the fused residual + Vanka apply against
-                             the separate kernels, and the bottom of the V-cycle
+  int autotune;           /* 1: at mesh setup, time the SpMV (one and four
+                             threads per row), Vanka and transfer kernels of
+                             every level at workgroup sizes 64, 128 and 256,
+                             the fused residual + Vanka apply against the
+                             separate kernels, and the bottom of the V-cycle
                              (levels <= 2 and the coarse solve) in a single
                              workgroup against its launches, and keep the
                              fastest (scheduling only: results are bitwise the
-                             same); 0: 256 throughout, separate kernels;
-                             2: as 0 with the fused apply on every level;
+                             same); 0: 256 throughout, separate kernels, one
+                             thread per row; 2: as 0 with the fused apply and
+                             four threads per SpMV row on every level;
                              3: as 0 with the single-workgroup bottom cycle  */
   int newton_predictor;   /* 0: Newton starts from x_{n-1}; 1: from the linear
                              extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
@@ -386,11 +388,12 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..7] = SpMV, Vanka apply,
+/* Workgroup sizes in use on `level`: block_sizes[0..8] = SpMV, Vanka apply,
  * Vanka update, restriction from `level`, prolongation to `level`, the fused
  * residual + Vanka apply (0: SpMV and apply run separately), the
  * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0),
- * and the fused residual + restriction (0: separate) (8 ints, caller-owned).
+ * the fused residual + restriction (0: separate), and the SpMV with four
+ * threads per row (0: one thread per row) (9 ints, caller-owned).
  * DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:

@@ -129,6 +129,7 @@ struct OpLevel {
   // restrict / prolong are the transfers between this level and the next
   // coarser one
   int bs_spmv = 256, bs_apply = 256, bs_update = 256, bs_restrict = 256, bs_prolong = 256;
+  int bs_spmv4 = 0;    // > 0: four threads per row (k_spmv4) at this size
   int bs_smooth = 0;   // > 0: residual + Vanka apply fused (k_vanka_smooth) at this size
   int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
 };
@@ -170,12 +171,14 @@ class Solver {
   // and 256 and keeps the fastest (the choice changes scheduling only: every
   // thread does the same arithmetic, results are bitwise the same).
   void autotune();
-  // Fused residual + Vanka apply on every level, workgroup size 256 (a fixed
-  // configuration, e.g. for reproducible comparisons).
+  // Fused residual + Vanka apply and four threads per SpMV row on every
+  // level, workgroup size 256 (a fixed configuration, e.g. for reproducible
+  // comparisons).
   void fuse_all() {
     for (auto &o : ops_) {
       o.bs_smooth = 256;
       o.bs_rres = 256;
+      o.bs_spmv4 = 256;
     }
   }
   // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup

@@ -19,6 +19,11 @@
 namespace dnnmg {
 constexpr int kS = 64;
 
+// Explicit fused multiply-add (the rounding must not depend on whether the
+// compiler contracts a product that other code also uses).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ---------------------------------------------------------------- geometry
 struct LevelView {
   int N, C, NP;
@@ -466,10 +471,15 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
 // -------------------------------------------------------------- SpMV
 // y = b - J x (if b) or y = J x, T precision.
 constexpr int kSpmvChunk = 16;
-// Row i of J x (3 values).  Chunks of kSpmvChunk neighbours: all column
-// indices of a chunk are loaded before the x values they select, so the
-// dependent index -> x chain costs two memory latencies per chunk instead of
-// two per neighbour (the same summation order as a plain loop).
+// Row i of J x (3 values).  The row sum has one canonical order, whatever the
+// number of threads per row: entry k (the Q1 blocks, then the LPS extra
+// entries, each counted from 0) goes into partial sum k mod 4, in increasing
+// k, each block contribution as fma(m2, x2, fma(m1, x1, m0 x0)) and each extra
+// entry as one fma; the row is (s0 + s1) + (s2 + s3).  spmv_row evaluates the
+// four partial sums in one thread, spmv_row_part the partial sum q in thread
+// q of four: both give the same bits.  Chunks of kSpmvChunk entries: all
+// column indices of a chunk, then all x values, then the products, so that a
+// thread waits on two memory latencies per chunk, not two per entry.
 template <typename T>
 __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
                                          const T *__restrict__ x, int i, T &a0, T &a1, T &a2) {
@@ -477,9 +487,9 @@ __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict
   const int wq = L.wq[s], wx = L.wx[s];
   const T *jq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
   const int *cq = L.colq + static_cast<size_t>(L.oq[s]) * kS + lane;
-  a0 = 0;
-  a1 = 0;
-  a2 = 0;
+  T p[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) p[q][0] = p[q][1] = p[q][2] = 0;
   for (int k0 = 0; k0 < wq; k0 += kSpmvChunk) {
     int jv[kSpmvChunk];
 #pragma unroll
@@ -493,9 +503,10 @@ __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict
     for (int u = 0; u < kSpmvChunk; ++u) {
       if (jv[u] >= 0) {
         const T *m = jq + static_cast<size_t>(k0 + u) * 9 * kS;
-        a0 += m[0] * xv[u][0] + m[kS] * xv[u][1] + m[2 * kS] * xv[u][2];
-        a1 += m[3 * kS] * xv[u][0] + m[4 * kS] * xv[u][1] + m[5 * kS] * xv[u][2];
-        a2 += m[6 * kS] * xv[u][0] + m[7 * kS] * xv[u][1] + m[8 * kS] * xv[u][2];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+          p[u & 3][f] += fma_t(m[(3 * f + 2) * kS], xv[u][2],
+                               fma_t(m[(3 * f + 1) * kS], xv[u][1], m[3 * f * kS] * xv[u][0]));
       }
     }
   }
@@ -510,8 +521,65 @@ __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict
     for (int u = 0; u < kSpmvChunk; ++u) xv[u] = jv[u] >= 0 ? x[3 * jv[u] + 2] : T(0);
 #pragma unroll
     for (int u = 0; u < kSpmvChunk; ++u)
-      if (jv[u] >= 0) a2 += jx[(k0 + u) * kS] * xv[u];
+      if (jv[u] >= 0) p[u & 3][2] = fma_t(jx[(k0 + u) * kS], xv[u], p[u & 3][2]);
   }
+  a0 = (p[0][0] + p[1][0]) + (p[2][0] + p[3][0]);
+  a1 = (p[0][1] + p[1][1]) + (p[2][1] + p[3][1]);
+  a2 = (p[0][2] + p[1][2]) + (p[2][2] + p[3][2]);
+}
+
+// Partial sum q (entries k = q mod 4) of row i, for four threads per row.
+template <typename T>
+__device__ __forceinline__ void spmv_row_part(const LevelView &L, const T *__restrict__ JQ,
+                                              const T *__restrict__ JX, const T *__restrict__ x, int i, int q,
+                                              T &a0, T &a1, T &a2) {
+  const int s = i / kS, lane = i % kS;
+  const int wq = L.wq[s], wx = L.wx[s];
+  const T *jq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+  const int *cq = L.colq + static_cast<size_t>(L.oq[s]) * kS + lane;
+  T p[3] = {0, 0, 0};
+  constexpr int kPer = kSpmvChunk / 4;
+  for (int k0 = 0; k0 < wq; k0 += kSpmvChunk) {
+    int jv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = k0 + 4 * u + q;
+      jv[u] = k < wq ? cq[k * kS] : -1;
+    }
+    T xv[kPer][3];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) xv[u][f] = jv[u] >= 0 ? x[3 * jv[u] + f] : T(0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (jv[u] >= 0) {
+        const T *m = jq + static_cast<size_t>(k0 + 4 * u + q) * 9 * kS;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+          p[f] += fma_t(m[(3 * f + 2) * kS], xv[u][2], fma_t(m[(3 * f + 1) * kS], xv[u][1], m[3 * f * kS] * xv[u][0]));
+      }
+    }
+  }
+  const T *jx = JX + static_cast<size_t>(L.ox[s]) * kS + lane;
+  const int *cx = L.colx + static_cast<size_t>(L.ox[s]) * kS + lane;
+  for (int k0 = 0; k0 < wx; k0 += kSpmvChunk) {
+    int jv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = k0 + 4 * u + q;
+      jv[u] = k < wx ? cx[k * kS] : -1;
+    }
+    T xv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) xv[u] = jv[u] >= 0 ? x[3 * jv[u] + 2] : T(0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (jv[u] >= 0) p[2] = fma_t(jx[(k0 + 4 * u + q) * kS], xv[u], p[2]);
+  }
+  a0 = p[0];
+  a1 = p[1];
+  a2 = p[2];
 }
 
 // Each kernel below is a grid over items (nodes, cells) calling the item
@@ -539,6 +607,41 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
                        const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < L.N) spmv_item(L, JQ, JX, x, b, y, i);
+}
+
+// The same rows with four threads per node (more loads in flight on small
+// levels): lane q of a group of four sums the entries k = q mod 4; lane 0
+// combines (s0 + s1) + (s2 + s3), bitwise the value of k_spmv.  The
+// workgroup size is a multiple of 4.
+template <typename T>
+__global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                               const T *__restrict__ x, const T *__restrict__ b,
+                                               T *__restrict__ y) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid >> 2, q = gid & 3;
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (i < L.N) spmv_row_part(L, JQ, JX, x, i, q, a0, a1, a2);
+  const int lb = (threadIdx.x & 63) & ~3;
+  T s[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    s[k][0] = __shfl(a0, lb + k);
+    s[k][1] = __shfl(a1, lb + k);
+    s[k][2] = __shfl(a2, lb + k);
+  }
+  if (i >= L.N || q != 0) return;
+  const T r0 = (s[0][0] + s[1][0]) + (s[2][0] + s[3][0]);
+  const T r1 = (s[0][1] + s[1][1]) + (s[2][1] + s[3][1]);
+  const T r2 = (s[0][2] + s[1][2]) + (s[2][2] + s[3][2]);
+  if (b) {
+    y[3 * i] = b[3 * i] - r0;
+    y[3 * i + 1] = b[3 * i + 1] - r1;
+    y[3 * i + 2] = b[3 * i + 2] - r2;
+  } else {
+    y[3 * i] = r0;
+    y[3 * i + 1] = r1;
+    y[3 * i + 2] = r2;
+  }
 }
 
 // -------------------------------------------------------------- Vanka
@@ -699,10 +802,6 @@ __global__ void __launch_bounds__(256) k_vanka_smooth(LevelView L, const T *__re
 // their corrections, so that a thread waits on two memory latencies, not on
 // two per cell (small levels have too few waves to hide a dependent chain).
 constexpr int kCadj = 8;
-// Explicit fused multiply-add (the rounding must not depend on whether the
-// compiler contracts a product that other code also uses).
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Coloured multiplicative cell-Vanka, one colour: the cells of a colour
 // share no node, so each adds omega times its correction inv_c r|_c to its

@@ -419,6 +419,14 @@ void Solver<T>::autotune() {
         hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
                            o.b.p, o.t.p);
       });
+      // four threads per row (bitwise the same rows): kept if faster
+      o.bs_spmv4 = 0;
+      const float t_one = last_t;
+      const int bs4 = pick([&](int bs) {
+        hipLaunchKernelGGL(k_spmv4<T>, dim3(blocks(4 * static_cast<size_t>(L.h.N), bs)), dim3(bs), 0, s, v, o.JQ.p,
+                           o.JX.p, o.x.p, o.b.p, o.t.p);
+      });
+      if (last_t < t_one) o.bs_spmv4 = bs4;
       if (l == 0) continue;
       o.bs_apply = pick([&](int bs) {
         hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
@@ -569,8 +577,12 @@ void Solver<T>::spmv(int l, const T *x, const T *b, T *y) {
   DevLevel &L = *ctx_->levels[l];
   OpLevel<T> &o = ops_[l];
   ProfScope ps(ctx_->prof, ctx_->stream, b ? "residual_spmv" : "spmv", l);
-  hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, o.bs_spmv)), dim3(o.bs_spmv), 0, ctx_->stream, L.view(),
-                     o.JQ.p, o.JX.p, x, b, y);
+  if (o.bs_spmv4 > 0)
+    hipLaunchKernelGGL(k_spmv4<T>, dim3(blocks(4 * static_cast<size_t>(L.h.N), o.bs_spmv4)), dim3(o.bs_spmv4), 0,
+                       ctx_->stream, L.view(), o.JQ.p, o.JX.p, x, b, y);
+  else
+    hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, o.bs_spmv)), dim3(o.bs_spmv), 0, ctx_->stream, L.view(),
+                       o.JQ.p, o.JX.p, x, b, y);
   LAUNCH_CHECK("k_spmv");
 }
 

@@ -132,7 +132,8 @@ def test_autotuned_launches_are_bitwise_equal():
 
 
 def test_fused_residual_and_apply_is_bitwise_equal():
-    """autotune=2 fuses the residual into the Vanka apply on every level."""
+    """autotune=2 fuses the residual into the Vanka apply and runs the SpMV
+    with four threads per row on every level."""
     import paper_2106_07687_amd as P
     macro = channel_obstacle(2)
     ctxs = []
@@ -141,6 +142,7 @@ def test_fused_residual_and_apply_is_bitwise_equal():
         ctx.setup_mesh(macro, LEVEL)
         ctxs.append(ctx)
     assert all(ctxs[0].launch_config(l)["vanka_smooth"] == 256 for l in range(1, LEVEL + 1))
+    assert all(ctxs[0].launch_config(l)["spmv4"] == 256 for l in range(LEVEL + 1))
     lev = mesh.hierarchy(macro, LEVEL)
     x = random_state(lev[LEVEL].n_nodes, 5) * 0.3
     sts = []
