@@ -24,8 +24,11 @@ def test_defaults_and_invalid_params():
     assert lib.dnnmg_params_default(C.byref(p)) == 0
     assert (p.theta, p.alpha0, p.nu_pre, p.nu_post, p.gmres_restart) == (0.5, 0.5, 2, 2, 30)
     h = C.c_void_p()
+    assert (p.jacobian_reuse, p.reuse_contraction, p.smoother, p.switch_off_newton) == (0, 0.1, 0, 0)
     for field, bad in (("nu", -1.0), ("theta", 0.0), ("gmres_restart", 65), ("precision", 2),
-                       ("vanka_omega", 0.0), ("gmres_rtol", 1.5)):
+                       ("vanka_omega", 0.0), ("gmres_rtol", 1.5), ("jacobian_reuse", 2),
+                       ("reuse_contraction", 0.0), ("reuse_contraction", 1.0), ("smoother", 2),
+                       ("switch_off_newton", -1), ("autotune", 4), ("newton_predictor", 3)):
         q = _lib.Params()
         lib.dnnmg_params_default(C.byref(q))
         setattr(q, field, bad)
@@ -73,3 +76,9 @@ def test_oscillation_entry_point_matches_oracle():
                 dict(f=np.array([0.0, np.nan, 1.0, 0.0]), dt=0.1)):
         with pytest.raises(P.DnnmgError):
             P.oscillation(bad["f"], 0.0, bad["dt"])
+
+
+def test_unknown_parameter_names_are_rejected():
+    """A misspelt solver parameter must not be silently ignored."""
+    with pytest.raises(TypeError):
+        P.Context(precision=1, jacobain_reuse=1)
