@@ -533,7 +533,7 @@ def main():
         gmg_keys = [f"{k}@L{F}" for k in ("spmv", "residual_spmv", "vanka_apply", "vanka_update",
                                           "assemble", "vanka_factor", "residual", "gs_dots")]
         dnn_keys = [f"{k}{l}@L{F}" for l in range(args.layers)
-                    for k in ("gru_gemm_in", "gru_step", "gru_gemm_hh", "gru_gates")]
+                    for k in ("gru_gemm_in", "gru_step")]
         dnn_keys += [f"{k}@L{F}" for k in ("gru_head", "dnnmg_rhs", "dnnmg_prolong",
                                            "patch_gather", "patch_scatter")]
     t0 = time.perf_counter()

@@ -159,22 +159,12 @@ void net_forward(Net &n) {
       ProfScope ps(n.ctx->prof, s, ("gru_gemm_in" + lay).c_str(), n.F);
       gemm(s, n.B, H3, K, in, K, n.wih_b[l].p, K, n.Gi.p, H3, false);
     }
-    if (n.H % 32 == 0) {   // recurrent product and gate update in one kernel
-      ProfScope ps(n.ctx->prof, s, ("gru_step" + lay).c_str(), n.F);
-      hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(n.B, 64)), dim3(256), 0, s, n.B, n.H, n.Gi.p,
-                         n.hb[l].p, n.h[l].p, n.whh_b[l].p, n.h[l].p, n.hb_next[l].p, nullptr);
-      check(hipGetLastError(), "k_gru_step_fused");
-      std::swap(n.hb[l], n.hb_next[l]);
-      continue;
-    }
-    {
-      ProfScope ps(n.ctx->prof, s, ("gru_gemm_hh" + lay).c_str(), n.F);
-      gemm(s, n.B, H3, n.H, n.hb[l].p, n.H, n.whh_b[l].p, n.H, n.Gh.p, H3, false);
-    }
-    ProfScope ps(n.ctx->prof, s, ("gru_gates" + lay).c_str(), n.F);
-    hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(n.B) * n.H, 256)), dim3(256), 0, s, n.B,
-                       n.H, n.Gi.p, n.Gh.p, n.h[l].p, n.h[l].p, n.hb[l].p, n.H, nullptr);
-    check(hipGetLastError(), "k_gru_gates");
+    // recurrent product and gate update in one kernel (H is a multiple of 32)
+    ProfScope ps(n.ctx->prof, s, ("gru_step" + lay).c_str(), n.F);
+    hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(n.B, 64)), dim3(256), 0, s, n.B, n.H, n.Gi.p,
+                       n.hb[l].p, n.h[l].p, n.whh_b[l].p, n.h[l].p, n.hb_next[l].p, nullptr);
+    check(hipGetLastError(), "k_gru_step_fused");
+    std::swap(n.hb[l], n.hb_next[l]);
   }
   ProfScope ps(n.ctx->prof, s, "gru_head", n.F);
   gemm(s, n.B, n.O, n.H, n.hb[n.layers - 1].p, n.H, n.wout_b.p, n.H, n.Y.p, n.O, false);
@@ -367,7 +357,6 @@ int dnnmg_net_create_patch(dnnmg_ctx *ctx, int coarse_level, int m_levels, int h
     n.X.alloc(static_cast<size_t>(n.B) * n.K0);
     n.Xf.alloc(static_cast<size_t>(n.B) * n.K0);
     n.Gi.alloc(static_cast<size_t>(n.B) * 3 * n.H);
-    n.Gh.alloc(static_cast<size_t>(n.B) * 3 * n.H);
     n.Y.alloc(static_cast<size_t>(n.B) * n.O);
     n.xt.resize(m_levels + 1);
     n.rchain.resize(m_levels + 1);

@@ -36,7 +36,7 @@ struct Net {
   std::vector<DevBuf<float>> h;                // [B x H] per layer
   std::vector<DevBuf<uint16_t>> hb, hb_next;   // BF16 state; the fused step writes hb_next, then they swap
   DevBuf<uint16_t> X;
-  DevBuf<float> Xf, Gi, Gh, Y;
+  DevBuf<float> Xf, Gi, Y;
   // fine-level vectors (FP64)
   std::vector<DevBuf<double>> xt;              // prolongation chain, index l - L
   DevBuf<double> vprev, vc, bF, dcorr;

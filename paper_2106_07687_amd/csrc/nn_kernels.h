@@ -105,42 +105,16 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const
     }
 }
 
-// GRU gate update for one layer (gate rows r, z, n):
-// r = s(gi_r + gh_r), z = s(gi_z + gh_z), n = tanh(gi_n + r gh_n),
-// h_out = (1 - z) n + z h_in (h_out may be h_in).  Optionally stores r, z, n,
-// gh_n for the backward pass.
-__global__ void k_gru_gates(int B, int H, const float *__restrict__ Gi, const float *__restrict__ Gh,
-                            const float *hin, float *h, uint16_t *__restrict__ hb, int ldhb,
-                            float *__restrict__ save) {
-  const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= static_cast<size_t>(B) * H) return;
-  const int b = static_cast<int>(t / H), j = static_cast<int>(t % H);
-  const float *gi = Gi + static_cast<size_t>(b) * 3 * H;
-  const float *gh = Gh + static_cast<size_t>(b) * 3 * H;
-  const float r = sigmoidf_(gi[j] + gh[j]);
-  const float z = sigmoidf_(gi[H + j] + gh[H + j]);
-  const float n = tanhf(gi[2 * H + j] + r * gh[2 * H + j]);
-  const float hp = hin[t];
-  const float hn = (1.0f - z) * n + z * hp;
-  h[t] = hn;
-  hb[static_cast<size_t>(b) * ldhb + j] = f2bf(hn);
-  if (save) {
-    float *s = save + static_cast<size_t>(b) * 4 * H;
-    s[j] = r;
-    s[H + j] = z;
-    s[2 * H + j] = n;
-    s[3 * H + j] = gh[2 * H + j];
-  }
-}
-
-// Recurrent product fused with the gate update: Gh = h_in W_hh^T for a tile of
-// 64 rows x 32 hidden units and all three gates (MFMA 16x16x16 BF16, the K
-// loop in 32-wide chunks as in k_gemm_nt_bf16, so the accumulators hold the
-// values that kernel would store), then the gate update of k_gru_gates on the
-// accumulators: bitwise the pair k_gemm_nt_bf16 + k_gru_gates without the
-// FP32 Gh round trip.  Wave w owns rows 16w..16w+15 of the tile, both
-// 16-unit halves and the three gates, so each lane holds r, z, n inputs of
-// the same (row, unit).  H must be a multiple of 32.
+// One GRU time step of a layer (gate rows r, z, n): the recurrent product
+// Gh = h_in W_hh^T for a tile of 64 rows x 32 hidden units and all three
+// gates (MFMA 16x16x16 BF16, the K loop in 32-wide chunks as in
+// k_gemm_nt_bf16), then, on the accumulators, with Gi = x W_ih^T from that
+// kernel: r = s(gi_r + gh_r), z = s(gi_z + gh_z), n = tanh(gi_n + r gh_n),
+// h = (1 - z) n + z h_in (FP32; h may be hin), its BF16 copy into hb_out (not
+// hb_in), and optionally r, z, n, gh_n for the backward pass.  Gh never goes
+// to memory.  Wave w owns rows 16w..16w+15 of the tile, both 16-unit halves
+// and the three gates, so each lane holds r, z, n inputs of the same (row,
+// unit).  H must be a multiple of 32.
 __global__ void __launch_bounds__(256) k_gru_step_fused(int B, int H, const float *__restrict__ Gi,
                                                         const uint16_t *__restrict__ hb_in,
                                                         const float *hin, const uint16_t *__restrict__ Whh,

@@ -50,7 +50,7 @@ struct Trainer {
   std::vector<DevBuf<float>> sv;             // per layer: seg x Bt x 4H saved gates
   std::vector<DevBuf<uint16_t>> dgi, dgh;    // per layer: seg x Bt x 3H
   std::vector<DevBuf<float>> dh;             // per layer: Bt x H
-  DevBuf<float> dhp, Gi, Gh, Yseg;           // Yseg: seg x Bt x O
+  DevBuf<float> dhp, Gi, Yseg;               // Yseg: seg x Bt x O
   DevBuf<uint16_t> dYb;                      // seg x Bt x O
   DevBuf<float> grad, part;
   DevBuf<double> lpart;
@@ -82,7 +82,6 @@ void ensure(Net &n, Trainer &tr, int T, int Bt, int seg) {
   }
   tr.dhp.alloc(bh);
   tr.Gi.alloc(3 * bh);
-  tr.Gh.alloc(3 * bh);
   tr.Yseg.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.dYb.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.grad.alloc(static_cast<size_t>(n.nparam));
@@ -100,14 +99,11 @@ void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector
     const uint16_t *in = l == 0 ? x : h16_out[l - 1];
     const int K = l == 0 ? n.K0 : n.H;
     gemm_nt(s, tr.Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
-    if (n.H % 32 == 0 && h16_in[l] != h16_out[l]) {   // recurrent product + gates fused
-      hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(tr.Bt, 64)), dim3(256), 0, s, tr.Bt, n.H, tr.Gi.p,
-                         h16_in[l], h32_in[l], n.whh_b[l].p, h32[l], h16_out[l], save[l]);
-      continue;
-    }
-    gemm_nt(s, tr.Bt, H3, n.H, h16_in[l], n.H, n.whh_b[l].p, n.H, tr.Gh.p, H3);
-    hipLaunchKernelGGL(k_gru_gates, dim3(blocks(static_cast<size_t>(tr.Bt) * n.H, 256)), dim3(256), 0, s, tr.Bt,
-                       n.H, tr.Gi.p, tr.Gh.p, h32_in[l], h32[l], h16_out[l], n.H, save[l]);
+    // recurrent product + gates in one kernel (H a multiple of 32; the BF16
+    // input and output states are distinct buffers)
+    if (h16_in[l] == h16_out[l]) throw DnnmgError{DNNMG_EDEVICE, "fwd_step: BF16 state aliases its output"};
+    hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(tr.Bt, 64)), dim3(256), 0, s, tr.Bt, n.H, tr.Gi.p,
+                       h16_in[l], h32_in[l], n.whh_b[l].p, h32[l], h16_out[l], save[l]);
   }
   if (Y) gemm_nt(s, tr.Bt, n.O, n.H, h16_out[n.layers - 1], n.H, n.wout_b.p, n.H, Y, n.O);
   check(hipGetLastError(), "fwd_step");
@@ -186,16 +182,10 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
                            tr.sv[l].p + static_cast<size_t>(k) * 4 * bh, tr.hs32[l].p + k * bh, dgi, dgh,
                            tr.dh[l].p);
         // dh_{t-1} = g z + dgh W_hh; gradient into the layer below: dgi W_ih.
-        // With the transposed BF16 weights these are NT products (K = 3H,
-        // a multiple of the 32-wide K tile when H is).
-        if (H % 32 == 0) {
-          gemm_nt(s, Bt, H, 3 * H, dgh, 3 * H, n.whh_t[l].p, 3 * H, tr.dh[l].p, H, true);
-          if (l > 0) gemm_nt(s, Bt, H, 3 * H, dgi, 3 * H, n.wih_t[l].p, 3 * H, tr.dh[l - 1].p, H, true);
-        } else {
-          gemm_strided(s, Bt, H, 3 * H, dgh, 3 * H, 1, n.whh_b[l].p, 1, H, tr.dh[l].p, H, true, tr.part);
-          if (l > 0)
-            gemm_strided(s, Bt, H, 3 * H, dgi, 3 * H, 1, n.wih_b[l].p, 1, H, tr.dh[l - 1].p, H, true, tr.part);
-        }
+        // With the transposed BF16 weights these are NT products (K = 3H, a
+        // multiple of the 32-wide K tile).
+        gemm_nt(s, Bt, H, 3 * H, dgh, 3 * H, n.whh_t[l].p, 3 * H, tr.dh[l].p, H, true);
+        if (l > 0) gemm_nt(s, Bt, H, 3 * H, dgi, 3 * H, n.wih_t[l].p, 3 * H, tr.dh[l - 1].p, H, true);
       }
     }
     // weight gradients of the segment: K = ns * Bt rows at once
