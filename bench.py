@@ -492,6 +492,12 @@ def main():
     ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
                     help="keep Newton's Jacobians across iterations and steps while the "
                          "residual contracts by 0.1 or better (0: rebuild every step)")
+    ap.add_argument("--nu-coarse", type=int, default=0,
+                    help="full-depth GMG leg: sweeps before and after on the V-cycle levels below the "
+                         "one GMRES works on (0: the same V(2,2) on every level)")
+    ap.add_argument("--nu-coarse-dnnmg", type=int, default=1,
+                    help="the same for the coarse solves of the DNN-MG leg (measured: fewer sweeps "
+                         "below level 5 cost fewer extra Krylov steps than they save)")
     ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
                     help="0: additive cell-Vanka, 1: coloured multiplicative cell-Vanka")
     ap.add_argument("--no-graphs", action="store_true",
@@ -525,7 +531,7 @@ def main():
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
                     use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
-                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother)
+                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother, nu_coarse=args.nu_coarse)
     F = args.level
     if args.profile == "all":
         gmg_keys = dnn_keys = None
@@ -574,6 +580,7 @@ def main():
         ctx.step(sfr, args.dt)
         xF.append(sfr.get()[0])
     sfr.close()
+    ctx.set_params(nu_coarse=args.nu_coarse_dnnmg)   # coarse solves of the DNN-MG leg
     train_info = None
     if args.train_net:
         train_info = train_dnnmg(ctx, net, xF, args.coarse_level, args.dt, args.train_net_iters,
@@ -709,7 +716,8 @@ def main():
                    "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
                    "newton_predictor": args.newton_predictor,
-                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother},
+                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother,
+                   "nu_coarse": {"gmg": args.nu_coarse, "dnnmg": args.nu_coarse_dnnmg}},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

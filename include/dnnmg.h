@@ -109,6 +109,11 @@ typedef struct {
                              not converged after this many iterations is redone
                              with the plain right-hand side (stats.fallback =
                              1); 0: only when Newton fails (newton_max)      */
+  int nu_coarse;          /* 0: every level of a V-cycle takes nu_pre / nu_post
+                             sweeps; k in 1..8: the levels below the one the
+                             cycle is called on take k sweeps before and k
+                             after (the level the Krylov solver works on keeps
+                             nu_pre / nu_post)                                */
   int smoother;           /* 0: additive cell-Vanka (every cell's correction,
                              averaged over the cells of a node, omega times);
                              1: coloured multiplicative cell-Vanka (greedy cell

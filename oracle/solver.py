@@ -16,7 +16,8 @@
   index order take the smallest colour no cell sharing a node has taken
   (reading N17); per colour the residual is recomputed and every cell of the
   colour adds omega times its local correction (the cells of a colour share
-  no node).
+  no node).  Optionally (reading N18) the levels below the one a V-cycle is
+  called on take nu_coarse sweeps before and after instead of (nu1, nu2).
 """
 from __future__ import annotations
 
@@ -119,10 +120,11 @@ class MGHierarchy:
     injected to each level: coarse vertices keep their ids, so injection is
     the prefix of the fine vector)."""
 
-    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive"):
+    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0):
         self.levels = levels
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
+        self.nu_coarse = nu_coarse          # > 0: sweeps before and after on the levels below the top
         self.smoother = smoother
         self.colours = [cell_colours(L.cells) for L in levels] if smoother == "coloured" else None
         self.J = []
@@ -150,17 +152,20 @@ class MGHierarchy:
             return vanka_sweep_coloured(self.J[l], self.blocks[l], L.cells, self.colours[l], x, b, self.omega)
         return vanka_sweep(self.J[l], self.blocks[l], L.cells, x, b, self.omega)
 
-    def vcycle(self, l, b, x=None):
-        """One V(nu1, nu2) cycle on level l for J_l x = b."""
+    def vcycle(self, l, b, x=None, top=None):
+        """One V(nu1, nu2) cycle on level l for J_l x = b (V(nu_coarse,
+        nu_coarse) on the levels below the one it is called on, if set)."""
+        top = l if top is None else top
         if l == 0:
             return sla.lu_solve(self.lu0, b)
+        nu1, nu2 = (self.nu_coarse, self.nu_coarse) if self.nu_coarse > 0 and l != top else (self.nu1, self.nu2)
         x = np.zeros_like(b) if x is None else x.copy()
-        for _ in range(self.nu1):
+        for _ in range(nu1):
             x = self.sweep(l, x, b)
         r = b - self.J[l] @ x
-        e = self.vcycle(l - 1, self._restrict(l, r))
+        e = self.vcycle(l - 1, self._restrict(l, r), top=top)
         x = x + self._prolong(l, e)
-        for _ in range(self.nu2):
+        for _ in range(nu2):
             x = self.sweep(l, x, b)
         return x
 
@@ -225,7 +230,7 @@ def gmres(A, b, precond, rtol=1e-2, restart=30, maxit=100):
 
 
 def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1e-2,
-                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6, smoother="additive"):
+                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0):
     """Newton's method (eq. newton) with GMRES + V-cycle linear solves, as in
     the coarse solve of Algorithm 1 (full steps, reading N1)."""
     fine = levels[-1]
@@ -240,7 +245,7 @@ def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1
             return x, stats
         if it == maxit:
             break
-        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother)
+        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother, nu_coarse)
         w, k, _ = gmres(mg.J[-1], R, lambda v: mg.vcycle(len(levels) - 1, v),
                         gmres_rtol, restart, gmres_max)
         stats["gmres"].append(k)

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
                 ("newton_predictor", C.c_int), ("jacobian_reuse", C.c_int),
                 ("reuse_contraction", C.c_double), ("switch_off_newton", C.c_int),
-                ("smoother", C.c_int),
+                ("nu_coarse", C.c_int), ("smoother", C.c_int),
                 ("stream", C.c_void_p)]
 
 

@@ -41,7 +41,7 @@ bool params_ok(const dnnmg_params *p) {
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
          (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1) &&
          (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && (p->smoother == 0 || p->smoother == 1) &&
-         p->switch_off_newton >= 0 &&
+         p->switch_off_newton >= 0 && p->nu_coarse >= 0 && p->nu_coarse <= 8 &&
          p->reuse_contraction > 0 &&
          p->reuse_contraction < 1;
 }
@@ -257,6 +257,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->reuse_contraction = 0.1;
   p->smoother = 0;
   p->switch_off_newton = 0;
+  p->nu_coarse = 0;
   p->stream = nullptr;
   return DNNMG_OK;
 }

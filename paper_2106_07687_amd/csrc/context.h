@@ -202,7 +202,12 @@ class Solver {
     hipGraphExec_t exec = nullptr;
     long gen = -1;
   };
-  std::map<std::tuple<int, const void *, const void *>, GraphSlot> vgraphs_;
+  // key: level, whether the level is the top of its cycle, b, x
+  std::map<std::tuple<int, int, const void *, const void *>, GraphSlot> vgraphs_;
+  int cycle_top_ = -1;   // level of the outermost vcycle call in progress
+  int cycle_depth_ = 0;
+  bool inner_level(int l) const { return ctx_coarse_sweeps() > 0 && l != cycle_top_; }
+  int ctx_coarse_sweeps() const;
   GraphSlot ginv_;
   bool capturing_ = false;
   template <class F>

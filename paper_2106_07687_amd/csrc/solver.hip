@@ -255,6 +255,11 @@ Solver<T>::~Solver() {
 }
 
 template <typename T>
+int Solver<T>::ctx_coarse_sweeps() const {
+  return ctx_->prm.nu_coarse;
+}
+
+template <typename T>
 void Solver<T>::clear_graphs() {
   for (auto &kv : vgraphs_)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -672,8 +677,9 @@ SmallCycle<T> Solver<T>::small_params(int top, const T *b, T *x) {
     V.x = l == top ? x : o.x.p;
   }
   P.top = top;
-  P.nu_pre = ctx_->prm.nu_pre;
-  P.nu_post = ctx_->prm.nu_post;
+  // every level of the one-workgroup cycle lies below the top when nu_coarse is set
+  P.nu_pre = ctx_->prm.nu_coarse > 0 ? ctx_->prm.nu_coarse : ctx_->prm.nu_pre;
+  P.nu_post = ctx_->prm.nu_coarse > 0 ? ctx_->prm.nu_coarse : ctx_->prm.nu_post;
   P.omega = static_cast<T>(ctx_->prm.vanka_omega);
   P.nblk = nblk_;
   P.nb = nb_;
@@ -691,12 +697,23 @@ void Solver<T>::launch_small(int top, const T *b, T *x) {
 
 template <typename T>
 void Solver<T>::vcycle(int l, const T *b, T *x) {
-  if (l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0) {   // the one-workgroup cycle is additive
+  // the outermost call's level is the top of the cycle (nu_pre / nu_post
+  // sweeps); the levels below take nu_coarse sweeps when that is set
+  struct Depth {
+    int &d;
+    explicit Depth(int &v) : d(v) { ++d; }
+    ~Depth() { --d; }
+  };
+  if (cycle_depth_ == 0) cycle_top_ = l;
+  Depth guard(cycle_depth_);
+  // the one-workgroup cycle is additive and uses one sweep count for all its levels
+  if (l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0 && (ctx_->prm.nu_coarse == 0 || l != cycle_top_)) {
     launch_small(l, b, x);
     return;
   }
   if (l > 0 && use_graph(l)) {
-    const auto key = std::make_tuple(l, static_cast<const void *>(b), static_cast<const void *>(x));
+    const auto key = std::make_tuple(l, l == cycle_top_ ? 1 : 0, static_cast<const void *>(b),
+                                     static_cast<const void *>(x));
     // bound the cache: keys of freed work vectors are never looked up again
     if (vgraphs_.size() >= 512 && vgraphs_.find(key) == vgraphs_.end()) clear_graphs();
     graph_run(vgraphs_[key], [&]() { vcycle_body(l, b, x); });
@@ -723,7 +740,9 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
   OpLevel<T> &o = ops_[l];
   OpLevel<T> &oc = ops_[l - 1];
   const size_t n = 3 * static_cast<size_t>(L.h.N);
-  const int nu1 = ctx_->prm.nu_pre, nu2 = ctx_->prm.nu_post;
+  const bool inner = inner_level(l);
+  const int nu1 = inner ? ctx_->prm.nu_coarse : ctx_->prm.nu_pre;
+  const int nu2 = inner ? ctx_->prm.nu_coarse : ctx_->prm.nu_post;
   // zero iterate: the first sweep stores its update (no separate fill)
   if (nu1 == 0)
     hipLaunchKernelGGL(k_fill<T>, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, x, n, T(0));

@@ -261,3 +261,39 @@ def test_coloured_smoother_steps_match_oracle(precision, bar):
             st.set(x_ref, n * DT)               # per-step error
     st.close()
     ctx.close()
+
+
+def test_coarse_sweep_count_parity(c1):
+    """nu_coarse = 1: V-cycles called on levels 3 and 2 take one sweep before
+    and after on the levels below (oracle to 1e-10, FP64); FP64 time steps
+    still reach the oracle's x_n (1e-10)."""
+    macro, lev, ctx, prob = c1
+    x = random_state(lev[3].n_nodes, 26) * 0.3
+    st = ctx.state(3)
+    st.set(x, 0.0)
+    ctx.set_params(nu_coarse=1)
+    try:
+        ctx.linearize(st, 3, DT)
+        mg = solver.MGHierarchy(lev, prob, x, nu_coarse=1)
+        b = random_state(lev[3].n_nodes, 27)
+        b.reshape(-1, 3)[lev[3].dirichlet_nodes(), :2] = 0.0
+        for l in (3, 2, 1):
+            bl = b[:3 * lev[l].n_nodes].copy()
+            bl.reshape(-1, 3)[lev[l].dirichlet_nodes(), :2] = 0.0
+            for rep in range(2):                   # captured, then replayed
+                v_gpu = ctx.vcycle(l, bl)
+                v_ref = mg.vcycle(l, bl)
+                assert rel(v_gpu, v_ref) < 1e-10, (l, rep, rel(v_gpu, v_ref))
+        ctx.set_params(newton_tol=1e-14)
+        s2 = ctx.state(3)
+        x_ref = np.zeros(3 * lev[3].n_nodes)
+        for n in range(1, 3):
+            ctx.step(s2, DT)
+            x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=1e-15)
+            e = rel(s2.get()[0], x_ref)
+            print(f"[nu_coarse] step {n}: {e:.2e}", flush=True)
+            assert e < 1e-10
+        s2.close()
+    finally:
+        ctx.set_params(nu_coarse=0, newton_tol=1e-10)
+        st.close()

@@ -152,3 +152,24 @@ def test_mg_newton_with_coloured_smoother_matches_direct_newton():
     # the multiplicative sweep is the stronger smoother: fewer Krylov steps
     _, sa = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, smoother="additive", omega=0.6)
     assert sum(st["gmres"]) < sum(sa["gmres"]), (st["gmres"], sa["gmres"])
+
+
+def test_coarse_sweep_count_changes_only_the_lower_levels():
+    """nu_coarse acts below the level a cycle is called on: a cycle called
+    on level 1 (whose only lower level is the direct solve) is unchanged, a
+    cycle on level 2 changes; MG-Newton with it still reaches the direct
+    Newton solution."""
+    m = channel_obstacle(1)
+    lev = mesh.hierarchy(m, 2)
+    prob = fem.Problem(nu=m.nu, dt=0.01)
+    x = np.random.default_rng(3).uniform(-0.3, 0.3, 3 * lev[2].n_nodes)
+    a = solver.MGHierarchy(lev, prob, x)
+    c = solver.MGHierarchy(lev, prob, x, nu_coarse=1)
+    b1 = np.random.default_rng(4).standard_normal(3 * lev[1].n_nodes)
+    np.testing.assert_array_equal(a.vcycle(1, b1), c.vcycle(1, b1))
+    b2 = np.random.default_rng(5).standard_normal(3 * lev[2].n_nodes)
+    assert np.abs(a.vcycle(2, b2) - c.vcycle(2, b2)).max() > 1e-8
+    x0 = np.zeros(3 * lev[-1].n_nodes)
+    xd = solver.newton_step(lev[-1], prob, x0, 0.2, tol=1e-13)
+    xm, _ = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, nu_coarse=1)
+    np.testing.assert_allclose(xm, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
