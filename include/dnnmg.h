@@ -84,8 +84,9 @@ typedef struct {
                              workgroup against its launches, and keep the
                              fastest (scheduling only: results are bitwise the
                              same); 0: 256 throughout, separate kernels, one
-                             thread per row; 2: as 0 with the fused apply and
-                             four threads per SpMV row on every level;
+                             thread per row; 2: as 0 with the fused apply
+                             (sixteen lanes per cell) and four threads per
+                             SpMV row on every level;
                              3: as 0 with the single-workgroup bottom cycle  */
   int newton_predictor;   /* 0: Newton starts from x_{n-1}; 1: from the linear
                              extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
@@ -393,12 +394,14 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..8] = SpMV, Vanka apply,
+/* Workgroup sizes in use on `level`: block_sizes[0..9] = SpMV, Vanka apply,
  * Vanka update, restriction from `level`, prolongation to `level`, the fused
  * residual + Vanka apply (0: SpMV and apply run separately), the
  * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0),
- * the fused residual + restriction (0: separate), and the SpMV with four
- * threads per row (0: one thread per row) (9 ints, caller-owned).
+ * the fused residual + restriction (0: separate), the SpMV with four
+ * threads per row (0: one thread per row), and the lanes per cell of the
+ * fused residual + Vanka apply (4 or 16; 0 when not fused) (10 ints,
+ * caller-owned).
  * DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:

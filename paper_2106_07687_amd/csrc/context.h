@@ -130,7 +130,8 @@ struct OpLevel {
   // coarser one
   int bs_spmv = 256, bs_apply = 256, bs_update = 256, bs_restrict = 256, bs_prolong = 256;
   int bs_spmv4 = 0;    // > 0: four threads per row (k_spmv4) at this size
-  int bs_smooth = 0;   // > 0: residual + Vanka apply fused (k_vanka_smooth) at this size
+  int bs_smooth = 0;   // > 0: residual + Vanka apply fused at this size
+  int smooth_lanes = 4;   // lanes per cell of the fused kernel: 4 (k_vanka_smooth) or 16 (k_vanka_smooth16)
   int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
 };
 
@@ -171,12 +172,13 @@ class Solver {
   // and 256 and keeps the fastest (the choice changes scheduling only: every
   // thread does the same arithmetic, results are bitwise the same).
   void autotune();
-  // Fused residual + Vanka apply and four threads per SpMV row on every
-  // level, workgroup size 256 (a fixed configuration, e.g. for reproducible
-  // comparisons).
+  // Fused residual + Vanka apply (sixteen lanes per cell) and four threads
+  // per SpMV row on every level, workgroup size 256 (a fixed configuration,
+  // e.g. for reproducible comparisons).
   void fuse_all() {
     for (auto &o : ops_) {
       o.bs_smooth = 256;
+      o.smooth_lanes = 16;
       o.bs_rres = 256;
       o.bs_spmv4 = 256;
     }

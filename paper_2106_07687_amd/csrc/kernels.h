@@ -797,6 +797,56 @@ __global__ void __launch_bounds__(256) k_vanka_smooth(LevelView L, const T *__re
   }
 }
 
+// The same with sixteen lanes per cell: lane 4a + q sums partial q of the
+// residual row of the cell's node a (the split of k_spmv4), the four
+// partials are combined as (s0 + s1) + (s2 + s3) and the twelve residual
+// values exchanged between the cell's lanes; lane i < 12 forms correction row
+// i with the arithmetic of k_vanka_apply.  Bitwise k_spmv followed by
+// k_vanka_apply.  The workgroup size is a multiple of 16.
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_smooth16(LevelView L, const T *__restrict__ JQ,
+                                                        const T *__restrict__ JX, const T *__restrict__ x,
+                                                        const T *__restrict__ b, const T *__restrict__ inv,
+                                                        T *__restrict__ delta) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = gid >> 4, sub = gid & 15, a = sub >> 2, q = sub & 3;
+  const bool live = c < L.C;
+  T p0 = 0, p1 = 0, p2 = 0;
+  int node = 0;
+  if (live) {
+    const int4 cn = L.cells[c];
+    node = a == 0 ? cn.x : a == 1 ? cn.y : a == 2 ? cn.z : cn.w;
+    spmv_row_part(L, JQ, JX, x, node, q, p0, p1, p2);
+  }
+  const int lc = (threadIdx.x & 63) & ~15;   // first lane of the cell's sixteen
+  const int la = lc + 4 * a;                 // first lane of node a's four
+  T s[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    s[k][0] = __shfl(p0, la + k);
+    s[k][1] = __shfl(p1, la + k);
+    s[k][2] = __shfl(p2, la + k);
+  }
+  T r0 = 0, r1 = 0, r2 = 0;
+  if (live) {
+    r0 = b[3 * node] - ((s[0][0] + s[1][0]) + (s[2][0] + s[3][0]));
+    r1 = b[3 * node + 1] - ((s[0][1] + s[1][1]) + (s[2][1] + s[3][1]));
+    r2 = b[3 * node + 2] - ((s[0][2] + s[1][2]) + (s[2][2] + s[3][2]));
+  }
+  T rc[12];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    rc[3 * k] = __shfl(r0, lc + 4 * k);
+    rc[3 * k + 1] = __shfl(r1, lc + 4 * k);
+    rc[3 * k + 2] = __shfl(r2, lc + 4 * k);
+  }
+  if (!live || sub >= 12) return;
+  T acc = 0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc += inv[static_cast<size_t>(12 * sub + j) * L.C + c] * rc[j];
+  delta[static_cast<size_t>(sub) * L.C + c] = acc;
+}
+
 // x_j += omega / m_j * sum over the cells containing j of their corrections.
 // The first kCadj (cell, slot) entries of a node are loaded before any of
 // their corrections, so that a thread waits on two memory latencies, not on

@@ -451,7 +451,19 @@ void Solver<T>::autotune() {
         hipLaunchKernelGGL(k_vanka_smooth<T>, dim3(blocks(4 * static_cast<size_t>(L.h.C), bs)), dim3(bs), 0, s,
                            v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.inv.p, o.delta.p);
       });
-      if (last_t < t_sep) o.bs_smooth = bsm;
+      const float t_four = last_t;
+      const int bsm16 = pick([&](int bs) {
+        hipLaunchKernelGGL(k_vanka_smooth16<T>, dim3(blocks(16 * static_cast<size_t>(L.h.C), bs)), dim3(bs), 0,
+                           s, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.inv.p, o.delta.p);
+      });
+      const float t_sixteen = last_t;
+      o.smooth_lanes = 4;
+      if (t_sixteen < t_four && t_sixteen < t_sep) {
+        o.bs_smooth = bsm16;
+        o.smooth_lanes = 16;
+      } else if (t_four < t_sep) {
+        o.bs_smooth = bsm;
+      }
       o.bs_update = pick([&](int bs) {
         hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.delta.p, omega,
                            o.t.p, 0);
@@ -613,8 +625,12 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
   const T *r = b;
   if (!zero_start && o.bs_smooth > 0) {
     ProfScope ps(ctx_->prof, s, "vanka_smooth", l);
-    hipLaunchKernelGGL(k_vanka_smooth<T>, dim3(blocks(4 * static_cast<size_t>(L.h.C), o.bs_smooth)),
-                       dim3(o.bs_smooth), 0, s, L.view(), o.JQ.p, o.JX.p, x, b, o.inv.p, o.delta.p);
+    if (o.smooth_lanes == 16)
+      hipLaunchKernelGGL(k_vanka_smooth16<T>, dim3(blocks(16 * static_cast<size_t>(L.h.C), o.bs_smooth)),
+                         dim3(o.bs_smooth), 0, s, L.view(), o.JQ.p, o.JX.p, x, b, o.inv.p, o.delta.p);
+    else
+      hipLaunchKernelGGL(k_vanka_smooth<T>, dim3(blocks(4 * static_cast<size_t>(L.h.C), o.bs_smooth)),
+                         dim3(o.bs_smooth), 0, s, L.view(), o.JQ.p, o.JX.p, x, b, o.inv.p, o.delta.p);
   } else {
     if (!zero_start) {
       spmv(l, x, b, o.r.p);

@@ -120,7 +120,7 @@ def test_autotuned_launches_are_bitwise_equal():
     for l in range(LEVEL + 1):
         cfg = ctxs[0].launch_config(l)
         print(f"[tune] level {l}: {cfg}", flush=True)
-        assert set(cfg.values()) <= {0, 64, 128, 256, 1024}
+        assert set(cfg.values()) <= {0, 4, 16, 64, 128, 256, 1024}
         assert set(ctxs[1].launch_config(l).values()) <= {0, 256}
     sts = [c.state(LEVEL) for c in ctxs]
     for k in range(2):
@@ -132,8 +132,8 @@ def test_autotuned_launches_are_bitwise_equal():
 
 
 def test_fused_residual_and_apply_is_bitwise_equal():
-    """autotune=2 fuses the residual into the Vanka apply and runs the SpMV
-    with four threads per row on every level."""
+    """autotune=2 fuses the residual into the Vanka apply (sixteen lanes per
+    cell) and runs the SpMV with four threads per row on every level."""
     import paper_2106_07687_amd as P
     macro = channel_obstacle(2)
     ctxs = []
@@ -143,6 +143,7 @@ def test_fused_residual_and_apply_is_bitwise_equal():
         ctxs.append(ctx)
     assert all(ctxs[0].launch_config(l)["vanka_smooth"] == 256 for l in range(1, LEVEL + 1))
     assert all(ctxs[0].launch_config(l)["spmv4"] == 256 for l in range(LEVEL + 1))
+    assert all(ctxs[0].launch_config(l)["smooth_lanes"] == 16 for l in range(1, LEVEL + 1))
     lev = mesh.hierarchy(macro, LEVEL)
     x = random_state(lev[LEVEL].n_nodes, 5) * 0.3
     sts = []
