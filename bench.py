@@ -495,9 +495,10 @@ def main():
     ap.add_argument("--nu-coarse", type=int, default=0,
                     help="full-depth GMG leg: sweeps before and after on the V-cycle levels below the "
                          "one GMRES works on (0: the same V(2,2) on every level)")
-    ap.add_argument("--nu-coarse-dnnmg", type=int, default=1,
-                    help="the same for the coarse solves of the DNN-MG leg (measured: fewer sweeps "
-                         "below level 5 cost fewer extra Krylov steps than they save)")
+    ap.add_argument("--dnnmg-sweeps", default="2,1,1",
+                    help="pre,post,coarse sweeps of the V-cycles of the DNN-MG leg's level-5 solves "
+                         "(measured on level 5: V(2,1) with V(1,1) below is the fastest schedule; the "
+                         "GMG leg keeps V(2,2) throughout)")
     ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
                     help="0: additive cell-Vanka, 1: coloured multiplicative cell-Vanka")
     ap.add_argument("--no-graphs", action="store_true",
@@ -580,7 +581,8 @@ def main():
         ctx.step(sfr, args.dt)
         xF.append(sfr.get()[0])
     sfr.close()
-    ctx.set_params(nu_coarse=args.nu_coarse_dnnmg)   # coarse solves of the DNN-MG leg
+    pre, post, coarse = (int(v) for v in args.dnnmg_sweeps.split(","))
+    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse)   # coarse solves of the DNN-MG leg
     train_info = None
     if args.train_net:
         train_info = train_dnnmg(ctx, net, xF, args.coarse_level, args.dt, args.train_net_iters,
@@ -717,7 +719,9 @@ def main():
                    "graphs": not args.no_graphs, "profile": args.profile,
                    "newton_predictor": args.newton_predictor,
                    "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother,
-                   "nu_coarse": {"gmg": args.nu_coarse, "dnnmg": args.nu_coarse_dnnmg}},
+                   "v_cycle": {"gmg": f"V(2,2), {args.nu_coarse or 'same'} below the top",
+                               "dnnmg": "V({},{}), V({c},{c}) below the top".format(
+                                   *args.dnnmg_sweeps.split(",")[:2], c=args.dnnmg_sweeps.split(",")[2])}},
         "roofline": roof,
         "mfma": mfma,
         "train": train,
