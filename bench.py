@@ -671,7 +671,9 @@ def main():
         tsec = (time.perf_counter() - t0) / args.train_iters
         H, I, O, Lr = args.hidden, net.n_in, net.n_out, args.layers
         fwd = 2.0 * (3 * H * ((I + 31) // 32 * 32) + 3 * H * H + (Lr - 1) * 6 * H * H + O * H)
-        flop = T * B * fwd * (1 + 1 + 2)      # forward, recompute, backward (2x forward)
+        nseg = (T + 7) // 8                   # checkpoints every 8 steps
+        # forward, recompute of all segments but the last, backward (2x forward)
+        flop = T * B * fwd * (1 + (nseg - 1) / nseg + 2)
         train = {"seq": T, "batch": B, "hidden": H, "layers": Lr, "ms_per_iter": round(1e3 * tsec, 2),
                  "model_tflop_per_iter": round(flop / 1e12, 4),
                  "tflops": round(flop / tsec / 1e12, 2), "mfma_frac": round(flop / tsec / 2.5e15, 5)}

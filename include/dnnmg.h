@@ -320,7 +320,8 @@ int dnnmg_net_targets(dnnmg_ctx *ctx, const dnnmg_state *coarse, dnnmg_net *net,
  * starting at 0 (independent of the network's inference state).  Exact
  * backpropagation through time with the forward pass recomputed from
  * checkpoints every `ckpt` steps; BF16 MFMA GEMMs with FP32 accumulation,
- * FP32 gates and gradients.
+ * FP32 gates and gradients.  1 <= T <= 4096, 1 <= B <= 2^22, T B <= 2^26
+ * and ckpt >= 1, else DNNMG_EINVAL.
  * dnnmg_net_gradient: host inputs, writes the FP32 gradient (n_params, flat
  * weight order) and the loss; no update.
  * dnnmg_train_step / _dev: one Adam step (beta = 0.9, 0.999, eps = 1e-8,

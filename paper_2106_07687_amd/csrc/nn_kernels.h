@@ -375,16 +375,18 @@ __global__ void k_reduce_split(int M, int N, int ld, int Z, long zstride, const 
 // (r, z, n, gh_n) and h_{t-1}.  Out: dgi = dL/d(W_ih x) (3H), dgh =
 // dL/d(W_hh h_{t-1}) (3H) as FP32 and BF16, dhp = g * z (the direct part of
 // dL/dh_{t-1}; the GEMM dgh W_hh is added to it afterwards).
-// g: dL/dh_t in; dhp: the z-path of dL/dh_{t-1} out (elementwise, may be g).
-__global__ void k_gru_gates_bwd(int B, int H, const float *g, const float *__restrict__ save,
-                                const float *__restrict__ hprev, uint16_t *__restrict__ dgi_b,
-                                uint16_t *__restrict__ dgh_b, float *dhp) {
+// g: dL/dh_t in, as the sum g + e (the carried gradient of the same layer plus
+// the one arriving from the layer above or the head, added here in FP32);
+// dhp: the z-path of dL/dh_{t-1} out (elementwise, may be g).
+__global__ void k_gru_gates_bwd(int B, int H, const float *g, const float *__restrict__ e,
+                                const float *__restrict__ save, const float *__restrict__ hprev,
+                                uint16_t *__restrict__ dgi_b, uint16_t *__restrict__ dgh_b, float *dhp) {
   const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<size_t>(B) * H) return;
   const int b = static_cast<int>(t / H), j = static_cast<int>(t % H);
   const float *s = save + static_cast<size_t>(b) * 4 * H;
   const float r = s[j], z = s[H + j], n = s[2 * H + j], ghn = s[3 * H + j];
-  const float gg = g[t], hp = hprev[t];
+  const float gg = g[t] + e[t], hp = hprev[t];
   const float dz = gg * (hp - n);
   const float dn = gg * (1.0f - z);
   const float dan = dn * (1.0f - n * n);
@@ -401,11 +403,17 @@ __global__ void k_gru_gates_bwd(int B, int H, const float *g, const float *__res
   dhp[t] = gg * z;
 }
 
-// dY = 2 (Y - D) / B (BF16 copy) and per-block partial sums of (Y - D)^2.
+// dY = 2 (Y - D) / B (BF16 copy) and per-block partial sums of (Y - D)^2,
+// for one time step per blockIdx.y (each step's B x O block and gridDim.x
+// partials follow the previous step's).
 __global__ void k_loss_grad(int B, int O, const float *__restrict__ Y, const float *__restrict__ D,
                             uint16_t *__restrict__ dYb, double *__restrict__ partial) {
   __shared__ double sh[256];
   const size_t n = static_cast<size_t>(B) * O;
+  Y += blockIdx.y * n;
+  D += blockIdx.y * n;
+  dYb += blockIdx.y * n;
+  partial += static_cast<size_t>(blockIdx.y) * gridDim.x;
   double s = 0.0;
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {

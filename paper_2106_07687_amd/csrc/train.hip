@@ -11,10 +11,17 @@ using namespace dnnmg;
 
 namespace {
 
-void gemm_nt(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+// C (+)= A(M,K) B(N,K)^T; M is split into launches of at most 32768 row
+// tiles (each row's result does not depend on the split).
+void gemm_nt(hipStream_t s, long M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
              float *C, int ldc, bool acc = false) {
-  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
-  hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, acc ? 1 : 0);
+  const long chunk = 32768L * GBM;
+  for (long m0 = 0; m0 < M; m0 += chunk) {
+    const int mc = static_cast<int>(std::min(chunk, M - m0));
+    dim3 grid((N + GBN - 1) / GBN, (mc + GBM - 1) / GBM);
+    hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, mc, N, K, A + m0 * lda, lda, B, ldb, C + m0 * ldc,
+                       ldc, acc ? 1 : 0);
+  }
   check(hipGetLastError(), "k_gemm_nt_bf16");
 }
 
@@ -26,8 +33,14 @@ void gemm_strided(hipStream_t s, int M, int N, int K, const uint16_t *A, long sA
   while (tiles * Z < 512 && K / (Z * 2) >= 1024) Z *= 2;
   dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, Z);
   if (Z == 1) {
-    hipLaunchKernelGGL(k_gemm_bf16_strided, grid, dim3(256), 0, s, M, N, K, K, A, sAm, sAk, B, sBn, sBk, C, ldc,
-                       0L, acc ? 1 : 0);
+    // M in launches of at most 32768 row tiles
+    const int chunk = 32768 * GBM;
+    for (int m0 = 0; m0 < M; m0 += chunk) {
+      const int mc = std::min(chunk, M - m0);
+      dim3 g1((N + GBN - 1) / GBN, (mc + GBM - 1) / GBM);
+      hipLaunchKernelGGL(k_gemm_bf16_strided, g1, dim3(256), 0, s, mc, N, K, K, A + m0 * sAm, sAm, sAk, B, sBn, sBk,
+                         C + static_cast<long>(m0) * ldc, ldc, 0L, acc ? 1 : 0);
+    }
     check(hipGetLastError(), "k_gemm_bf16_strided");
     return;
   }
@@ -50,7 +63,9 @@ struct Trainer {
   std::vector<DevBuf<float>> sv;             // per layer: seg x Bt x 4H saved gates
   std::vector<DevBuf<uint16_t>> dgi, dgh;    // per layer: seg x Bt x 3H
   std::vector<DevBuf<float>> dh;             // per layer: Bt x H
-  DevBuf<float> dhp, Gi, Yseg;               // Yseg: seg x Bt x O
+  DevBuf<float> Gi;                          // seg x Bt x 3H input projections
+  DevBuf<float> E;                           // seg x Bt x H gradient from above
+  DevBuf<float> Yseg;                        // seg x Bt x O
   DevBuf<uint16_t> dYb;                      // seg x Bt x O
   DevBuf<float> grad, part;
   DevBuf<double> lpart;
@@ -80,33 +95,43 @@ void ensure(Net &n, Trainer &tr, int T, int Bt, int seg) {
     tr.dgh[l].alloc(static_cast<size_t>(seg) * 3 * bh);
     tr.dh[l].alloc(bh);
   }
-  tr.dhp.alloc(bh);
-  tr.Gi.alloc(3 * bh);
+  tr.Gi.alloc(static_cast<size_t>(seg) * 3 * bh);
+  tr.E.alloc(static_cast<size_t>(seg) * bh);
   tr.Yseg.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.dYb.alloc(static_cast<size_t>(seg) * Bt * n.O);
   tr.grad.alloc(static_cast<size_t>(n.nparam));
   tr.lpart.alloc(static_cast<size_t>(T) * 1024);
 }
 
-// One forward GRU step for all layers.  h32_in/h16_in: state before the step
-// (per layer), h32/h16_out: state after (may alias the inputs: in place);
-// save: gate storage per layer (or null); Y: head output (or null).
-void fwd_step(Net &n, Trainer &tr, hipStream_t s, const uint16_t *x, std::vector<float *> &h32_in,
-              std::vector<float *> &h32, std::vector<uint16_t *> &h16_in, std::vector<uint16_t *> &h16_out,
-              std::vector<float *> &save, float *Y) {
-  const int H3 = 3 * n.H;
+// The ns steps t0 .. t0 + ns - 1 of the whole stack, layer by layer: one
+// input-projection GEMM over all ns steps of a layer, then its recurrent
+// steps (k_gru_step_fused, BF16 state slot k in, slot k + 1 out).  On entry
+// slot 0 of hs32[l] / hs16[l] holds every layer's state before t0.  With
+// `keep`, every FP32 state (slots 1 .. ns), the gates and the head outputs
+// Yseg are kept for the backward sweep; without, the FP32 state is updated
+// in place in slot 0.
+void segment_forward(Net &n, Trainer &tr, hipStream_t s, int t0, int ns, bool keep) {
+  const int Bt = tr.Bt, H = n.H, H3 = 3 * H;
+  const size_t bh = static_cast<size_t>(Bt) * H;
   for (int l = 0; l < n.layers; ++l) {
-    const uint16_t *in = l == 0 ? x : h16_out[l - 1];
-    const int K = l == 0 ? n.K0 : n.H;
-    gemm_nt(s, tr.Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
-    // recurrent product + gates in one kernel (H a multiple of 32; the BF16
-    // input and output states are distinct buffers)
-    if (h16_in[l] == h16_out[l]) throw DnnmgError{DNNMG_EDEVICE, "fwd_step: BF16 state aliases its output"};
-    hipLaunchKernelGGL(k_gru_step_fused, dim3(n.H / 32, blocks(tr.Bt, 64)), dim3(256), 0, s, tr.Bt, n.H, tr.Gi.p,
-                       h16_in[l], h32_in[l], n.whh_b[l].p, h32[l], h16_out[l], save[l]);
+    const uint16_t *in = l == 0 ? tr.Xb.p + static_cast<size_t>(t0) * Bt * n.K0 : tr.hs16[l - 1].p + bh;
+    const int K = l == 0 ? n.K0 : H;
+    gemm_nt(s, static_cast<long>(ns) * Bt, H3, K, in, K, n.wih_b[l].p, K, tr.Gi.p, H3);
+    for (int k = 0; k < ns; ++k) {
+      float *h32_in = tr.hs32[l].p + (keep ? k * bh : 0);
+      float *h32_out = tr.hs32[l].p + (keep ? (k + 1) * bh : 0);
+      float *save = keep ? tr.sv[l].p + static_cast<size_t>(k) * 4 * bh : nullptr;
+      // recurrent product + gates in one kernel (H a multiple of 32; the BF16
+      // input and output states are distinct slots)
+      hipLaunchKernelGGL(k_gru_step_fused, dim3(H / 32, blocks(Bt, 64)), dim3(256), 0, s, Bt, H,
+                         tr.Gi.p + static_cast<size_t>(k) * 3 * bh, tr.hs16[l].p + k * bh, h32_in,
+                         n.whh_b[l].p, h32_out, tr.hs16[l].p + (k + 1) * bh, save);
+    }
   }
-  if (Y) gemm_nt(s, tr.Bt, n.O, n.H, h16_out[n.layers - 1], n.H, n.wout_b.p, n.H, Y, n.O);
-  check(hipGetLastError(), "fwd_step");
+  if (keep)
+    gemm_nt(s, static_cast<long>(ns) * Bt, n.O, H, tr.hs16[n.layers - 1].p + bh, H, n.wout_b.p, H, tr.Yseg.p,
+            n.O);
+  check(hipGetLastError(), "segment_forward");
 }
 
 // Loss and gradient (into tr.grad) by BPTT with checkpoints every `seg` steps.
@@ -118,25 +143,25 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
   hipLaunchKernelGGL(k_pack_bf16, dim3(blocks(static_cast<size_t>(T) * Bt * n.K0, 256)), dim3(256), 0, s,
                      T * Bt, n.I, X, n.K0, tr.Xb.p);
   hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.grad.p, tr.grad.n, 0.0f);
-  // forward sweep storing checkpoints (running state in hs32[.][0] / hs16[.][0])
-  std::vector<float *> h32(L), sv_null(L, nullptr);
-  std::vector<uint16_t *> h16(L);
+  // forward sweep storing checkpoints (running state in slot 0 of hs32 /
+  // hs16); the last segment keeps what its backward sweep needs
   for (int l = 0; l < L; ++l) {
-    h32[l] = tr.hs32[l].p;
-    h16[l] = tr.hs16[l].p;
-    hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, h32[l], bh, 0.0f);
-    hipLaunchKernelGGL(k_fill<uint16_t>, dim3(1024), dim3(256), 0, s, h16[l], bh, uint16_t(0));
+    hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.hs32[l].p, bh, 0.0f);
+    hipLaunchKernelGGL(k_fill<uint16_t>, dim3(1024), dim3(256), 0, s, tr.hs16[l].p, bh, uint16_t(0));
   }
-  std::vector<uint16_t *> h16b(L);   // BF16 state alternates between slots 0 and 1
-  for (int l = 0; l < L; ++l) h16b[l] = tr.hs16[l].p + bh;
-  for (int t = 0; t < T; ++t) {
-    if (t % seg == 0)
+  for (int sg = 0; sg < tr.nseg; ++sg) {
+    const int t0 = sg * seg, ns = std::min(seg, T - t0);
+    for (int l = 0; l < L; ++l)
+      check(hipMemcpyAsync(tr.hck[l].p + static_cast<size_t>(sg) * bh, tr.hs32[l].p, bh * sizeof(float),
+                           hipMemcpyDeviceToDevice, s),
+            "checkpoint");
+    const bool last = sg == tr.nseg - 1;
+    segment_forward(n, tr, s, t0, ns, last);
+    if (!last)
       for (int l = 0; l < L; ++l)
-        check(hipMemcpyAsync(tr.hck[l].p + static_cast<size_t>(t / seg) * bh, h32[l], bh * sizeof(float),
+        check(hipMemcpyAsync(tr.hs16[l].p, tr.hs16[l].p + static_cast<size_t>(ns) * bh, bh * sizeof(uint16_t),
                              hipMemcpyDeviceToDevice, s),
-              "checkpoint");
-    fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t) * Bt * n.K0, h32, h32, h16, h16b, sv_null, nullptr);
-    std::swap(h16, h16b);
+              "BF16 state");
   }
   for (int l = 0; l < L; ++l)
     hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, tr.dh[l].p, bh, 0.0f);
@@ -145,48 +170,39 @@ double loss_and_grad(Net &n, Trainer &tr, const float *X, const float *D) {
   const int lblocks = std::min(1024, blocks(static_cast<size_t>(Bt) * n.O, 256));
   for (int sg = tr.nseg - 1; sg >= 0; --sg) {
     const int t0 = sg * seg, ns = std::min(seg, T - t0);
-    // recompute the segment from its checkpoint, keeping every state
-    for (int l = 0; l < L; ++l) {
-      check(hipMemcpyAsync(tr.hs32[l].p, tr.hck[l].p + static_cast<size_t>(sg) * bh, bh * sizeof(float),
-                           hipMemcpyDeviceToDevice, s),
-            "restore");
-      hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks(bh, 256)), dim3(256), 0, s, bh, tr.hs32[l].p, tr.hs16[l].p);
-    }
-    for (int k = 0; k < ns; ++k) {
-      std::vector<float *> hk_in(L), hk(L), svk(L);
-      std::vector<uint16_t *> hin(L), hout(L);
+    if (sg != tr.nseg - 1) {
+      // recompute the segment from its checkpoint, keeping every state
       for (int l = 0; l < L; ++l) {
-        hk_in[l] = tr.hs32[l].p + k * bh;
-        hk[l] = tr.hs32[l].p + (k + 1) * bh;
-        hin[l] = tr.hs16[l].p + k * bh;
-        hout[l] = tr.hs16[l].p + (k + 1) * bh;
-        svk[l] = tr.sv[l].p + static_cast<size_t>(k) * 4 * bh;
+        check(hipMemcpyAsync(tr.hs32[l].p, tr.hck[l].p + static_cast<size_t>(sg) * bh, bh * sizeof(float),
+                             hipMemcpyDeviceToDevice, s),
+              "restore");
+        hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks(bh, 256)), dim3(256), 0, s, bh, tr.hs32[l].p,
+                           tr.hs16[l].p);
       }
-      fwd_step(n, tr, s, tr.Xb.p + static_cast<size_t>(t0 + k) * Bt * n.K0, hk_in, hk, hin, hout, svk,
-               tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O);
+      segment_forward(n, tr, s, t0, ns, true);
     }
-    // backward through the segment
-    for (int k = ns - 1; k >= 0; --k) {
-      const int t = t0 + k;
-      uint16_t *dY = tr.dYb.p + static_cast<size_t>(k) * Bt * n.O;
-      // per-block loss partials of step t stay on the device until the end
-      hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, s, Bt, n.O,
-                         tr.Yseg.p + static_cast<size_t>(k) * Bt * n.O, D + static_cast<size_t>(t) * Bt * n.O, dY,
-                         tr.lpart.p + static_cast<size_t>(t) * lblocks);
-      // dh_top += dY W_out
-      gemm_strided(s, Bt, H, n.O, dY, n.O, 1, n.wout_b.p, 1, H, tr.dh[L - 1].p, H, true, tr.part);
-      for (int l = L - 1; l >= 0; --l) {
+    // backward through the segment, layer by layer from the top.  Loss
+    // gradients of all ns steps (per-block loss partials of step t stay on
+    // the device until the end), then the head's gradient dY W_out for all
+    // steps as one product into E.
+    hipLaunchKernelGGL(k_loss_grad, dim3(lblocks, ns), dim3(256), 0, s, Bt, n.O, tr.Yseg.p,
+                       D + static_cast<size_t>(t0) * Bt * n.O, tr.dYb.p,
+                       tr.lpart.p + static_cast<size_t>(t0) * lblocks);
+    gemm_strided(s, ns * Bt, H, n.O, tr.dYb.p, n.O, 1, n.wout_b.p, 1, H, tr.E.p, H, false, tr.part);
+    for (int l = L - 1; l >= 0; --l) {
+      for (int k = ns - 1; k >= 0; --k) {
         uint16_t *dgi = tr.dgi[l].p + static_cast<size_t>(k) * 3 * bh;
         uint16_t *dgh = tr.dgh[l].p + static_cast<size_t>(k) * 3 * bh;
+        // dL/dh_t = (carried) + E_t; then dh_{t-1} = g z + dgh W_hh (an NT
+        // product with the transposed BF16 weights, K = 3H)
         hipLaunchKernelGGL(k_gru_gates_bwd, dim3(blocks(bh, 256)), dim3(256), 0, s, Bt, H, tr.dh[l].p,
-                           tr.sv[l].p + static_cast<size_t>(k) * 4 * bh, tr.hs32[l].p + k * bh, dgi, dgh,
-                           tr.dh[l].p);
-        // dh_{t-1} = g z + dgh W_hh; gradient into the layer below: dgi W_ih.
-        // With the transposed BF16 weights these are NT products (K = 3H, a
-        // multiple of the 32-wide K tile).
+                           tr.E.p + static_cast<size_t>(k) * bh, tr.sv[l].p + static_cast<size_t>(k) * 4 * bh,
+                           tr.hs32[l].p + k * bh, dgi, dgh, tr.dh[l].p);
         gemm_nt(s, Bt, H, 3 * H, dgh, 3 * H, n.whh_t[l].p, 3 * H, tr.dh[l].p, H, true);
-        if (l > 0) gemm_nt(s, Bt, H, 3 * H, dgi, 3 * H, n.wih_t[l].p, 3 * H, tr.dh[l - 1].p, H, true);
       }
+      // gradient into the layer below at every step of the segment: dgi W_ih
+      if (l > 0)
+        gemm_nt(s, static_cast<long>(ns) * Bt, H, 3 * H, tr.dgi[l].p, 3 * H, n.wih_t[l].p, 3 * H, tr.E.p, H);
     }
     // weight gradients of the segment: K = ns * Bt rows at once
     const int Ks = ns * Bt;
@@ -228,7 +244,7 @@ TrainState &tstate(Net &n) {
 }
 
 int check_batch(Net &n, int T, int Bt, int ckpt) {
-  if (T < 1 || Bt < 1 || ckpt < 1 || T > 4096 || Bt > (1 << 22)) {
+  if (T < 1 || Bt < 1 || ckpt < 1 || T > 4096 || Bt > (1 << 22) || static_cast<long>(T) * Bt > (1L << 26)) {
     n.ctx->last_error = "invalid batch shape";
     return DNNMG_EINVAL;
   }
