@@ -144,6 +144,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
                            "`python -m paper_2106_07687_amd.build` first")
+    # One HIP runtime per process: torch ships its own copy of the runtime.
+    # Loaded first, it satisfies the library's libamdhip64.so.7 dependency;
+    # loaded after the library, it would add a second runtime, which then
+    # may not see the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

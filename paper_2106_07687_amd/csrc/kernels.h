@@ -613,11 +613,12 @@ __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__
 // levels): lane q of a group of four sums the entries k = q mod 4; lane 0
 // combines (s0 + s1) + (s2 + s3), bitwise the value of k_spmv.  The
 // workgroup size is a multiple of 4.
+// Four lanes per node: gid = 4 i + q (gid and threadIdx.x agree modulo 64).
+// Every lane of the wavefront must take part (shuffles).
 template <typename T>
-__global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
-                                               const T *__restrict__ x, const T *__restrict__ b,
-                                               T *__restrict__ y) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void spmv4_item(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y,
+                                           int gid) {
   const int i = gid >> 2, q = gid & 3;
   T a0 = 0, a1 = 0, a2 = 0;
   if (i < L.N) spmv_row_part(L, JQ, JX, x, i, q, a0, a1, a2);
@@ -642,6 +643,13 @@ __global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict_
     y[3 * i + 1] = r1;
     y[3 * i + 2] = r2;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
+                                               const T *__restrict__ x, const T *__restrict__ b,
+                                               T *__restrict__ y) {
+  spmv4_item(L, JQ, JX, x, b, y, static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 // -------------------------------------------------------------- Vanka
@@ -804,11 +812,10 @@ __global__ void __launch_bounds__(256) k_vanka_smooth(LevelView L, const T *__re
 // i with the arithmetic of k_vanka_apply.  Bitwise k_spmv followed by
 // k_vanka_apply.  The workgroup size is a multiple of 16.
 template <typename T>
-__global__ void __launch_bounds__(256) k_vanka_smooth16(LevelView L, const T *__restrict__ JQ,
-                                                        const T *__restrict__ JX, const T *__restrict__ x,
-                                                        const T *__restrict__ b, const T *__restrict__ inv,
-                                                        T *__restrict__ delta) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void smooth16_item(const LevelView &L, const T *__restrict__ JQ,
+                                              const T *__restrict__ JX, const T *__restrict__ x,
+                                              const T *__restrict__ b, const T *__restrict__ inv,
+                                              T *__restrict__ delta, int gid) {
   const int c = gid >> 4, sub = gid & 15, a = sub >> 2, q = sub & 3;
   const bool live = c < L.C;
   T p0 = 0, p1 = 0, p2 = 0;
@@ -845,6 +852,14 @@ __global__ void __launch_bounds__(256) k_vanka_smooth16(LevelView L, const T *__
 #pragma unroll
   for (int j = 0; j < 12; ++j) acc += inv[static_cast<size_t>(12 * sub + j) * L.C + c] * rc[j];
   delta[static_cast<size_t>(sub) * L.C + c] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_smooth16(LevelView L, const T *__restrict__ JQ,
+                                                        const T *__restrict__ JX, const T *__restrict__ x,
+                                                        const T *__restrict__ b, const T *__restrict__ inv,
+                                                        T *__restrict__ delta) {
+  smooth16_item(L, JQ, JX, x, b, inv, delta, static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 // x_j += omega / m_j * sum over the cells containing j of their corrections.
@@ -1419,7 +1434,10 @@ __global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict_
 // Vanka sweeps, residual, restriction, coarse solve, prolongation) run in the
 // same order, separated by workgroup barriers instead of kernel boundaries,
 // each phase looping over its items with the item functions of the kernels
-// above, so every value is bitwise the one of the multi-launch path.
+// above (corrections with sixteen lanes per cell, residuals with four lanes
+// per node, coarse solve rows with 32 lanes), whose sums are ordered as in
+// every launch variant, so every value is bitwise the one of the multi-launch
+// path.
 constexpr int kSmallLevels = 3;
 template <typename T>
 struct SmallLevel {
@@ -1437,22 +1455,52 @@ struct SmallCycle {
   const int *bdof;
 };
 
+// delta_c = inv_c b|_c (the first sweep from a zero iterate, where the
+// residual is b) with sixteen lanes per cell: lane i < 12 forms row i with
+// the arithmetic of apply_item.
+template <typename T>
+__device__ __forceinline__ void apply16_item(const LevelView &L, const T *__restrict__ inv, const T *__restrict__ r,
+                                             T *__restrict__ delta, int gid) {
+  const int c = gid >> 4, sub = gid & 15;
+  if (c >= L.C || sub >= 12) return;
+  const int4 cn = L.cells[c];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  T rc[12];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
+  T acc = 0;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc += inv[static_cast<size_t>(12 * sub + j) * L.C + c] * rc[j];
+  delta[static_cast<size_t>(sub) * L.C + c] = acc;
+}
+
+// One additive Vanka sweep of a level in the workgroup: the corrections with
+// sixteen lanes per cell (residual and apply fused as in k_vanka_smooth16, or
+// the apply alone from a zero iterate), then the node update.  The lane loops
+// start at multiples of the workgroup size, so every lane of a wavefront runs
+// the same number of passes (the item functions shuffle).
 template <typename T>
 __device__ void small_sweep(const SmallLevel<T> &V, T omega, bool zero_start) {
-  const T *r = V.b;
-  if (!zero_start) {
-    for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
-    __syncthreads();
-    r = V.r;
+  const int n16 = 16 * V.L.C;
+  if (zero_start) {
+    for (int g = threadIdx.x; g < n16; g += blockDim.x) apply16_item(V.L, V.inv, V.b, V.delta, g);
+  } else {
+    for (int g0 = 0; g0 < n16; g0 += blockDim.x)
+      smooth16_item(V.L, V.JQ, V.JX, V.x, V.b, V.inv, V.delta, g0 + static_cast<int>(threadIdx.x));
   }
-  for (int c = threadIdx.x; c < V.L.C; c += blockDim.x) apply_item(V.L, V.inv, r, V.delta, c);
   __syncthreads();
   for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) update_item(V.L, V.delta, omega, V.x, i, zero_start);
   __syncthreads();
 }
 
+// Capacity (doubles) of the workgroup's copy of the coarse right-hand side.
+constexpr int kSmallDenseLds = 4096;
+
 template <typename T>
 __global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
+  __shared__ double bl[kSmallDenseLds];
   const int tid = threadIdx.x, nt = blockDim.x;
 #pragma unroll
   for (int l = kSmallLevels - 1; l >= 1; --l) {
@@ -1463,13 +1511,47 @@ __global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
       __syncthreads();
     }
     for (int k = 0; k < P.nu_pre; ++k) small_sweep(V, P.omega, k == 0);
-    for (int i = tid; i < V.L.N; i += nt) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
+    for (int g0 = 0; g0 < 4 * V.L.N; g0 += nt) spmv4_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, g0 + tid);
     __syncthreads();
     for (int j = tid; j < V.tv.Nc; j += nt) restrict_item(V.tv, V.r, P.lv[l - 1].b, j);
     __syncthreads();
   }
-  for (int row = tid >> 5; row < P.nblk * P.nb; row += nt >> 5)
-    dense_row_blk(P.nblk, P.nb, P.Ainv, P.bdof, P.lv[0].b, P.lv[0].x, row, tid & 31);
+  const int rows = P.nblk * P.nb;
+  if (rows <= kSmallDenseLds) {
+    // coarse solve x = A^-1 b with b gathered once into LDS (zero where a
+    // block row is unused) and four rows per 32-lane group in flight; each
+    // row is summed as in dense_row_blk (an unused column adds an exact
+    // zero to a sum that starts at +0, which leaves it unchanged)
+    for (int k = tid; k < rows; k += nt) {
+      const int g = P.bdof[k];
+      bl[k] = g >= 0 ? static_cast<double>(P.lv[0].b[g]) : 0.0;
+    }
+    __syncthreads();
+    const int grp = tid >> 5, lane = tid & 31, ngrp = nt >> 5;
+    for (int r0 = grp; r0 < rows; r0 += 4 * ngrp) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      int dst[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = r0 + u * ngrp;
+        dst[u] = row < rows ? P.bdof[row] : -1;
+        if (dst[u] >= 0) {
+          const double *ar = P.Ainv + static_cast<size_t>(row) * P.nb;
+          const double *bb = bl + (row / P.nb) * P.nb;
+          for (int k = lane; k < P.nb; k += 32) s[u] += ar[k] * bb[k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) s[u] += __shfl_xor(s[u], off, 32);
+        if (dst[u] >= 0 && lane == 0) P.lv[0].x[dst[u]] = static_cast<T>(s[u]);
+      }
+    }
+  } else {
+    for (int row = tid >> 5; row < rows; row += nt >> 5)
+      dense_row_blk(P.nblk, P.nb, P.Ainv, P.bdof, P.lv[0].b, P.lv[0].x, row, tid & 31);
+  }
   __syncthreads();
 #pragma unroll
   for (int l = 1; l < kSmallLevels; ++l) {
