@@ -1434,10 +1434,10 @@ __global__ void k_add_to_f64(int n, const T *__restrict__ w, double *__restrict_
 // Vanka sweeps, residual, restriction, coarse solve, prolongation) run in the
 // same order, separated by workgroup barriers instead of kernel boundaries,
 // each phase looping over its items with the item functions of the kernels
-// above (corrections with sixteen lanes per cell, residuals with four lanes
-// per node, coarse solve rows with 32 lanes), whose sums are ordered as in
-// every launch variant, so every value is bitwise the one of the multi-launch
-// path.
+// above (one thread per cell or node: in one workgroup, one pass with long
+// independent load chains beats several passes with short ones), whose sums
+// are ordered as in every launch variant, so every value is bitwise the one
+// of the multi-launch path.
 constexpr int kSmallLevels = 3;
 template <typename T>
 struct SmallLevel {
@@ -1455,41 +1455,15 @@ struct SmallCycle {
   const int *bdof;
 };
 
-// delta_c = inv_c b|_c (the first sweep from a zero iterate, where the
-// residual is b) with sixteen lanes per cell: lane i < 12 forms row i with
-// the arithmetic of apply_item.
-template <typename T>
-__device__ __forceinline__ void apply16_item(const LevelView &L, const T *__restrict__ inv, const T *__restrict__ r,
-                                             T *__restrict__ delta, int gid) {
-  const int c = gid >> 4, sub = gid & 15;
-  if (c >= L.C || sub >= 12) return;
-  const int4 cn = L.cells[c];
-  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
-  T rc[12];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int f = 0; f < 3; ++f) rc[3 * a + f] = r[3 * nn[a] + f];
-  T acc = 0;
-#pragma unroll
-  for (int j = 0; j < 12; ++j) acc += inv[static_cast<size_t>(12 * sub + j) * L.C + c] * rc[j];
-  delta[static_cast<size_t>(sub) * L.C + c] = acc;
-}
-
-// One additive Vanka sweep of a level in the workgroup: the corrections with
-// sixteen lanes per cell (residual and apply fused as in k_vanka_smooth16, or
-// the apply alone from a zero iterate), then the node update.  The lane loops
-// start at multiples of the workgroup size, so every lane of a wavefront runs
-// the same number of passes (the item functions shuffle).
 template <typename T>
 __device__ void small_sweep(const SmallLevel<T> &V, T omega, bool zero_start) {
-  const int n16 = 16 * V.L.C;
-  if (zero_start) {
-    for (int g = threadIdx.x; g < n16; g += blockDim.x) apply16_item(V.L, V.inv, V.b, V.delta, g);
-  } else {
-    for (int g0 = 0; g0 < n16; g0 += blockDim.x)
-      smooth16_item(V.L, V.JQ, V.JX, V.x, V.b, V.inv, V.delta, g0 + static_cast<int>(threadIdx.x));
+  const T *r = V.b;
+  if (!zero_start) {
+    for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
+    __syncthreads();
+    r = V.r;
   }
+  for (int c = threadIdx.x; c < V.L.C; c += blockDim.x) apply_item(V.L, V.inv, r, V.delta, c);
   __syncthreads();
   for (int i = threadIdx.x; i < V.L.N; i += blockDim.x) update_item(V.L, V.delta, omega, V.x, i, zero_start);
   __syncthreads();
@@ -1511,7 +1485,7 @@ __global__ void __launch_bounds__(1024) k_vcycle_small(SmallCycle<T> P) {
       __syncthreads();
     }
     for (int k = 0; k < P.nu_pre; ++k) small_sweep(V, P.omega, k == 0);
-    for (int g0 = 0; g0 < 4 * V.L.N; g0 += nt) spmv4_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, g0 + tid);
+    for (int i = tid; i < V.L.N; i += nt) spmv_item(V.L, V.JQ, V.JX, V.x, V.b, V.r, i);
     __syncthreads();
     for (int j = tid; j < V.tv.Nc; j += nt) restrict_item(V.tv, V.r, P.lv[l - 1].b, j);
     __syncthreads();

@@ -392,16 +392,23 @@ void Solver<T>::autotune() {
     throw DnnmgError{DNNMG_EDEVICE, "hipEventCreate failed"};
   }
   const int cand[3] = {64, 128, 256};
-  float last_t = 0.0f;   // time of the last pick's winner (4 launches, ms)
+  // In a V-cycle a level's operator, inverses and vectors have left the L2
+  // caches (32 MB in all) by the time they are used again, and on the small
+  // levels the dependent load chains then decide which variant is faster.
+  // Each timed launch therefore follows a 64 MB fill that evicts the L2s.
+  DevBuf<float> evict;
+  evict.alloc(size_t(16) << 20);
+  float last_t = 0.0f;   // time of the last pick's winner (one launch after eviction, ms)
   auto pick = [&](auto launch) {
     float best_t = 1e30f;
     int best = 256;
-    for (int rep = 0; rep < 2; ++rep)
+    for (int rep = 0; rep < 3; ++rep)
       for (int ci = 0; ci < 3; ++ci) {
-        const int bs = cand[rep ? 2 - ci : ci];
-        launch(bs);
+        const int bs = cand[rep == 1 ? 2 - ci : ci];
+        if (rep == 0) launch(bs);
+        hipLaunchKernelGGL(k_fill<float>, dim3(2048), dim3(256), 0, s, evict.p, evict.n, 0.0f);
         check(hipEventRecord(e0, s), "hipEventRecord");
-        for (int k = 0; k < 4; ++k) launch(bs);
+        launch(bs);
         check(hipEventRecord(e1, s), "hipEventRecord");
         check(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.0f;
