@@ -499,6 +499,10 @@ def main():
                     help="pre,post,coarse sweeps of the V-cycles of the DNN-MG leg's level-5 solves "
                          "(measured on level 5: V(2,1) with V(1,1) below is the fastest schedule; the "
                          "GMG leg keeps V(2,2) throughout)")
+    ap.add_argument("--direct-level", type=int, default=1, choices=(0, 1, 2),
+                    help="level of the direct (FP64 dense inverse) solve at the bottom of every V-cycle, "
+                         "both legs (level 1: 1,140 unknowns, one 10 MB mat-vec instead of level-1 "
+                         "sweeps and the level-0 solve)")
     ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
                     help="0: additive cell-Vanka, 1: coloured multiplicative cell-Vanka")
     ap.add_argument("--no-graphs", action="store_true",
@@ -532,7 +536,8 @@ def main():
     macro = channel_obstacle(args.seed)
     ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
                     use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
-                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother, nu_coarse=args.nu_coarse)
+                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother, nu_coarse=args.nu_coarse,
+                    coarse_level=args.direct_level)
     F = args.level
     if args.profile == "all":
         gmg_keys = dnn_keys = None
@@ -720,7 +725,7 @@ def main():
                    "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
                    "newton_predictor": args.newton_predictor,
-                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother,
+                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother, "direct_solve_level": args.direct_level,
                    "v_cycle": {"gmg": f"V(2,2), {args.nu_coarse or 'same'} below the top",
                                "dnnmg": "V({},{}), V({c},{c}) below the top".format(
                                    *args.dnnmg_sweeps.split(",")[:2], c=args.dnnmg_sweeps.split(",")[2])}},

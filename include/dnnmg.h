@@ -122,6 +122,12 @@ typedef struct {
                              share a node; per colour the residual is
                              recomputed and each cell of the colour adds omega
                              times its correction); same vanka_omega          */
+  int coarse_level;       /* level of the direct solve at the bottom of every
+                             V-cycle (FP64 dense inverse of its Jacobian, built
+                             with each hierarchy); 0: the level-0 mesh, k > 0:
+                             levels below k are not used by the solver, and
+                             a solve on a level below k is DNNMG_EINVAL.  Fixed
+                             at creation, at most 2, and 0 for batches        */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
 } dnnmg_params;
 
@@ -168,8 +174,8 @@ int dnnmg_create(const dnnmg_params *p, dnnmg_ctx **out);
 int dnnmg_destroy(dnnmg_ctx *ctx);
 /* Message of the last failed call on this context ("" if none). */
 const char *dnnmg_last_error(const dnnmg_ctx *ctx);
-/* Replaces nu, alpha0, theta, tolerances, omega and the stream; precision is
- * fixed at creation.  Returns DNNMG_EINVAL for out-of-range values. */
+/* Replaces nu, alpha0, theta, tolerances, omega and the stream; precision and
+ * coarse_level are fixed at creation (a different value is DNNMG_EINVAL).  Returns DNNMG_EINVAL for out-of-range values. */
 int dnnmg_set_params(dnnmg_ctx *ctx, const dnnmg_params *p);
 
 /* Mesh hierarchy setup (once): refines the macro mesh to levels

@@ -120,8 +120,10 @@ class MGHierarchy:
     injected to each level: coarse vertices keep their ids, so injection is
     the prefix of the fine vector)."""
 
-    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0):
+    def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0,
+                 coarse=0):
         self.levels = levels
+        self.coarse = coarse                # level of the direct solve (Sec. 2: coarse-grid solver)
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         self.nu_coarse = nu_coarse          # > 0: sweeps before and after on the levels below the top
@@ -136,7 +138,7 @@ class MGHierarchy:
             self.blocks.append(cell_blocks(Jl, L.cells))
         self.P = [None] + [levels[l].prolongation() for l in range(1, len(levels))]
         self.dmask = [L.dirichlet_nodes() for L in levels]
-        self.lu0 = sla.lu_factor(self.J[0].toarray())
+        self.lu0 = sla.lu_factor(self.J[coarse].toarray())
 
     def _prolong(self, l, e):
         return (self.P[l] @ e.reshape(-1, 3)).reshape(-1)
@@ -156,7 +158,9 @@ class MGHierarchy:
         """One V(nu1, nu2) cycle on level l for J_l x = b (V(nu_coarse,
         nu_coarse) on the levels below the one it is called on, if set)."""
         top = l if top is None else top
-        if l == 0:
+        if l < self.coarse:
+            raise ValueError("V-cycle below the coarse level")
+        if l == self.coarse:
             return sla.lu_solve(self.lu0, b)
         nu1, nu2 = (self.nu_coarse, self.nu_coarse) if self.nu_coarse > 0 and l != top else (self.nu1, self.nu2)
         x = np.zeros_like(b) if x is None else x.copy()
@@ -230,7 +234,8 @@ def gmres(A, b, precond, rtol=1e-2, restart=30, maxit=100):
 
 
 def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1e-2,
-                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0):
+                   restart=30, gmres_max=100, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0,
+                   coarse=0):
     """Newton's method (eq. newton) with GMRES + V-cycle linear solves, as in
     the coarse solve of Algorithm 1 (full steps, reading N1)."""
     fine = levels[-1]
@@ -245,7 +250,7 @@ def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1
             return x, stats
         if it == maxit:
             break
-        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother, nu_coarse)
+        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother, nu_coarse, coarse)
         w, k, _ = gmres(mg.J[-1], R, lambda v: mg.vcycle(len(levels) - 1, v),
                         gmres_rtol, restart, gmres_max)
         stats["gmres"].append(k)

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
                 ("newton_predictor", C.c_int), ("jacobian_reuse", C.c_int),
                 ("reuse_contraction", C.c_double), ("switch_off_newton", C.c_int),
-                ("nu_coarse", C.c_int), ("smoother", C.c_int),
+                ("nu_coarse", C.c_int), ("smoother", C.c_int), ("coarse_level", C.c_int),
                 ("stream", C.c_void_p)]
 
 
@@ -251,8 +251,11 @@ class Context:
             pass
 
     def set_params(self, **kw):
-        _set_fields(self.params, kw)
-        self._check(self.lib.dnnmg_set_params(self.h, C.byref(self.params)))
+        p = Params()
+        C.pointer(p)[0] = self.params          # copy: kept only if the library accepts it
+        _set_fields(p, kw)
+        self._check(self.lib.dnnmg_set_params(self.h, C.byref(p)))
+        self.params = p
 
     def setup_mesh(self, macro, finest_level):
         m, keep = _coarse_mesh(macro)

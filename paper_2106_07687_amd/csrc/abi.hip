@@ -41,7 +41,8 @@ bool params_ok(const dnnmg_params *p) {
          (p->precision == 0 || p->precision == 1) && (p->use_graphs == 0 || p->use_graphs == 1) &&
          (p->autotune >= 0 && p->autotune <= 3) && (p->newton_predictor == 0 || p->newton_predictor == 1) &&
          (p->jacobian_reuse == 0 || p->jacobian_reuse == 1) && (p->smoother == 0 || p->smoother == 1) &&
-         p->switch_off_newton >= 0 && p->nu_coarse >= 0 && p->nu_coarse <= 8 &&
+         p->switch_off_newton >= 0 && p->nu_coarse >= 0 && p->nu_coarse <= 8 && p->coarse_level >= 0 &&
+         p->coarse_level <= 2 &&
          p->reuse_contraction > 0 &&
          p->reuse_contraction < 1;
 }
@@ -258,6 +259,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->smoother = 0;
   p->switch_off_newton = 0;
   p->nu_coarse = 0;
+  p->coarse_level = 0;
   p->stream = nullptr;
   return DNNMG_OK;
 }
@@ -287,6 +289,8 @@ const char *dnnmg_last_error(const dnnmg_ctx *ctx) {
 int dnnmg_set_params(dnnmg_ctx *ctx, const dnnmg_params *p) {
   if (!ctx) return DNNMG_EINVAL;
   if (!params_ok(p)) return fail(ctx, DNNMG_EINVAL, "invalid parameters");
+  if (p->coarse_level != ctx->impl.prm.coarse_level)
+    return fail(ctx, DNNMG_EINVAL, "coarse_level is fixed at creation");
   const int prec = ctx->impl.prm.precision;
   ctx->impl.prm = *p;
   ctx->impl.prm.precision = prec;

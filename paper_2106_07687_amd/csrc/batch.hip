@@ -138,7 +138,7 @@ int build_group(dnnmg_batch *b, Group &g, const dnnmg_params *p, const dnnmg_sim
 extern "C" {
 
 int dnnmg_batch_create(const dnnmg_params *p, const dnnmg_sim_desc *sims, int n_sims, dnnmg_batch **out) {
-  if (!p || !sims || n_sims < 1 || !out) return DNNMG_EINVAL;
+  if (!p || !sims || n_sims < 1 || !out || p->coarse_level != 0) return DNNMG_EINVAL;
   for (int s = 0; s < n_sims; ++s)
     if (!mesh_ok(sims[s].mesh) || !(sims[s].nu > 0) || sims[s].depth < 0 || sims[s].depth > 9)
       return DNNMG_EINVAL;

@@ -185,7 +185,7 @@ class Solver {
   }
   // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup
   // launch; 0 = off.  Needs the blocked level-0 inverse.
-  void set_small_top(int top) { small_top_ = gj_b_ > 0 ? std::min(top, kSmallLevels - 1) : 0; }
+  void set_small_top(int top) { small_top_ = gj_b_ > 0 && c_ == 0 ? std::min(top, kSmallLevels - 1) : 0; }
   int small_top() const { return small_top_; }
 
  private:
@@ -220,6 +220,7 @@ class Solver {
   void coarse_inverse();
   std::vector<OpLevel<T>> ops_;
   DevBuf<double> W_, prow_, colk_;
+  int c_ = 0;    // level of the coarse direct solve
   int n0_ = 0;
   // blocked Gauss-Jordan: panel width (0: one pivot + one elimination launch
   // per column), second workspace, panel transforms, pivot rows, used-row

@@ -334,13 +334,17 @@ void Solver<T>::setup(int finest) {
     o.x.alloc(3 * static_cast<size_t>(h.N));
     o.t.alloc(3 * static_cast<size_t>(h.N));
   }
-  n0_ = 3 * ctx_->levels[0]->h.N;
-  // Level-0 blocks: one per simulation of a batch (its nodes are those of its
+  // the direct solve at the bottom of the V-cycle: level c_ (0 unless set)
+  c_ = ctx_->prm.coarse_level;
+  if (c_ > finest) throw DnnmgError{DNNMG_EINVAL, "coarse_level above the finest level"};
+  if (c_ > 0 && !ctx_->blk0.empty()) throw DnnmgError{DNNMG_EINVAL, "a batch solves on level 0"};
+  n0_ = 3 * ctx_->levels[c_]->h.N;
+  // Coarse blocks: one per simulation of a batch (its nodes are those of its
   // own mesh), a single block otherwise.  A block is solved by blocked
   // Gauss-Jordan (panels of kGjB columns, one thread per row) when it has at
   // most 1024 unknowns; a single larger block falls back to one pivot and one
   // elimination launch per column.
-  const int N0 = ctx_->levels[0]->h.N;
+  const int N0 = ctx_->levels[c_]->h.N;
   std::vector<int> blk(N0, 0);
   if (!ctx_->blk0.empty()) {
     if (static_cast<int>(ctx_->blk0.size()) != N0)
@@ -504,7 +508,7 @@ void Solver<T>::autotune() {
     // the launches it replaces (those replayed from a graph, as in use)
     small_top_ = 0;
     const int tmax = std::min(kSmallLevels - 1, static_cast<int>(ops_.size()) - 1);
-    for (int top = 1; top <= tmax && gj_b_ > 0; ++top) {
+    for (int top = 1; top <= tmax && gj_b_ > 0 && c_ == 0; ++top) {
       OpLevel<T> &o = ops_[top];
       const int keep = small_top_;
       pick([&](int) { vcycle(top, o.b.p, o.x.p); });
@@ -530,8 +534,9 @@ template <typename T>
 void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) {
   hipStream_t s = ctx_->stream;
   kept_key_ = 0;
+  if (level < c_) throw DnnmgError{DNNMG_EINVAL, "solve level below coarse_level"};
   if (lin_level_ < level) full = true;   // never factorised at this depth
-  for (int l = full ? 0 : level; l <= level; ++l) {
+  for (int l = full ? c_ : level; l <= level; ++l) {
     ctx_->ensure_lps(l, dt);
     DevLevel &L = *ctx_->levels[l];
     OpLevel<T> &o = ops_[l];
@@ -543,7 +548,7 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
                          ctx_->phys(dt, 0.0), x_dev, L.sP.p, o.JQ.p, o.JX.p);
     }
     LAUNCH_CHECK("k_assemble");
-    if (full && l > 0) {
+    if (full && l > c_) {
       ProfScope ps(ctx_->prof, s, "vanka_factor", l);
       hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 16, 256)),
                          dim3(256), 0, s, L.view(), o.JQ.p, o.inv.p);
@@ -551,25 +556,26 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
     }
   }
   if (!full) return;
-  if (use_graph(0))
+  if (use_graph(c_))
     graph_run(ginv_, [&]() { coarse_inverse(); });
   else
     coarse_inverse();
   lin_level_ = level;
 }
 
-// Level-0 dense inverse (FP64): Gauss-Jordan with partial pivoting on
-// [J_0 | I], one pivot kernel and one elimination kernel per column.
+// Dense inverse (FP64) of the coarse level's Jacobian: blocked Gauss-Jordan
+// with partial pivoting on [J_c | I] per block, or one pivot kernel and one
+// elimination kernel per column for a single large block.
 template <typename T>
 void Solver<T>::coarse_inverse() {
   hipStream_t s = ctx_->stream;
-  DevLevel &L0 = *ctx_->levels[0];
-  ProfScope ps(ctx_->prof, s, "coarse_inverse", 0);
+  DevLevel &L0 = *ctx_->levels[c_];
+  ProfScope ps(ctx_->prof, s, "coarse_inverse", c_);
   hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, W_.p, W_.n, 0.0);
   if (gj_b_ > 0) {
     const int nb = nb_;
     hipLaunchKernelGGL(k_dense_from_sell_blk<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
-                       ops_[0].JQ.p, ops_[0].JX.p, g2l_.p, blk_.p, nb, W_.p);
+                       ops_[c_].JQ.p, ops_[c_].JX.p, g2l_.p, blk_.p, nb, W_.p);
     hipLaunchKernelGGL(k_gjb_init, dim3(blocks(nb, 256), nblk_), dim3(256), 0, s, nblk_, nb, bdof_.p, W_.p);
     double *wo = W_.p, *wn = W2_.p;
     for (int k0 = 0; k0 < nb; k0 += gj_b_) {
@@ -586,7 +592,7 @@ void Solver<T>::coarse_inverse() {
     return;
   }
   hipLaunchKernelGGL(k_dense_from_sell<T>, dim3(blocks(L0.h.N, 64)), dim3(64), 0, s, L0.view(),
-                     ops_[0].JQ.p, ops_[0].JX.p, W_.p, 2 * n0_);
+                     ops_[c_].JQ.p, ops_[c_].JX.p, W_.p, 2 * n0_);
   hipLaunchKernelGGL(k_identity_right, dim3(blocks(n0_, 256)), dim3(256), 0, s, n0_, W_.p);
   const dim3 eg(blocks(2 * n0_, 256), n0_);
   for (int k = 0; k < n0_; ++k) {
@@ -730,11 +736,13 @@ void Solver<T>::vcycle(int l, const T *b, T *x) {
   if (cycle_depth_ == 0) cycle_top_ = l;
   Depth guard(cycle_depth_);
   // the one-workgroup cycle is additive and uses one sweep count for all its levels
-  if (l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0 && (ctx_->prm.nu_coarse == 0 || l != cycle_top_)) {
+  if (l < c_) throw DnnmgError{DNNMG_EINVAL, "V-cycle below coarse_level"};
+  if (c_ == 0 && l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0 &&
+      (ctx_->prm.nu_coarse == 0 || l != cycle_top_)) {
     launch_small(l, b, x);
     return;
   }
-  if (l > 0 && use_graph(l)) {
+  if (l > c_ && use_graph(l)) {
     const auto key = std::make_tuple(l, l == cycle_top_ ? 1 : 0, static_cast<const void *>(b),
                                      static_cast<const void *>(x));
     // bound the cache: keys of freed work vectors are never looked up again
@@ -748,8 +756,8 @@ void Solver<T>::vcycle(int l, const T *b, T *x) {
 template <typename T>
 void Solver<T>::vcycle_body(int l, const T *b, T *x) {
   hipStream_t s = ctx_->stream;
-  if (l == 0) {
-    ProfScope ps(ctx_->prof, s, "coarse_solve", 0);
+  if (l == c_) {
+    ProfScope ps(ctx_->prof, s, "coarse_solve", c_);
     if (gj_b_ > 0)
       hipLaunchKernelGGL(k_dense_solve_blk<T>, dim3(blocks(static_cast<size_t>(nblk_) * nb_, 8)), dim3(256), 0,
                          s, nblk_, nb_, Ainv_.p, bdof_.p, b, x);

@@ -25,15 +25,23 @@ def test_defaults_and_invalid_params():
     assert (p.theta, p.alpha0, p.nu_pre, p.nu_post, p.gmres_restart) == (0.5, 0.5, 2, 2, 30)
     h = C.c_void_p()
     assert (p.jacobian_reuse, p.reuse_contraction, p.smoother, p.switch_off_newton) == (0, 0.1, 0, 0)
+    assert p.coarse_level == 0
     for field, bad in (("nu", -1.0), ("theta", 0.0), ("gmres_restart", 65), ("precision", 2),
                        ("vanka_omega", 0.0), ("gmres_rtol", 1.5), ("jacobian_reuse", 2),
                        ("reuse_contraction", 0.0), ("reuse_contraction", 1.0), ("smoother", 2),
-                       ("switch_off_newton", -1), ("autotune", 4), ("newton_predictor", 3)):
+                       ("switch_off_newton", -1), ("autotune", 4), ("newton_predictor", 3),
+                       ("coarse_level", -1), ("coarse_level", 3)):
         q = _lib.Params()
         lib.dnnmg_params_default(C.byref(q))
         setattr(q, field, bad)
         assert lib.dnnmg_create(C.byref(q), C.byref(h)) == _lib.EINVAL, field
     assert lib.dnnmg_create(None, C.byref(h)) == _lib.EINVAL
+    ctx = P.Context(precision=1, coarse_level=1)   # fixed at creation
+    with pytest.raises(P.DnnmgError) as e:
+        ctx.set_params(coarse_level=2)
+    assert e.value.code == _lib.EINVAL
+    ctx.set_params(coarse_level=1, nu_pre=1)
+    ctx.close()
 
 
 def test_calls_out_of_order_and_bad_mesh_are_rejected_without_device_work():

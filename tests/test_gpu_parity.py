@@ -297,3 +297,50 @@ def test_coarse_sweep_count_parity(c1):
     finally:
         ctx.set_params(nu_coarse=0, newton_tol=1e-10)
         st.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("coarse", [1, 2])
+def test_coarse_level_direct_solve_parity(coarse):
+    """coarse_level = c: the FP64 dense inverse sits on level c (level 1: one
+    block of more than 1024 unknowns, the per-column Gauss-Jordan; level 2
+    the same); V-cycles called on levels 3 .. c match the oracle's hierarchy
+    with its direct solve on level c (1e-10, FP64; on level c the exact
+    solve), a cycle below c is refused, and FP64 time steps reach the
+    oracle's x_n (1e-10)."""
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    lev = mesh.hierarchy(macro, 3)
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    ctx = _ctx(0, nu=macro.nu, coarse_level=coarse)
+    ctx.setup_mesh(macro, 3)
+    print(f"[coarse_level {coarse}] level {coarse} unknowns {3 * lev[coarse].n_nodes}", flush=True)
+    x = random_state(lev[3].n_nodes, 60 + coarse) * 0.3
+    st = ctx.state(3)
+    st.set(x, 0.0)
+    ctx.linearize(st, 3, DT)
+    mg = solver.MGHierarchy(lev, prob, x, coarse=coarse)
+    b = random_state(lev[3].n_nodes, 70 + coarse)
+    for l in range(3, coarse - 1, -1):
+        bl = b[:3 * lev[l].n_nodes].copy()
+        bl.reshape(-1, 3)[lev[l].dirichlet_nodes(), :2] = 0.0
+        for rep in range(2):                       # captured, then replayed
+            v_gpu = ctx.vcycle(l, bl)
+            v_ref = mg.vcycle(l, bl)
+            assert rel(v_gpu, v_ref) < 1e-10, (l, rep, rel(v_gpu, v_ref))
+    with pytest.raises(P.DnnmgError):
+        ctx.vcycle(coarse - 1, b[:3 * lev[coarse - 1].n_nodes].copy())
+    with pytest.raises(P.DnnmgError):
+        ctx.set_params(coarse_level=0)
+    ctx.set_params(newton_tol=1e-14)
+    s2 = ctx.state(3)
+    x_ref = np.zeros(3 * lev[3].n_nodes)
+    for n in range(1, 3):
+        info = ctx.step(s2, DT)
+        x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=1e-15)
+        e = rel(s2.get()[0], x_ref)
+        print(f"[coarse_level {coarse}] step {n}: {e:.2e}, gmres {info['gmres_iters']}", flush=True)
+        assert e < 1e-10
+    s2.close()
+    st.close()
+    ctx.close()

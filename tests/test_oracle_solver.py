@@ -173,3 +173,29 @@ def test_coarse_sweep_count_changes_only_the_lower_levels():
     xd = solver.newton_step(lev[-1], prob, x0, 0.2, tol=1e-13)
     xm, _ = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, nu_coarse=1)
     np.testing.assert_allclose(xm, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
+
+
+def test_direct_solve_on_a_finer_coarse_level():
+    """With the direct solve on level c, a cycle called on level c is the
+    exact solve of J_c x = b, a cycle on a finer level changes against the
+    level-0 hierarchy, a cycle below c is refused, and MG-Newton still
+    reaches the direct Newton solution."""
+    m = channel_obstacle(1)
+    lev = mesh.hierarchy(m, 2)
+    prob = fem.Problem(nu=m.nu, dt=0.01)
+    x = np.random.default_rng(13).uniform(-0.3, 0.3, 3 * lev[2].n_nodes)
+    a = solver.MGHierarchy(lev, prob, x)
+    c = solver.MGHierarchy(lev, prob, x, coarse=1)
+    b1 = np.random.default_rng(14).standard_normal(3 * lev[1].n_nodes)
+    x1 = c.vcycle(1, b1)
+    assert np.linalg.norm(c.J[1] @ x1 - b1) <= 1e-11 * np.linalg.norm(b1)
+    # the level-0 hierarchy's cycle on level 1 is only an approximate solve
+    assert np.linalg.norm(a.J[1] @ a.vcycle(1, b1) - b1) > 1e-6 * np.linalg.norm(b1)
+    b2 = np.random.default_rng(15).standard_normal(3 * lev[2].n_nodes)
+    assert np.abs(a.vcycle(2, b2) - c.vcycle(2, b2)).max() > 1e-8
+    with pytest.raises(ValueError):
+        c.vcycle(0, b1[:3 * lev[0].n_nodes])
+    x0 = np.zeros(3 * lev[-1].n_nodes)
+    xd = solver.newton_step(lev[-1], prob, x0, 0.2, tol=1e-13)
+    xm, _ = solver.newton_step_mg(lev, prob, x0, 0.2, tol=1e-13, coarse=1)
+    np.testing.assert_allclose(xm, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
