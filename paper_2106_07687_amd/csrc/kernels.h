@@ -1284,20 +1284,30 @@ __global__ void k_gjb_extract(int n, const double *__restrict__ W, const int *__
   Ainv[static_cast<size_t>(k) * n + j] = W[piv[k] * 2 * static_cast<size_t>(n) + n + j];
 }
 
-// x = A^{-1} b, the inverse row-major with leading dimension ld: 32 lanes
-// per row split the dot product.
+// x = A^{-1} b, the inverse row-major with leading dimension ld: one
+// wavefront per row (four rows per workgroup); lane l sums the columns
+// k = l (mod 64) in four independent partial sums (more loads in flight),
+// combined as (s0 + s1) + (s2 + s3), then a butterfly over the wavefront.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dense_solve_w(int n, const double *__restrict__ Ainv, size_t ld,
                                                        const T *__restrict__ b, T *__restrict__ x) {
-  const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int lane = threadIdx.x & 31;
-  double s = 0.0;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (row < n) {
     const double *r = Ainv + static_cast<size_t>(row) * ld;
-    for (int k = lane; k < n; k += 32) s += r[k] * static_cast<double>(b[k]);
+    int k = lane;
+    for (; k + 192 < n; k += 256) {
+      s0 += r[k] * static_cast<double>(b[k]);
+      s1 += r[k + 64] * static_cast<double>(b[k + 64]);
+      s2 += r[k + 128] * static_cast<double>(b[k + 128]);
+      s3 += r[k + 192] * static_cast<double>(b[k + 192]);
+    }
+    for (; k < n; k += 64) s0 += r[k] * static_cast<double>(b[k]);
   }
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
-  for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (row < n && lane == 0) x[row] = static_cast<T>(s);
 }
 

@@ -762,7 +762,7 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
       hipLaunchKernelGGL(k_dense_solve_blk<T>, dim3(blocks(static_cast<size_t>(nblk_) * nb_, 8)), dim3(256), 0,
                          s, nblk_, nb_, Ainv_.p, bdof_.p, b, x);
     else
-      hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 8)), dim3(256), 0, s, n0_, W_.p + n0_,
+      hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 4)), dim3(256), 0, s, n0_, W_.p + n0_,
                          2 * static_cast<size_t>(n0_), b, x);
     LAUNCH_CHECK("k_dense_solve");
     return;
