@@ -79,14 +79,17 @@ typedef struct {
                              threads per row), Vanka and transfer kernels of
                              every level at workgroup sizes 64, 128 and 256,
                              the fused residual + Vanka apply against the
-                             separate kernels, and the bottom of the V-cycle
+                             separate kernels, a coarse level's last update
+                             fused into the prolongation against the two
+                             launches, and the bottom of the V-cycle
                              (levels <= 2 and the coarse solve) in a single
                              workgroup against its launches, and keep the
                              fastest (scheduling only: results are bitwise the
                              same); 0: 256 throughout, separate kernels, one
                              thread per row; 2: as 0 with the fused apply
-                             (sixteen lanes per cell) and four threads per
-                             SpMV row on every level;
+                             (sixteen lanes per cell), four threads per
+                             SpMV row and the fused update + prolongation on
+                             every level;
                              3: as 0 with the single-workgroup bottom cycle  */
   int newton_predictor;   /* 0: Newton starts from x_{n-1}; 1: from the linear
                              extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
@@ -401,14 +404,15 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..9] = SpMV, Vanka apply,
+/* Workgroup sizes in use on `level`: block_sizes[0..10] = SpMV, Vanka apply,
  * Vanka update, restriction from `level`, prolongation to `level`, the fused
  * residual + Vanka apply (0: SpMV and apply run separately), the
  * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0),
  * the fused residual + restriction (0: separate), the SpMV with four
  * threads per row (0: one thread per row), and the lanes per cell of the
- * fused residual + Vanka apply (4 or 16; 0 when not fused) (10 ints,
- * caller-owned).
+ * fused residual + Vanka apply (4 or 16; 0 when not fused), and the fused
+ * last update of the next coarser level + prolongation to `level` (0:
+ * separate) (11 ints, caller-owned).
  * DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:

@@ -316,11 +316,13 @@ class Context:
         inside the single-workgroup bottom cycle; restrict_residual 0: the
         residual is stored, then restricted; spmv4 0: one thread per SpMV
         row; smooth_lanes: lanes per cell of the fused kernel, 0 if not
-        fused)."""
-        out = np.zeros(10, dtype=np.int32)
+        fused; update_prolong: the next coarser level's last update fused into
+        the prolongation, 0 if separate)."""
+        out = np.zeros(11, dtype=np.int32)
         self._check(self.lib.dnnmg_launch_config(self.h, level, out.ctypes.data_as(_IP)))
         return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong", "vanka_smooth",
-                         "vcycle_small", "restrict_residual", "spmv4", "smooth_lanes"), out.tolist()))
+                         "vcycle_small", "restrict_residual", "spmv4", "smooth_lanes", "update_prolong"),
+                        out.tolist()))
 
     def level_stats(self, level):
         v = [C.c_longlong() for _ in range(4)]

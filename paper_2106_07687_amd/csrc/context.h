@@ -133,6 +133,8 @@ struct OpLevel {
   int bs_smooth = 0;   // > 0: residual + Vanka apply fused at this size
   int smooth_lanes = 4;   // lanes per cell of the fused kernel: 4 (k_vanka_smooth) or 16 (k_vanka_smooth16)
   int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
+  int bs_upro = 0;     // > 0: the next coarser level's last update fused into
+                       // the prolongation to this level (k_update_prolong_add)
 };
 
 class Ctx;
@@ -158,8 +160,12 @@ class Solver {
     return key != 0 && kept_key_ == key && kept_level_ == level && kept_dt_ == dt;
   }
   void forget_jacobian() { kept_key_ = 0; }
-  void vanka_sweep(int l, T *x, const T *b, bool zero_start);
-  void vcycle(int l, const T *b, T *x);                         // x = V(b), zero start
+  // defer_update: leave the node update of the sweep to the caller (the
+  // corrections are in op(l).delta)
+  void vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer_update = false);
+  // x = V(b), zero start.  With defer, the last post-sweep's node update may
+  // be left to the caller (returns true if it was).
+  bool vcycle(int l, const T *b, T *x, bool defer = false);
   int gmres(int level, const T *b, T *x, double rtol, int restart, int maxit, double *res0,
             double *res);
   void spmv(int l, const T *x, const T *b, T *y);               // y = b - J x or J x
@@ -176,11 +182,13 @@ class Solver {
   // per SpMV row on every level, workgroup size 256 (a fixed configuration,
   // e.g. for reproducible comparisons).
   void fuse_all() {
-    for (auto &o : ops_) {
+    for (size_t l = 0; l < ops_.size(); ++l) {
+      OpLevel<T> &o = ops_[l];
       o.bs_smooth = 256;
       o.smooth_lanes = 16;
       o.bs_rres = 256;
       o.bs_spmv4 = 256;
+      o.bs_upro = static_cast<int>(l) - 1 > c_ ? 256 : 0;
     }
   }
   // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup
@@ -216,7 +224,8 @@ class Solver {
   void graph_run(GraphSlot &g, F &&body);
   bool use_graph(int level) const;
   void clear_graphs();
-  void vcycle_body(int l, const T *b, T *x);
+  bool vcycle_body(int l, const T *b, T *x, bool defer);
+  bool will_defer(int l) const;
   void coarse_inverse();
   std::vector<OpLevel<T>> ops_;
   DevBuf<double> W_, prow_, colk_;

@@ -897,9 +897,10 @@ __global__ void __launch_bounds__(256) k_vanka_colour(LevelView L, const T *__re
 }
 
 // set: x is zero on entry (first sweep from a zero iterate): store instead of add.
+// The updated values of node i (update_item without the store).
 template <typename T>
-__device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,
-                                            T *__restrict__ x, int i, bool set = false) {
+__device__ __forceinline__ void update_value(const LevelView &L, const T *__restrict__ delta, T omega,
+                                             const T *__restrict__ x, int i, bool set, T &v0, T &v1, T &v2) {
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
   const size_t C = static_cast<size_t>(L.C);
@@ -929,14 +930,24 @@ __device__ __forceinline__ void update_item(const LevelView &L, const T *__restr
   }
   const T w = omega / static_cast<T>(e1 - e0);
   if (set) {
-    x[3 * i] = w * a0;
-    x[3 * i + 1] = w * a1;
-    x[3 * i + 2] = w * a2;
+    v0 = w * a0;
+    v1 = w * a1;
+    v2 = w * a2;
   } else {
-    x[3 * i] = fma_t(w, a0, x[3 * i]);
-    x[3 * i + 1] = fma_t(w, a1, x[3 * i + 1]);
-    x[3 * i + 2] = fma_t(w, a2, x[3 * i + 2]);
+    v0 = fma_t(w, a0, x[3 * i]);
+    v1 = fma_t(w, a1, x[3 * i + 1]);
+    v2 = fma_t(w, a2, x[3 * i + 2]);
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,
+                                            T *__restrict__ x, int i, bool set = false) {
+  T v0, v1, v2;
+  update_value(L, delta, omega, x, i, set, v0, v1, v2);
+  x[3 * i] = v0;
+  x[3 * i + 1] = v1;
+  x[3 * i + 2] = v2;
 }
 
 template <typename T>
@@ -978,6 +989,44 @@ template <typename T>
 __global__ void k_prolong_add(TransferView tv, const T *__restrict__ ec, T *__restrict__ xf) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f < tv.Nf) prolong_item(tv, ec, xf, f);
+}
+
+// The coarse level's last node update (not a first sweep) fused into the
+// prolongation that follows it: fine node f adds P e, where each coarse
+// value it interpolates is that node's updated value, formed with the
+// arithmetic of update_item (a coarse node is updated by each fine node that
+// uses it).  Bitwise k_vanka_update followed by k_prolong_add; the coarse
+// iterate itself is not written (nothing reads it afterwards).
+template <typename T>
+__global__ void k_update_prolong_add(TransferView tv, LevelView Lc, const T *__restrict__ delta, T omega,
+                                     const T *__restrict__ xc, T *__restrict__ xf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= tv.Nf) return;
+  T v0, v1, v2;
+  if (f < tv.Nc) {
+    update_value(Lc, delta, omega, xc, f, false, v0, v1, v2);
+  } else if (f < tv.Nc + tv.Ec) {
+    const int a = tv.edge_ends[2 * (f - tv.Nc)], b = tv.edge_ends[2 * (f - tv.Nc) + 1];
+    T a0, a1, a2, b0, b1, b2;
+    update_value(Lc, delta, omega, xc, a, false, a0, a1, a2);
+    update_value(Lc, delta, omega, xc, b, false, b0, b1, b2);
+    v0 = T(0.5) * (a0 + b0);
+    v1 = T(0.5) * (a1 + b1);
+    v2 = T(0.5) * (a2 + b2);
+  } else {
+    const int4 cn = tv.ccells[f - tv.Nc - tv.Ec];
+    T p[4][3];
+    update_value(Lc, delta, omega, xc, cn.x, false, p[0][0], p[0][1], p[0][2]);
+    update_value(Lc, delta, omega, xc, cn.y, false, p[1][0], p[1][1], p[1][2]);
+    update_value(Lc, delta, omega, xc, cn.z, false, p[2][0], p[2][1], p[2][2]);
+    update_value(Lc, delta, omega, xc, cn.w, false, p[3][0], p[3][1], p[3][2]);
+    v0 = T(0.25) * (p[0][0] + p[1][0] + p[2][0] + p[3][0]);
+    v1 = T(0.25) * (p[0][1] + p[1][1] + p[2][1] + p[3][1]);
+    v2 = T(0.25) * (p[0][2] + p[1][2] + p[2][2] + p[3][2]);
+  }
+  xf[3 * f] += v0;
+  xf[3 * f + 1] += v1;
+  xf[3 * f + 2] += v2;
 }
 
 // r_coarse = P^T r_fine with the Dirichlet velocity rows of the coarse level zeroed.

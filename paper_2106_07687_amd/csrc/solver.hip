@@ -488,6 +488,22 @@ void Solver<T>::autotune() {
       o.bs_prolong = pick([&](int bs) {
         hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, tv, oc.x.p, o.t.p);
       });
+      // the coarser level's last update + this prolongation: separate, or fused
+      o.bs_upro = 0;
+      if (l - 1 > c_) {
+        const int bsu = oc.bs_update, bsq = o.bs_prolong;
+        pick([&](int) {
+          hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(Cl.h.N, bsu)), dim3(bsu), 0, s, Cl.view(), oc.delta.p,
+                             omega, oc.x.p, 0);
+          hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(L.h.N, bsq)), dim3(bsq), 0, s, tv, oc.x.p, o.t.p);
+        });
+        const float t_sep_up = last_t;
+        const int bsf = pick([&](int bs) {
+          hipLaunchKernelGGL(k_update_prolong_add<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, tv, Cl.view(),
+                             oc.delta.p, omega, oc.x.p, o.t.p);
+        });
+        if (last_t < t_sep_up) o.bs_upro = bsf;
+      }
       // residual + restriction: separate at their best sizes, or fused
       o.bs_rres = 0;
       const int bsr = o.bs_restrict;
@@ -617,7 +633,7 @@ void Solver<T>::spmv(int l, const T *x, const T *b, T *y) {
 }
 
 template <typename T>
-void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
+void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer_update) {
   DevLevel &L = *ctx_->levels[l];
   OpLevel<T> &o = ops_[l];
   hipStream_t s = ctx_->stream;
@@ -653,7 +669,7 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start) {
     hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
                        o.inv.p, r, o.delta.p);
   }
-  {
+  if (!defer_update) {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
     hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, o.bs_update)), dim3(o.bs_update), 0, s, L.view(),
                        o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x, zero_start ? 1 : 0);
@@ -725,7 +741,7 @@ void Solver<T>::launch_small(int top, const T *b, T *x) {
 }
 
 template <typename T>
-void Solver<T>::vcycle(int l, const T *b, T *x) {
+bool Solver<T>::vcycle(int l, const T *b, T *x, bool defer) {
   // the outermost call's level is the top of the cycle (nu_pre / nu_post
   // sweeps); the levels below take nu_coarse sweeps when that is set
   struct Depth {
@@ -740,21 +756,33 @@ void Solver<T>::vcycle(int l, const T *b, T *x) {
   if (c_ == 0 && l >= 1 && l <= small_top_ && ctx_->prm.smoother == 0 &&
       (ctx_->prm.nu_coarse == 0 || l != cycle_top_)) {
     launch_small(l, b, x);
-    return;
+    return false;
   }
   if (l > c_ && use_graph(l)) {
-    const auto key = std::make_tuple(l, l == cycle_top_ ? 1 : 0, static_cast<const void *>(b),
+    const auto key = std::make_tuple(l, (l == cycle_top_ ? 1 : 0) + (defer ? 2 : 0), static_cast<const void *>(b),
                                      static_cast<const void *>(x));
     // bound the cache: keys of freed work vectors are never looked up again
     if (vgraphs_.size() >= 512 && vgraphs_.find(key) == vgraphs_.end()) clear_graphs();
-    graph_run(vgraphs_[key], [&]() { vcycle_body(l, b, x); });
-    return;
+    // the body decides from the level and parameters alone (will_defer), so
+    // a replay defers exactly when the captured body did
+    graph_run(vgraphs_[key], [&]() { vcycle_body(l, b, x, defer); });
+    return defer && will_defer(l);
   }
-  vcycle_body(l, b, x);
+  return vcycle_body(l, b, x, defer);
+}
+
+// Whether vcycle_body(l, ..., defer = true) leaves its last update to the
+// caller: an additive smoother with at least one post-sweep on a level above
+// the direct solve.
+template <typename T>
+bool Solver<T>::will_defer(int l) const {
+  if (l <= c_ || ctx_->prm.smoother != 0) return false;
+  const int nu2 = inner_level(l) ? ctx_->prm.nu_coarse : ctx_->prm.nu_post;
+  return nu2 > 0;
 }
 
 template <typename T>
-void Solver<T>::vcycle_body(int l, const T *b, T *x) {
+bool Solver<T>::vcycle_body(int l, const T *b, T *x, bool defer) {
   hipStream_t s = ctx_->stream;
   if (l == c_) {
     ProfScope ps(ctx_->prof, s, "coarse_solve", c_);
@@ -765,7 +793,7 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
       hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(n0_, 4)), dim3(256), 0, s, n0_, W_.p + n0_,
                          2 * static_cast<size_t>(n0_), b, x);
     LAUNCH_CHECK("k_dense_solve");
-    return;
+    return false;
   }
   DevLevel &L = *ctx_->levels[l];
   OpLevel<T> &o = ops_[l];
@@ -789,9 +817,21 @@ void Solver<T>::vcycle_body(int l, const T *b, T *x) {
     spmv(l, x, b, o.r.p);
     restrict_to(l, o.r.p, oc.b.p);
   }
-  vcycle(l - 1, oc.b.p, oc.x.p);
-  prolong_add(l, oc.x.p, x);
-  for (int k = 0; k < nu2; ++k) vanka_sweep(l, x, b, false);
+  // the coarser level's last update fused into the prolongation, where the
+  // autotuner found that faster
+  if (vcycle(l - 1, oc.b.p, oc.x.p, o.bs_upro > 0)) {
+    DevLevel &Cl = *ctx_->levels[l - 1];
+    TransferView tv{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
+    ProfScope ps(ctx_->prof, s, "update_prolong", l);
+    hipLaunchKernelGGL(k_update_prolong_add<T>, dim3(blocks(L.h.N, o.bs_upro)), dim3(o.bs_upro), 0, s, tv,
+                       Cl.view(), oc.delta.p, static_cast<T>(ctx_->prm.vanka_omega), oc.x.p, x);
+    LAUNCH_CHECK("k_update_prolong_add");
+  } else {
+    prolong_add(l, oc.x.p, x);
+  }
+  const bool dfr = defer && will_defer(l);
+  for (int k = 0; k < nu2; ++k) vanka_sweep(l, x, b, false, dfr && k == nu2 - 1);
+  return dfr;
 }
 
 template <typename T>

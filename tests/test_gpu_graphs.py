@@ -133,7 +133,8 @@ def test_autotuned_launches_are_bitwise_equal():
 
 def test_fused_residual_and_apply_is_bitwise_equal():
     """autotune=2 fuses the residual into the Vanka apply (sixteen lanes per
-    cell) and runs the SpMV with four threads per row on every level."""
+    cell), runs the SpMV with four threads per row on every level and fuses
+    each coarse level's last update into the prolongation above it."""
     import paper_2106_07687_amd as P
     macro = channel_obstacle(2)
     ctxs = []
@@ -144,6 +145,8 @@ def test_fused_residual_and_apply_is_bitwise_equal():
     assert all(ctxs[0].launch_config(l)["vanka_smooth"] == 256 for l in range(1, LEVEL + 1))
     assert all(ctxs[0].launch_config(l)["spmv4"] == 256 for l in range(LEVEL + 1))
     assert all(ctxs[0].launch_config(l)["smooth_lanes"] == 16 for l in range(1, LEVEL + 1))
+    assert [ctxs[0].launch_config(l)["update_prolong"] for l in range(LEVEL + 1)] == [0, 0] + [256] * (LEVEL - 1)
+    assert all(ctxs[1].launch_config(l)["update_prolong"] == 0 for l in range(LEVEL + 1))
     lev = mesh.hierarchy(macro, LEVEL)
     x = random_state(lev[LEVEL].n_nodes, 5) * 0.3
     sts = []
