@@ -787,6 +787,7 @@ int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes) {
     block_sizes[8] = o.bs_spmv4;
     block_sizes[9] = o.bs_smooth > 0 ? o.smooth_lanes : 0;
     block_sizes[10] = o.bs_upro;
+    block_sizes[11] = o.bs_apply4;
   };
   if (c.s32)
     fill(*c.s32);

@@ -133,6 +133,7 @@ struct OpLevel {
   int bs_smooth = 0;   // > 0: residual + Vanka apply fused at this size
   int smooth_lanes = 4;   // lanes per cell of the fused kernel: 4 (k_vanka_smooth) or 16 (k_vanka_smooth16)
   int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
+  int bs_apply4 = 0;   // > 0: FP32 Vanka apply with four cells per thread (k_vanka_apply4)
   int bs_upro = 0;     // > 0: the next coarser level's last update fused into
                        // the prolongation to this level (k_update_prolong_add)
 };
@@ -181,16 +182,8 @@ class Solver {
   // Fused residual + Vanka apply (sixteen lanes per cell) and four threads
   // per SpMV row on every level, workgroup size 256 (a fixed configuration,
   // e.g. for reproducible comparisons).
-  void fuse_all() {
-    for (size_t l = 0; l < ops_.size(); ++l) {
-      OpLevel<T> &o = ops_[l];
-      o.bs_smooth = 256;
-      o.smooth_lanes = 16;
-      o.bs_rres = 256;
-      o.bs_spmv4 = 256;
-      o.bs_upro = static_cast<int>(l) - 1 > c_ ? 256 : 0;
-    }
-  }
+  void fuse_all();
+
   // Levels 1..top of every V-cycle (and the level-0 solve) in one workgroup
   // launch; 0 = off.  Needs the blocked level-0 inverse.
   void set_small_top(int top) { small_top_ = gj_b_ > 0 && c_ == 0 ? std::min(top, kSmallLevels - 1) : 0; }

@@ -762,6 +762,40 @@ __global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__res
   if (c < L.C) apply_item(L, inv, r, delta, c);
 }
 
+// The same (FP32) with four consecutive cells per thread: 16-byte loads of
+// the entry-major inverses and 16-byte stores of the corrections (C a
+// multiple of 4, so every row of the layout starts 16-byte aligned); each
+// cell's rows are summed as in apply_item.
+__global__ void __launch_bounds__(256) k_vanka_apply4(LevelView L, const float *__restrict__ inv,
+                                                      const float *__restrict__ r, float *__restrict__ delta) {
+  const int c0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (c0 >= L.C) return;
+  const size_t C = static_cast<size_t>(L.C);
+  float rc[4][12];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int4 cn = L.cells[c0 + q];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) rc[q][3 * a + f] = r[3 * nn[a] + f];
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    float s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      const float4 m = *reinterpret_cast<const float4 *>(inv + static_cast<size_t>(12 * i + j) * C + c0);
+      s0 += m.x * rc[0][j];
+      s1 += m.y * rc[1][j];
+      s2 += m.z * rc[2][j];
+      s3 += m.w * rc[3][j];
+    }
+    *reinterpret_cast<float4 *>(delta + static_cast<size_t>(i) * C + c0) = make_float4(s0, s1, s2, s3);
+  }
+}
+
 // Fused residual + Vanka apply (for small levels, where launches and memory
 // latency dominate): 4 threads per cell, thread a evaluates the residual row
 // b - J x of the cell's node a with the row arithmetic of k_spmv; the four
@@ -899,7 +933,7 @@ __global__ void __launch_bounds__(256) k_vanka_colour(LevelView L, const T *__re
 // set: x is zero on entry (first sweep from a zero iterate): store instead of add.
 // The updated values of node i (update_item without the store).
 template <typename T>
-__device__ __forceinline__ void update_value(const LevelView &L, const T *__restrict__ delta, T omega,
+__device__ __forceinline__ void update_row(const LevelView &L, const T *__restrict__ delta, T omega,
                                              const T *__restrict__ x, int i, bool set, T &v0, T &v1, T &v2) {
   T a0 = 0, a1 = 0, a2 = 0;
   const int e0 = L.cadj_ptr[i], e1 = L.cadj_ptr[i + 1];
@@ -944,7 +978,7 @@ template <typename T>
 __device__ __forceinline__ void update_item(const LevelView &L, const T *__restrict__ delta, T omega,
                                             T *__restrict__ x, int i, bool set = false) {
   T v0, v1, v2;
-  update_value(L, delta, omega, x, i, set, v0, v1, v2);
+  update_row(L, delta, omega, x, i, set, v0, v1, v2);
   x[3 * i] = v0;
   x[3 * i + 1] = v1;
   x[3 * i + 2] = v2;
@@ -1004,22 +1038,22 @@ __global__ void k_update_prolong_add(TransferView tv, LevelView Lc, const T *__r
   if (f >= tv.Nf) return;
   T v0, v1, v2;
   if (f < tv.Nc) {
-    update_value(Lc, delta, omega, xc, f, false, v0, v1, v2);
+    update_row(Lc, delta, omega, xc, f, false, v0, v1, v2);
   } else if (f < tv.Nc + tv.Ec) {
     const int a = tv.edge_ends[2 * (f - tv.Nc)], b = tv.edge_ends[2 * (f - tv.Nc) + 1];
     T a0, a1, a2, b0, b1, b2;
-    update_value(Lc, delta, omega, xc, a, false, a0, a1, a2);
-    update_value(Lc, delta, omega, xc, b, false, b0, b1, b2);
+    update_row(Lc, delta, omega, xc, a, false, a0, a1, a2);
+    update_row(Lc, delta, omega, xc, b, false, b0, b1, b2);
     v0 = T(0.5) * (a0 + b0);
     v1 = T(0.5) * (a1 + b1);
     v2 = T(0.5) * (a2 + b2);
   } else {
     const int4 cn = tv.ccells[f - tv.Nc - tv.Ec];
     T p[4][3];
-    update_value(Lc, delta, omega, xc, cn.x, false, p[0][0], p[0][1], p[0][2]);
-    update_value(Lc, delta, omega, xc, cn.y, false, p[1][0], p[1][1], p[1][2]);
-    update_value(Lc, delta, omega, xc, cn.z, false, p[2][0], p[2][1], p[2][2]);
-    update_value(Lc, delta, omega, xc, cn.w, false, p[3][0], p[3][1], p[3][2]);
+    update_row(Lc, delta, omega, xc, cn.x, false, p[0][0], p[0][1], p[0][2]);
+    update_row(Lc, delta, omega, xc, cn.y, false, p[1][0], p[1][1], p[1][2]);
+    update_row(Lc, delta, omega, xc, cn.z, false, p[2][0], p[2][1], p[2][2]);
+    update_row(Lc, delta, omega, xc, cn.w, false, p[3][0], p[3][1], p[3][2]);
     v0 = T(0.25) * (p[0][0] + p[1][0] + p[2][0] + p[3][0]);
     v1 = T(0.25) * (p[0][1] + p[1][1] + p[2][1] + p[3][1]);
     v2 = T(0.25) * (p[0][2] + p[1][2] + p[2][2] + p[3][2]);

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "context.h"
 
@@ -380,6 +381,20 @@ void Solver<T>::setup(int finest) {
   lin_level_ = -1;
 }
 
+// Every fused or vectorised launch variant at workgroup size 256 (no timing).
+template <typename T>
+void Solver<T>::fuse_all() {
+  for (size_t l = 0; l < ops_.size(); ++l) {
+    OpLevel<T> &o = ops_[l];
+    o.bs_smooth = 256;
+    o.smooth_lanes = 16;
+    o.bs_rres = 256;
+    o.bs_spmv4 = 256;
+    o.bs_upro = static_cast<int>(l) - 1 > c_ ? 256 : 0;
+    o.bs_apply4 = ctx_->levels[l]->h.C % 4 == 0 ? 256 : 0;
+  }
+}
+
 template <typename T>
 void Solver<T>::autotune() {
   hipStream_t s = ctx_->stream;
@@ -448,12 +463,31 @@ void Solver<T>::autotune() {
         hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
                            o.delta.p);
       });
+      // four cells per thread with 16-byte loads (FP32, C a multiple of 4): kept if faster
+      o.bs_apply4 = 0;
+      if constexpr (std::is_same_v<T, float>) {
+        if (L.h.C % 4 == 0) {
+          const float t_one_apply = last_t;
+          const int bs4a = pick([&](int bs) {
+            hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
+                               o.delta.p);
+          });
+          if (last_t < t_one_apply) o.bs_apply4 = bs4a;
+        }
+      }
       // residual + apply: separate kernels at their best sizes, or fused
       o.bs_smooth = 0;
-      const int bsp = o.bs_spmv, bap = o.bs_apply;
+      const int bsp = o.bs_spmv, bap = o.bs_apply, bap4 = o.bs_apply4;
       pick([&](int) {
         hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bsp)), dim3(bsp), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
                            o.b.p, o.r.p);
+        if constexpr (std::is_same_v<T, float>) {
+          if (bap4 > 0) {
+            hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, bap4)), dim3(bap4), 0, s, v, o.inv.p,
+                               o.r.p, o.delta.p);
+            return;
+          }
+        }
         hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bap)), dim3(bap), 0, s, v, o.inv.p, o.r.p,
                            o.delta.p);
       });
@@ -666,8 +700,16 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer
       r = o.r.p;
     }
     ProfScope ps(ctx_->prof, s, "vanka_apply", l);
-    hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
-                       o.inv.p, r, o.delta.p);
+    if constexpr (std::is_same_v<T, float>) {
+      if (o.bs_apply4 > 0) {
+        hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, o.bs_apply4)), dim3(o.bs_apply4), 0, s,
+                           L.view(), o.inv.p, r, o.delta.p);
+        LAUNCH_CHECK("k_vanka_apply4");
+      }
+    }
+    if (!(std::is_same_v<T, float> && o.bs_apply4 > 0))
+      hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
+                         o.inv.p, r, o.delta.p);
   }
   if (!defer_update) {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
