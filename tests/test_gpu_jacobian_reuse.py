@@ -149,3 +149,40 @@ def test_stale_jacobian_behind_the_library_still_converges():
     for c, s in ((ref, sr), (ctx, st)):
         s.close()
         c.close()
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-10), (1, 1e-5)])
+def test_direct_solve_level_and_fused_variants_keep_the_trajectory(precision, bar):
+    """The benchmark's solver configuration (direct solve on level 1, kept
+    Jacobians, autotuned launch variants) against the plain one (level-0
+    direct solve, rebuilds, no autotuning): the same x_n per step to the
+    Newton tolerance (FP64 1e-10, mixed 1e-5 relative L2 per field), and
+    the FP64 trajectory against the oracle's direct-solve Newton steps."""
+    import paper_2106_07687_amd as P
+    macro = channel_obstacle(0)
+    lev = mesh.hierarchy(macro, LEVEL)
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    # absolute Newton tolerance: the first steps from rest have small
+    # velocities, so FP64 runs at 1e-14 as the FP64 parity tests do
+    tol = 1e-14 if precision == 0 else 1e-12
+    ctxs = [P.Context(precision=precision, nu=macro.nu, newton_tol=tol, coarse_level=1, jacobian_reuse=1),
+            P.Context(precision=precision, nu=macro.nu, newton_tol=tol, autotune=0)]
+    sts = []
+    for c in ctxs:
+        c.setup_mesh(macro, LEVEL)
+        sts.append(c.state(LEVEL))
+    x_ref = np.zeros(3 * lev[LEVEL].n_nodes)
+    for n in range(1, 5):
+        infos = [c.step(s, DT) for c, s in zip(ctxs, sts)]
+        assert all(i["converged"] == 1 for i in infos), infos
+        e = _fields(sts[0].get()[0], sts[1].get()[0])
+        print(f"[direct level 1] precision {precision} step {n}: {e:.2e}, gmres "
+              f"{infos[0]['gmres_iters']} vs {infos[1]['gmres_iters']}, builds {infos[0]['jacobian_builds']}",
+              flush=True)
+        assert e < bar, (n, e)
+        if precision == 0:
+            x_ref = solver.newton_step(lev[LEVEL], prob, x_ref, n * DT, tol=1e-15)
+            assert _fields(sts[0].get()[0], x_ref) < 1e-10, n
+    for c, s in zip(ctxs, sts):
+        s.close()
+        c.close()
