@@ -117,8 +117,7 @@ void build_patch_tables(Net &n) {
 
 void gemm(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *Bm, int ldb,
           float *C, int ldc, bool acc) {
-  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
-  hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, Bm, ldb, C, ldc, acc ? 1 : 0);
+  launch_gemm_nt(s, M, N, K, A, lda, Bm, ldb, C, ldc, acc);
   check(hipGetLastError(), "k_gemm_nt_bf16");
 }
 

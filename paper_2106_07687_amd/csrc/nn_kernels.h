@@ -105,6 +105,106 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const
     }
 }
 
+// The same product with a 128 x 128 tile per workgroup (4 waves, each 64 x 64
+// as 4 x 4 MFMA 16x16x16 blocks) and 64-wide K chunks, the next chunk loaded
+// into registers while the current one is multiplied out of LDS: four times
+// the MFMA work per LDS byte and a quarter of the barriers, for products
+// with enough tiles to fill the chip.  Every element's MFMA sequence over K
+// (16-wide steps in order; a chunk past K is cut at K, a multiple of 32) is
+// that of k_gemm_nt_bf16, so the two give bitwise the same C.
+constexpr int GBM2 = 128, GBN2 = 128, GBK2 = 64;
+__global__ void __launch_bounds__(256) k_gemm_nt_bf16_128(int M, int N, int K, const uint16_t *__restrict__ A,
+                                                          int lda, const uint16_t *__restrict__ Bm, int ldb,
+                                                          float *__restrict__ Cm, int ldc, int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM2][GBK2 + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN2][GBK2 + GPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int bm = blockIdx.y * GBM2, bn = blockIdx.x * GBN2;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 3, lc = (tid & 7) * 8;   // loader: rows lr + 32 h, 8-element chunk lc
+  uint4 va[4], vb[4];
+  auto load = [&](int k0) {
+    const bool kin = k0 + lc < K;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = lr + 32 * h;
+      va[h] = kin && bm + r < M
+                  ? *reinterpret_cast<const uint4 *>(A + static_cast<size_t>(bm + r) * lda + k0 + lc)
+                  : make_uint4(0, 0, 0, 0);
+      vb[h] = kin && bn + r < N
+                  ? *reinterpret_cast<const uint4 *>(Bm + static_cast<size_t>(bn + r) * ldb + k0 + lc)
+                  : make_uint4(0, 0, 0, 0);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GBK2) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      *reinterpret_cast<uint4 *>(&As[lr + 32 * h][lc]) = va[h];
+      *reinterpret_cast<uint4 *>(&Bs[lr + 32 * h][lc]) = vb[h];
+    }
+    __syncthreads();
+    if (k0 + GBK2 < K) load(k0 + GBK2);
+    const int kend = min(GBK2, K - k0);
+#pragma unroll
+    for (int kk = 0; kk < GBK2; kk += 16) {
+      if (kk >= kend) break;
+      bf16x4 a[4], b[4];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint16_t *pa = &As[wm * 64 + i * 16 + (lane & 15)][kq];
+        const uint16_t *pb = &Bs[wn * 64 + i * 16 + (lane & 15)][kq];
+        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
+                      static_cast<short>(pa[3])};
+        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
+                      static_cast<short>(pb[3])};
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = bn + wn * 64 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M) {
+          float *c = Cm + static_cast<size_t>(row) * ldc + col;
+          *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+    }
+}
+
+// C (+)= A B^T on stream s: the 128 x 128 tile kernel when the product has at
+// least 256 such tiles (enough to fill the chip), else the 64 x 64 one; the
+// result is bitwise the same either way.
+inline void launch_gemm_nt(hipStream_t s, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B,
+                           int ldb, float *C, int ldc, bool acc) {
+  const long tiles128 = static_cast<long>((M + GBM2 - 1) / GBM2) * ((N + GBN2 - 1) / GBN2);
+  if (tiles128 >= 256)
+    hipLaunchKernelGGL(k_gemm_nt_bf16_128, dim3((N + GBN2 - 1) / GBN2, (M + GBM2 - 1) / GBM2), dim3(256), 0, s, M,
+                       N, K, A, lda, B, ldb, C, ldc, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_gemm_nt_bf16, dim3((N + GBN - 1) / GBN, (M + GBM - 1) / GBM), dim3(256), 0, s, M, N, K,
+                       A, lda, B, ldb, C, ldc, acc ? 1 : 0);
+}
+
 // One GRU time step of a layer (gate rows r, z, n): the recurrent product
 // Gh = h_in W_hh^T for a tile of 64 rows x 32 hidden units and all three
 // gates (MFMA 16x16x16 BF16, the K loop in 32-wide chunks as in

@@ -18,9 +18,7 @@ void gemm_nt(hipStream_t s, long M, int N, int K, const uint16_t *A, int lda, co
   const long chunk = 32768L * GBM;
   for (long m0 = 0; m0 < M; m0 += chunk) {
     const int mc = static_cast<int>(std::min(chunk, M - m0));
-    dim3 grid((N + GBN - 1) / GBN, (mc + GBM - 1) / GBM);
-    hipLaunchKernelGGL(k_gemm_nt_bf16, grid, dim3(256), 0, s, mc, N, K, A + m0 * lda, lda, B, ldb, C + m0 * ldc,
-                       ldc, acc ? 1 : 0);
+    launch_gemm_nt(s, mc, N, K, A + m0 * lda, lda, B, ldb, C + m0 * ldc, ldc, acc);
   }
   check(hipGetLastError(), "k_gemm_nt_bf16");
 }
