@@ -397,29 +397,42 @@ def run_table1(P, args, log):
         sec = time.perf_counter() - t0
         st.close()
         st = restart(net)
-        lift, err = [], []
+        lift, err, newton = [], [], []
+        builds = fallbacks = 0
         for n in range(n_start + 1, n_end + 1):
-            ctx.step(st, dt)
+            info = ctx.step(st, dt)
+            newton.append(info["newton_iters"])
+            builds += info["jacobian_builds"]
+            fallbacks += info["fallback"]
             corr = net.correct(st, dt, debug=True)["correction"] if net is not None else None
             xl = st.get()[0]
             if n >= w0:
                 err.append(velocity_error(ctx, xl, L, F, xF[n], corr))
                 lift.append(float(ctx.functionals(F, fine_state(ctx, xl, L, F, corr), 1)[2][0]))
         st.close()
-        return (n_end - n_start) / sec, float(np.mean(err)), P.oscillation(lift, w0 * dt, dt)
+        stats = {"newton_iters": int(sum(newton)), "jacobian_builds": builds, "fallbacks": fallbacks,
+                 "newton_first10_median": float(np.median(newton[:10]))}
+        return (n_end - n_start) / sec, float(np.mean(err)), P.oscillation(lift, w0 * dt, dt), stats
 
     def phase(osc):
         """(period, first-maximum offset against MG(F) in periods of MG(F))."""
         off = (osc[0] - osc_F[0]) / osc_F[1]
         return round(osc[1], 5), round(float(off - np.round(off)), 4)
 
-    sps_L, err_L, osc_L = coarse_run()
+    sps_L, err_L, osc_L, st_L = coarse_run()
+    # switch-off (Sec. 3.3): a DNN-MG step whose Newton iteration needs more than
+    # twice the plain coarse method's median count over its first 10 steps is
+    # redone with the plain right-hand side
+    n_off = max(1, int(round(2 * st_L["newton_first10_median"])))
+    ctx.set_params(switch_off_newton=n_off)
     out = {"coarse_level": L, "fine_level": F, "dt": dt, "t_train": [n_train * dt, n_start * dt],
            "t_run": [n_start * dt, n_end * dt], "window": [w0 * dt, n_end * dt],
            "coarse_dofs": 3 * nL, "fine_dofs": 3 * ctx.level_info(F)[0],
            "mg_fine": {"steps_per_s": round(n_end / fine_sec, 2), "lift_period": round(osc_F[1], 5)},
            "mg_coarse": {"steps_per_s": round(sps_L, 2), "vel_err": round(err_L, 6),
-                         "lift_period": phase(osc_L)[0], "lift_phase_offset": phase(osc_L)[1]},
+                         "lift_period": phase(osc_L)[0], "lift_phase_offset": phase(osc_L)[1],
+                         "newton_iters": st_L["newton_iters"], "jacobian_builds": st_L["jacobian_builds"]},
+           "switch_off_newton": n_off,
            "nets": []}
     log(f"table1 MG(F): {out['mg_fine']}; MG(L): {out['mg_coarse']}")
     probe = P.Net(ctx, L, 1, 32, 1, patch="cell")
@@ -439,14 +452,15 @@ def run_table1(P, args, log):
         loss = fit(args.t1_iters, 2e-3)
         bptt_ms = 1e3 * fit.sec / fit.iters
         del fit, X, D
-        sps, err, osc_d = coarse_run(net)
+        sps, err, osc_d, st_d = coarse_run(net)
         per, off = phase(osc_d)
         row = {"hidden": H, "layers": layers, "params": net.n_params, "n_in": net.n_in, "n_out": net.n_out,
                "sequences": Xr.shape[1], "seq": seq, "bptt_iters": args.t1_iters,
                "bptt_ms_per_iter": round(bptt_ms, 3), "train_sec": round(bptt_ms * args.t1_iters / 1e3, 2),
                "final_loss": round(float(loss), 3),
                "steps_per_s": round(sps, 2), "vel_err": round(err, 6), "lift_period": per,
-               "lift_phase_offset": off}
+               "lift_phase_offset": off, "newton_iters": st_d["newton_iters"],
+               "jacobian_builds": st_d["jacobian_builds"], "fallbacks": st_d["fallbacks"]}
         log(f"table1 {H}x{layers}: {row}")
         out["nets"].append(row)
         net.close()
