@@ -458,6 +458,92 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_strided(int M, int N, int K, 
     }
 }
 
+// The same product for K-major operands with unit stride along m and n (A(m,
+// k) = A[k lda + m], B(n, k) = B[k ldb + n]; lda, ldb and M multiples of 8;
+// B columns are read up to Nl, N rounded up to 8, which each row of B must
+// hold): each thread loads 8 consecutive m (or n) of one k row with one
+// 16-byte load, so a workgroup reads whole 128-byte rows, and scatters them
+// into the [m][k] LDS layout.  The LDS contents of the stored columns, and so
+// every MFMA and its order, are those of k_gemm_bf16_strided: bitwise the
+// same C.
+__global__ void __launch_bounds__(256) k_gemm_bf16_tn(int M, int N, int Nl, int K, int kz,
+                                                      const uint16_t *__restrict__ A, long lda,
+                                                      const uint16_t *__restrict__ Bm, long ldb,
+                                                      float *__restrict__ Cm, int ldc, long zstride,
+                                                      int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+  const int kb = blockIdx.z * kz, ke = min(K, kb + kz);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lk = tid >> 3, lm = (tid & 7) * 8;   // loader: k row lk, 8 consecutive m (n) from lm
+  uint4 va, vb;
+  // the next K chunk is loaded into registers while the current one is
+  // multiplied out of LDS
+  auto load = [&](int k0) {
+    const int k = k0 + lk;
+    va = make_uint4(0, 0, 0, 0);
+    vb = make_uint4(0, 0, 0, 0);
+    if (k < ke && bm + lm < M) va = *reinterpret_cast<const uint4 *>(A + static_cast<size_t>(k) * lda + bm + lm);
+    if (k < ke && bn + lm < Nl) vb = *reinterpret_cast<const uint4 *>(Bm + static_cast<size_t>(k) * ldb + bn + lm);
+  };
+  load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    __syncthreads();
+    const uint16_t *ea = reinterpret_cast<const uint16_t *>(&va);
+    const uint16_t *eb = reinterpret_cast<const uint16_t *>(&vb);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[lm + e][lk] = ea[e];
+      Bs[lm + e][lk] = eb[e];
+    }
+    __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      bf16x4 a[2], b[2];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
+        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
+        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
+                      static_cast<short>(pa[3])};
+        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
+                      static_cast<short>(pb[3])};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  float *Cz = Cm + blockIdx.z * zstride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = bn + wn * 32 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M) {
+          float *c = Cz + static_cast<size_t>(row) * ldc + col;
+          *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+    }
+}
+
 // dst[i] (+)= sum_z part[z * zstride + i] for an M x N block with leading
 // dimension ld (fixed z order: deterministic).
 __global__ void k_reduce_split(int M, int N, int ld, int Z, long zstride, const float *__restrict__ part,

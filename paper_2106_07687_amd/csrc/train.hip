@@ -26,6 +26,21 @@ void gemm_nt(hipStream_t s, long M, int N, int K, const uint16_t *A, int lda, co
 // C (+)= A(m,k) B(n,k) with general strides; split-K through `part`.
 void gemm_strided(hipStream_t s, int M, int N, int K, const uint16_t *A, long sAm, long sAk,
                   const uint16_t *B, long sBn, long sBk, float *C, int ldc, bool acc, DevBuf<float> &part) {
+  // K-major operands with unit stride along m and n: the kernel with 16-byte
+  // row loads (bitwise the same products)
+  // (measured: for the input width of the first layer, N not a multiple of 8
+  // and read up to the padded row length, the element-gather kernel is as
+  // fast, so the 16-byte path is taken for N a multiple of 8 only)
+  const int Nl = N;
+  const bool tn = sAm == 1 && sBn == 1 && sAk % 8 == 0 && sBk % 8 == 0 && M % 8 == 0 && N % 8 == 0 &&
+                  reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  auto launch = [&](dim3 g, int m, int kz, const uint16_t *a, float *c, int ld, long zs, int accf) {
+    if (tn)
+      hipLaunchKernelGGL(k_gemm_bf16_tn, g, dim3(256), 0, s, m, N, Nl, K, kz, a, sAk, B, sBk, c, ld, zs, accf);
+    else
+      hipLaunchKernelGGL(k_gemm_bf16_strided, g, dim3(256), 0, s, m, N, K, kz, a, sAm, sAk, B, sBn, sBk, c, ld, zs,
+                         accf);
+  };
   const long tiles = static_cast<long>((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
   int Z = 1;
   while (tiles * Z < 512 && K / (Z * 2) >= 1024) Z *= 2;
@@ -36,8 +51,7 @@ void gemm_strided(hipStream_t s, int M, int N, int K, const uint16_t *A, long sA
     for (int m0 = 0; m0 < M; m0 += chunk) {
       const int mc = std::min(chunk, M - m0);
       dim3 g1((N + GBN - 1) / GBN, (mc + GBM - 1) / GBM);
-      hipLaunchKernelGGL(k_gemm_bf16_strided, g1, dim3(256), 0, s, mc, N, K, K, A + m0 * sAm, sAm, sAk, B, sBn, sBk,
-                         C + static_cast<long>(m0) * ldc, ldc, 0L, acc ? 1 : 0);
+      launch(g1, mc, K, A + m0 * sAm, C + static_cast<long>(m0) * ldc, ldc, 0L, acc ? 1 : 0);
     }
     check(hipGetLastError(), "k_gemm_bf16_strided");
     return;
@@ -45,8 +59,7 @@ void gemm_strided(hipStream_t s, int M, int N, int K, const uint16_t *A, long sA
   const int kz = ((K + Z - 1) / Z + GBK - 1) / GBK * GBK;
   const size_t need = static_cast<size_t>(Z) * M * N;
   if (part.n < need) part.alloc(need);
-  hipLaunchKernelGGL(k_gemm_bf16_strided, grid, dim3(256), 0, s, M, N, K, kz, A, sAm, sAk, B, sBn, sBk, part.p,
-                     N, static_cast<long>(M) * N, 0);
+  launch(grid, M, kz, A, part.p, N, static_cast<long>(M) * N, 0);
   hipLaunchKernelGGL(k_reduce_split, dim3(blocks(static_cast<size_t>(M) * N, 256)), dim3(256), 0, s, M, N, N, Z,
                      static_cast<long>(M) * N, part.p, C, ldc, acc ? 1 : 0);
   check(hipGetLastError(), "split-K GEMM");
