@@ -735,8 +735,10 @@ __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__re
 }
 
 // delta_c = inv_c r|_c, one thread per cell, stored entry-major
-// delta[(3 a + f) * C + c].
-template <typename T>
+// delta[(3 a + f) * C + c].  With kStream the inverse is read with
+// non-temporal loads (for levels whose inverses are far larger than the
+// caches: streamed once per sweep, they would only evict the residual).
+template <typename T, bool kStream = false>
 __device__ __forceinline__ void apply_item(const LevelView &L, const T *__restrict__ inv, const T *__restrict__ r,
                                            T *__restrict__ delta, int c) {
   const int4 cn = L.cells[c];
@@ -750,17 +752,24 @@ __device__ __forceinline__ void apply_item(const LevelView &L, const T *__restri
   for (int i = 0; i < 12; ++i) {
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) s += inv[static_cast<size_t>(12 * i + j) * L.C + c] * rc[j];
+    for (int j = 0; j < 12; ++j) {
+      const T *p = inv + static_cast<size_t>(12 * i + j) * L.C + c;
+      s += (kStream ? __builtin_nontemporal_load(p) : *p) * rc[j];
+    }
     delta[static_cast<size_t>(i) * L.C + c] = s;
   }
 }
 
-template <typename T>
+template <typename T, bool kStream = false>
 __global__ void __launch_bounds__(256) k_vanka_apply(LevelView L, const T *__restrict__ inv, const T *__restrict__ r,
                               T *__restrict__ delta) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < L.C) apply_item(L, inv, r, delta, c);
+  if (c < L.C) apply_item<T, kStream>(L, inv, r, delta, c);
 }
+
+// Levels with at least this many cells read their Vanka inverses with
+// non-temporal loads (576 B per cell in FP32: 134 MB and more).
+constexpr int kStreamCells = 1 << 18;
 
 // The same (FP32) with four consecutive cells per thread: 16-byte loads of
 // the entry-major inverses and 16-byte stores of the corrections (C a

@@ -382,6 +382,16 @@ void Solver<T>::setup(int finest) {
 }
 
 // Every fused or vectorised launch variant at workgroup size 256 (no timing).
+// The one-cell-per-thread Vanka apply, streaming the inverses on levels with
+// at least kStreamCells cells.
+template <typename T>
+void launch_apply(hipStream_t s, int C, int bs, const LevelView &v, const T *inv, const T *r, T *delta) {
+  if (C >= kStreamCells)
+    hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3(blocks(C, bs)), dim3(bs), 0, s, v, inv, r, delta);
+  else
+    hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3(blocks(C, bs)), dim3(bs), 0, s, v, inv, r, delta);
+}
+
 template <typename T>
 void Solver<T>::fuse_all() {
   for (size_t l = 0; l < ops_.size(); ++l) {
@@ -460,8 +470,7 @@ void Solver<T>::autotune() {
       if (last_t < t_one) o.bs_spmv4 = bs4;
       if (l == 0) continue;
       o.bs_apply = pick([&](int bs) {
-        hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
-                           o.delta.p);
+        launch_apply<T>(s, L.h.C, bs, v, o.inv.p, o.r.p, o.delta.p);
       });
       // four cells per thread with 16-byte loads (FP32, C a multiple of 4): kept if faster
       o.bs_apply4 = 0;
@@ -488,8 +497,7 @@ void Solver<T>::autotune() {
             return;
           }
         }
-        hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, bap)), dim3(bap), 0, s, v, o.inv.p, o.r.p,
-                           o.delta.p);
+        launch_apply<T>(s, L.h.C, bap, v, o.inv.p, o.r.p, o.delta.p);
       });
       const float t_sep = last_t;
       const int bsm = pick([&](int bs) {
@@ -708,8 +716,7 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer
       }
     }
     if (!(std::is_same_v<T, float> && o.bs_apply4 > 0))
-      hipLaunchKernelGGL(k_vanka_apply<T>, dim3(blocks(L.h.C, o.bs_apply)), dim3(o.bs_apply), 0, s, L.view(),
-                         o.inv.p, r, o.delta.p);
+      launch_apply<T>(s, L.h.C, o.bs_apply, L.view(), o.inv.p, r, o.delta.p);
   }
   if (!defer_update) {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
