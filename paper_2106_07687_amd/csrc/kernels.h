@@ -480,7 +480,14 @@ constexpr int kSpmvChunk = 16;
 // q of four: both give the same bits.  Chunks of kSpmvChunk entries: all
 // column indices of a chunk, then all x values, then the products, so that a
 // thread waits on two memory latencies per chunk, not two per entry.
-template <typename T>
+// Operator loads, optionally non-temporal (see kStreamCells).
+template <bool kStream, typename T>
+__device__ __forceinline__ T op_load(const T *p) {
+  if constexpr (kStream) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <typename T, bool kStream = false>
 __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
                                          const T *__restrict__ x, int i, T &a0, T &a1, T &a2) {
   const int s = i / kS, lane = i % kS;
@@ -505,8 +512,9 @@ __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict
         const T *m = jq + static_cast<size_t>(k0 + u) * 9 * kS;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
-          p[u & 3][f] += fma_t(m[(3 * f + 2) * kS], xv[u][2],
-                               fma_t(m[(3 * f + 1) * kS], xv[u][1], m[3 * f * kS] * xv[u][0]));
+          p[u & 3][f] += fma_t(op_load<kStream>(m + (3 * f + 2) * kS), xv[u][2],
+                               fma_t(op_load<kStream>(m + (3 * f + 1) * kS), xv[u][1],
+                                     op_load<kStream>(m + 3 * f * kS) * xv[u][0]));
       }
     }
   }
@@ -521,7 +529,7 @@ __device__ __forceinline__ void spmv_row(const LevelView &L, const T *__restrict
     for (int u = 0; u < kSpmvChunk; ++u) xv[u] = jv[u] >= 0 ? x[3 * jv[u] + 2] : T(0);
 #pragma unroll
     for (int u = 0; u < kSpmvChunk; ++u)
-      if (jv[u] >= 0) p[u & 3][2] = fma_t(jx[(k0 + u) * kS], xv[u], p[u & 3][2]);
+      if (jv[u] >= 0) p[u & 3][2] = fma_t(op_load<kStream>(jx + (k0 + u) * kS), xv[u], p[u & 3][2]);
   }
   a0 = (p[0][0] + p[1][0]) + (p[2][0] + p[3][0]);
   a1 = (p[0][1] + p[1][1]) + (p[2][1] + p[3][1]);
@@ -585,12 +593,12 @@ __device__ __forceinline__ void spmv_row_part(const LevelView &L, const T *__res
 // Each kernel below is a grid over items (nodes, cells) calling the item
 // function of the same name; the single-workgroup coarse V-cycle calls the
 // same item functions, so both paths compute bitwise the same values.
-template <typename T>
+template <typename T, bool kStream = false>
 __device__ __forceinline__ void spmv_item(const LevelView &L, const T *__restrict__ JQ, const T *__restrict__ JX,
                                           const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y,
                                           int i) {
   T a0, a1, a2;
-  spmv_row(L, JQ, JX, x, i, a0, a1, a2);
+  spmv_row<T, kStream>(L, JQ, JX, x, i, a0, a1, a2);
   if (b) {
     y[3 * i] = b[3 * i] - a0;
     y[3 * i + 1] = b[3 * i + 1] - a1;
@@ -602,11 +610,11 @@ __device__ __forceinline__ void spmv_item(const LevelView &L, const T *__restric
   }
 }
 
-template <typename T>
+template <typename T, bool kStream = false>
 __global__ void __launch_bounds__(256) k_spmv(LevelView L, const T *__restrict__ JQ, const T *__restrict__ JX,
                        const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < L.N) spmv_item(L, JQ, JX, x, b, y, i);
+  if (i < L.N) spmv_item<T, kStream>(L, JQ, JX, x, b, y, i);
 }
 
 // The same rows with four threads per node (more loads in flight on small

@@ -382,6 +382,17 @@ void Solver<T>::setup(int finest) {
 }
 
 // Every fused or vectorised launch variant at workgroup size 256 (no timing).
+// The one-thread-per-row SpMV, streaming the operator on levels with at
+// least kStreamCells nodes.
+template <typename T>
+void launch_spmv(hipStream_t s, int N, int bs, const LevelView &v, const T *JQ, const T *JX, const T *x,
+                 const T *b, T *y) {
+  if (N >= kStreamCells)
+    hipLaunchKernelGGL((k_spmv<T, true>), dim3(blocks(N, bs)), dim3(bs), 0, s, v, JQ, JX, x, b, y);
+  else
+    hipLaunchKernelGGL((k_spmv<T, false>), dim3(blocks(N, bs)), dim3(bs), 0, s, v, JQ, JX, x, b, y);
+}
+
 // The one-cell-per-thread Vanka apply, streaming the inverses on levels with
 // at least kStreamCells cells.
 template <typename T>
@@ -457,8 +468,7 @@ void Solver<T>::autotune() {
       OpLevel<T> &o = ops_[l];
       const LevelView v = L.view();
       o.bs_spmv = pick([&](int bs) {
-        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
-                           o.b.p, o.t.p);
+        launch_spmv<T>(s, L.h.N, bs, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.t.p);
       });
       // four threads per row (bitwise the same rows): kept if faster
       o.bs_spmv4 = 0;
@@ -488,8 +498,7 @@ void Solver<T>::autotune() {
       o.bs_smooth = 0;
       const int bsp = o.bs_spmv, bap = o.bs_apply, bap4 = o.bs_apply4;
       pick([&](int) {
-        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bsp)), dim3(bsp), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
-                           o.b.p, o.r.p);
+        launch_spmv<T>(s, L.h.N, bsp, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.r.p);
         if constexpr (std::is_same_v<T, float>) {
           if (bap4 > 0) {
             hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, bap4)), dim3(bap4), 0, s, v, o.inv.p,
@@ -550,8 +559,7 @@ void Solver<T>::autotune() {
       o.bs_rres = 0;
       const int bsr = o.bs_restrict;
       pick([&](int) {
-        hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, bsp)), dim3(bsp), 0, s, v, o.JQ.p, o.JX.p, o.x.p,
-                           o.b.p, o.r.p);
+        launch_spmv<T>(s, L.h.N, bsp, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.r.p);
         hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bsr)), dim3(bsr), 0, s, tv, o.r.p, oc.t.p);
       });
       const float t_sep2 = last_t;
@@ -669,8 +677,7 @@ void Solver<T>::spmv(int l, const T *x, const T *b, T *y) {
     hipLaunchKernelGGL(k_spmv4<T>, dim3(blocks(4 * static_cast<size_t>(L.h.N), o.bs_spmv4)), dim3(o.bs_spmv4), 0,
                        ctx_->stream, L.view(), o.JQ.p, o.JX.p, x, b, y);
   else
-    hipLaunchKernelGGL(k_spmv<T>, dim3(blocks(L.h.N, o.bs_spmv)), dim3(o.bs_spmv), 0, ctx_->stream, L.view(),
-                       o.JQ.p, o.JX.p, x, b, y);
+    launch_spmv<T>(ctx_->stream, L.h.N, o.bs_spmv, L.view(), o.JQ.p, o.JX.p, x, b, y);
   LAUNCH_CHECK("k_spmv");
 }
 
