@@ -783,6 +783,8 @@ constexpr int kStreamCells = 1 << 18;
 // the entry-major inverses and 16-byte stores of the corrections (C a
 // multiple of 4, so every row of the layout starts 16-byte aligned); each
 // cell's rows are summed as in apply_item.
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <bool kStream = false>
 __global__ void __launch_bounds__(256) k_vanka_apply4(LevelView L, const float *__restrict__ inv,
                                                       const float *__restrict__ r, float *__restrict__ delta) {
   const int c0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
@@ -803,11 +805,11 @@ __global__ void __launch_bounds__(256) k_vanka_apply4(LevelView L, const float *
     float s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
-      const float4 m = *reinterpret_cast<const float4 *>(inv + static_cast<size_t>(12 * i + j) * C + c0);
-      s0 += m.x * rc[0][j];
-      s1 += m.y * rc[1][j];
-      s2 += m.z * rc[2][j];
-      s3 += m.w * rc[3][j];
+      const v4f m = op_load<kStream>(reinterpret_cast<const v4f *>(inv + static_cast<size_t>(12 * i + j) * C + c0));
+      s0 += m[0] * rc[0][j];
+      s1 += m[1] * rc[1][j];
+      s2 += m[2] * rc[2][j];
+      s3 += m[3] * rc[3][j];
     }
     *reinterpret_cast<float4 *>(delta + static_cast<size_t>(i) * C + c0) = make_float4(s0, s1, s2, s3);
   }

@@ -382,6 +382,16 @@ void Solver<T>::setup(int finest) {
 }
 
 // Every fused or vectorised launch variant at workgroup size 256 (no timing).
+// The FP32 four-cells-per-thread Vanka apply (C a multiple of 4), streaming
+// the inverses on levels with at least kStreamCells cells.
+inline void launch_apply4(hipStream_t s, int C, int bs, const LevelView &v, const float *inv, const float *r,
+                          float *delta) {
+  if (C >= kStreamCells)
+    hipLaunchKernelGGL(k_vanka_apply4<true>, dim3(blocks(C / 4, bs)), dim3(bs), 0, s, v, inv, r, delta);
+  else
+    hipLaunchKernelGGL(k_vanka_apply4<false>, dim3(blocks(C / 4, bs)), dim3(bs), 0, s, v, inv, r, delta);
+}
+
 // The one-thread-per-row SpMV, streaming the operator on levels with at
 // least kStreamCells nodes.
 template <typename T>
@@ -488,8 +498,7 @@ void Solver<T>::autotune() {
         if (L.h.C % 4 == 0) {
           const float t_one_apply = last_t;
           const int bs4a = pick([&](int bs) {
-            hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, bs)), dim3(bs), 0, s, v, o.inv.p, o.r.p,
-                               o.delta.p);
+            launch_apply4(s, L.h.C, bs, v, o.inv.p, o.r.p, o.delta.p);
           });
           if (last_t < t_one_apply) o.bs_apply4 = bs4a;
         }
@@ -501,8 +510,7 @@ void Solver<T>::autotune() {
         launch_spmv<T>(s, L.h.N, bsp, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.r.p);
         if constexpr (std::is_same_v<T, float>) {
           if (bap4 > 0) {
-            hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, bap4)), dim3(bap4), 0, s, v, o.inv.p,
-                               o.r.p, o.delta.p);
+            launch_apply4(s, L.h.C, bap4, v, o.inv.p, o.r.p, o.delta.p);
             return;
           }
         }
@@ -717,8 +725,7 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer
     ProfScope ps(ctx_->prof, s, "vanka_apply", l);
     if constexpr (std::is_same_v<T, float>) {
       if (o.bs_apply4 > 0) {
-        hipLaunchKernelGGL(k_vanka_apply4, dim3(blocks(L.h.C / 4, o.bs_apply4)), dim3(o.bs_apply4), 0, s,
-                           L.view(), o.inv.p, r, o.delta.p);
+        launch_apply4(s, L.h.C, o.bs_apply4, L.view(), o.inv.p, r, o.delta.p);
         LAUNCH_CHECK("k_vanka_apply4");
       }
     }
