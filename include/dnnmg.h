@@ -88,9 +88,9 @@ typedef struct {
                              same); 0: 256 throughout, separate kernels, one
                              thread per row; 2: as 0 with the fused apply
                              (sixteen lanes per cell), four threads per
-                             SpMV row, the fused update + prolongation and
+                             SpMV row, the fused update + prolongation,
                              four cells per thread in the FP32 Vanka apply
-                             on every level;
+                             and the update in cell order on every level;
                              3: as 0 with the single-workgroup bottom cycle  */
   int newton_predictor;   /* 0: Newton starts from x_{n-1}; 1: from the linear
                              extrapolation x_{n-1} + (k_n/k_{n-1})(x_{n-1} -
@@ -405,7 +405,7 @@ int dnnmg_profile_select(dnnmg_ctx *ctx, const char *keys);
 /* Writes "key launches total_ms\n" lines into buf (NUL-terminated, at most
  * len bytes; DNNMG_EINVAL if it does not fit).  Synchronises the stream. */
 int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
-/* Workgroup sizes in use on `level`: block_sizes[0..11] = SpMV, Vanka apply,
+/* Workgroup sizes in use on `level`: block_sizes[0..12] = SpMV, Vanka apply,
  * Vanka update, restriction from `level`, prolongation to `level`, the fused
  * residual + Vanka apply (0: SpMV and apply run separately), the
  * single-workgroup bottom V-cycle (1024 when `level` is part of it, else 0),
@@ -413,8 +413,9 @@ int dnnmg_profile_report(dnnmg_ctx *ctx, char *buf, size_t len);
  * threads per row (0: one thread per row), and the lanes per cell of the
  * fused residual + Vanka apply (4 or 16; 0 when not fused), and the fused
  * last update of the next coarser level + prolongation to `level` (0:
- * separate), and the FP32 Vanka apply with four cells per thread (0: one
- * cell per thread) (12 ints, caller-owned).
+ * separate), the FP32 Vanka apply with four cells per thread (0: one
+ * cell per thread), and the Vanka update over the nodes in cell order (0:
+ * in node order) (13 ints, caller-owned).
  * DNNMG_ESTATE before dnnmg_setup_mesh. */
 int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes);
 /* Storage statistics of a level's operator, for traffic models:

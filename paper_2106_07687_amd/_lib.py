@@ -318,12 +318,13 @@ class Context:
         row; smooth_lanes: lanes per cell of the fused kernel, 0 if not
         fused; update_prolong: the next coarser level's last update fused into
         the prolongation, 0 if separate; vanka_apply4: FP32 apply with four
-        cells per thread, 0 if one)."""
-        out = np.zeros(12, dtype=np.int32)
+        cells per thread, 0 if one; update_ordered: the Vanka update over the
+        nodes in cell order, 0 if in node order)."""
+        out = np.zeros(13, dtype=np.int32)
         self._check(self.lib.dnnmg_launch_config(self.h, level, out.ctypes.data_as(_IP)))
         return dict(zip(("spmv", "vanka_apply", "vanka_update", "restrict", "prolong", "vanka_smooth",
                          "vcycle_small", "restrict_residual", "spmv4", "smooth_lanes", "update_prolong",
-                         "vanka_apply4"),
+                         "vanka_apply4", "update_ordered"),
                         out.tolist()))
 
     def level_stats(self, level):

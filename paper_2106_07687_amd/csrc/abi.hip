@@ -60,6 +60,18 @@ void upload_level(DevLevel &D, hipStream_t s) {
   D.cadj_ptr.upload(h.cadj_ptr, s);
   D.cadj.upload(h.cadj, s);
   D.colour_cells.upload(h.colour_cells, s);
+  {   // nodes in the order of their lowest adjacent cell (ties by id): the
+      // Vanka update's lanes then gather corrections of nearby cells
+    std::vector<int> first(h.N), order(h.N);
+    for (int i = 0; i < h.N; ++i) {
+      int m = h.C;
+      for (int e = h.cadj_ptr[i]; e < h.cadj_ptr[i + 1]; ++e) m = std::min(m, h.cadj[e] >> 2);
+      first[i] = m;
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return first[a] < first[b]; });
+    D.node_order.upload(order, s);
+  }
   D.cslot.upload(h.cslot, s);
   D.padj_ptr.upload(h.padj_ptr, s);
   D.padj.upload(h.padj, s);
@@ -788,6 +800,7 @@ int dnnmg_launch_config(const dnnmg_ctx *ctx, int level, int *block_sizes) {
     block_sizes[9] = o.bs_smooth > 0 ? o.smooth_lanes : 0;
     block_sizes[10] = o.bs_upro;
     block_sizes[11] = o.bs_apply4;
+    block_sizes[12] = o.bs_update_ord;
   };
   if (c.s32)
     fill(*c.s32);

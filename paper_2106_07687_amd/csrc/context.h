@@ -105,6 +105,12 @@ struct DevLevel {
   DevBuf<uint8_t> flag, cslot, pslot, vslot;
   DevBuf<int> cadj_ptr, cadj, padj_ptr, padj, patch_nodes, wq, wx, oq, ox, colq, colx;
   DevBuf<int> colour_cells;            // cells grouped by colour (h.colour_ptr)
+  DevBuf<int> node_order;              // nodes sorted by their lowest adjacent cell (N, or empty)
+  // the node order for node-gather kernels on levels of at least 2^18 nodes
+  // (where it pays), else null: natural order
+  const int *large_order() const {
+    return h.N >= (1 << 18) && node_order.n == static_cast<size_t>(h.N) ? node_order.p : nullptr;
+  }
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
   DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
   DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)
@@ -134,6 +140,7 @@ struct OpLevel {
   int smooth_lanes = 4;   // lanes per cell of the fused kernel: 4 (k_vanka_smooth) or 16 (k_vanka_smooth16)
   int bs_rres = 0;     // > 0: residual + restriction fused (k_restrict_residual)
   int bs_apply4 = 0;   // > 0: FP32 Vanka apply with four cells per thread (k_vanka_apply4)
+  int bs_update_ord = 0;   // > 0: Vanka update over the nodes in cell order (k_vanka_update_ordered)
   int bs_upro = 0;     // > 0: the next coarser level's last update fused into
                        // the prolongation to this level (k_update_prolong_add)
 };

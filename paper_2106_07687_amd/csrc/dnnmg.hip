@@ -208,7 +208,8 @@ void rhs_and_restrict(Net &n, State &st, double dt) {
     double *E = c.cell_vectors(n.F);
     hipLaunchKernelGGL(k_cell_vectors<1>, dim3(blocks(LF.h.C, 256)), dim3(256), 0, s, LF.view(),
                        c.phys(dt, st.t + dt), n.vc.p, nullptr, 0, E);
-    hipLaunchKernelGGL(k_rhs_nodes, dim3(blocks(LF.h.N, 256)), dim3(256), 0, s, LF.view(), E, n.bF.p);
+    hipLaunchKernelGGL(k_rhs_nodes, dim3(blocks(LF.h.N, 256)), dim3(256), 0, s, LF.view(), E, n.bF.p,
+                       LF.large_order());
     check(hipGetLastError(), "rhs");
   }
   const double *src = n.bF.p;

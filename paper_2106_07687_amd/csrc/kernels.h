@@ -301,9 +301,11 @@ __global__ void __launch_bounds__(256) k_lps_vectors(LevelView L, const double *
 __global__ void __launch_bounds__(256) k_residual_nodes(LevelView L, Phys ph, const double *__restrict__ x,
                                                         const double *__restrict__ rhs,
                                                         const double *__restrict__ S,
-                                                        const double *__restrict__ E, double *__restrict__ R) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.N) return;
+                                                        const double *__restrict__ E, double *__restrict__ R,
+                                                        const int *__restrict__ order) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= L.N) return;
+  const int i = order ? order[g] : g;   // nodes in cell order on large levels (as k_vanka_update_ordered)
   double Au = 0.0, Av = 0.0, Ap = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
@@ -335,9 +337,10 @@ __global__ void __launch_bounds__(256) k_residual_nodes(LevelView L, Phys ph, co
 
 // Rhs rows from the element vectors of k_cell_vectors<1>; pressure rows 0.
 __global__ void __launch_bounds__(256) k_rhs_nodes(LevelView L, const double *__restrict__ E,
-                                                   double *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.N) return;
+                                                   double *__restrict__ out, const int *__restrict__ order) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= L.N) return;
+  const int i = order ? order[g] : g;   // nodes in cell order on large levels
   double fu = 0.0, fv = 0.0;
   for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
     const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
@@ -1008,6 +1011,20 @@ __global__ void __launch_bounds__(256) k_vanka_update(LevelView L, const T *__re
                                                       int set) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < L.N) update_item(L, delta, omega, x, i, set != 0);
+}
+
+// The same over the nodes in the order `order` (a permutation of the nodes,
+// sorted by their lowest adjacent cell): the refinement numbers the coarse
+// vertices, edge midpoints and centres in separate ranges, so consecutive
+// node ids lie far apart, while consecutive cells are neighbours; in cell
+// order a wavefront gathers the corrections of nearby cells.  Each node's
+// update is update_item's.
+template <typename T>
+__global__ void __launch_bounds__(256) k_vanka_update_ordered(LevelView L, const int *__restrict__ order,
+                                                              const T *__restrict__ delta, T omega,
+                                                              T *__restrict__ x, int set) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < L.N) update_item(L, delta, omega, x, order[g], set != 0);
 }
 
 // -------------------------------------------------------------- transfers

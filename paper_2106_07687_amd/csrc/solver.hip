@@ -244,7 +244,7 @@ void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, 
                      phys(dt, t_new), x, xo, rhs ? 0 : 1, E);
   hipLaunchKernelGGL(k_lps_vectors, dim3(blocks(L.h.NP, 256)), dim3(256), 0, stream, L.view(), L.sP.p, x, S);
   hipLaunchKernelGGL(k_residual_nodes, dim3(blocks(L.h.N, 256)), dim3(256), 0, stream, L.view(),
-                     phys(dt, t_new), x, rhs, S, E, Rout);
+                     phys(dt, t_new), x, rhs, S, E, Rout, L.large_order());
   LAUNCH_CHECK("residual");
 }
 
@@ -423,6 +423,7 @@ void Solver<T>::fuse_all() {
     o.bs_spmv4 = 256;
     o.bs_upro = static_cast<int>(l) - 1 > c_ ? 256 : 0;
     o.bs_apply4 = ctx_->levels[l]->h.C % 4 == 0 ? 256 : 0;
+    o.bs_update_ord = ctx_->levels[l]->node_order.n == static_cast<size_t>(ctx_->levels[l]->h.N) ? 256 : 0;
   }
 }
 
@@ -538,6 +539,16 @@ void Solver<T>::autotune() {
         hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v, o.delta.p, omega,
                            o.t.p, 0);
       });
+      // the nodes in cell order: kept if faster
+      o.bs_update_ord = 0;
+      if (L.node_order.n == static_cast<size_t>(L.h.N)) {
+        const float t_nat = last_t;
+        const int bso = pick([&](int bs) {
+          hipLaunchKernelGGL(k_vanka_update_ordered<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, v,
+                             L.node_order.p, o.delta.p, omega, o.t.p, 0);
+        });
+        if (last_t < t_nat) o.bs_update_ord = bso;
+      }
       DevLevel &Cl = *ctx_->levels[l - 1];
       OpLevel<T> &oc = ops_[l - 1];
       TransferView tv{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
@@ -734,8 +745,13 @@ void Solver<T>::vanka_sweep(int l, T *x, const T *b, bool zero_start, bool defer
   }
   if (!defer_update) {
     ProfScope ps(ctx_->prof, s, "vanka_update", l);
-    hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, o.bs_update)), dim3(o.bs_update), 0, s, L.view(),
-                       o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x, zero_start ? 1 : 0);
+    if (o.bs_update_ord > 0 && L.node_order.n == static_cast<size_t>(L.h.N))
+      hipLaunchKernelGGL(k_vanka_update_ordered<T>, dim3(blocks(L.h.N, o.bs_update_ord)), dim3(o.bs_update_ord),
+                         0, s, L.view(), L.node_order.p, o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x,
+                         zero_start ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_vanka_update<T>, dim3(blocks(L.h.N, o.bs_update)), dim3(o.bs_update), 0, s, L.view(),
+                         o.delta.p, static_cast<T>(ctx_->prm.vanka_omega), x, zero_start ? 1 : 0);
   }
   LAUNCH_CHECK("vanka");
 }

@@ -148,6 +148,7 @@ def test_fused_residual_and_apply_is_bitwise_equal():
     assert [ctxs[0].launch_config(l)["update_prolong"] for l in range(LEVEL + 1)] == [0, 0] + [256] * (LEVEL - 1)
     assert all(ctxs[1].launch_config(l)["update_prolong"] == 0 for l in range(LEVEL + 1))
     assert all(ctxs[0].launch_config(l)["vanka_apply4"] == 256 for l in range(1, LEVEL + 1))
+    assert all(ctxs[0].launch_config(l)["update_ordered"] == 256 for l in range(LEVEL + 1))
     lev = mesh.hierarchy(macro, LEVEL)
     x = random_state(lev[LEVEL].n_nodes, 5) * 0.3
     sts = []
