@@ -56,11 +56,15 @@ struct DevBuf {
       throw DnnmgError{DNNMG_ENOMEM, "hipMalloc failed"};
     n = count;
   }
+  // Setup-time copy from a host vector, complete on return: callers pass
+  // locals and temporaries, which must not be read by a copy still queued
+  // after they are freed.
   void upload(const std::vector<T> &h, hipStream_t s) {
     alloc(h.size());
-    if (!h.empty() &&
-        hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (h.empty()) return;
+    if (hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
       throw DnnmgError{DNNMG_EDEVICE, "hipMemcpyAsync H2D failed"};
+    if (hipStreamSynchronize(s) != hipSuccess) throw DnnmgError{DNNMG_EDEVICE, "upload: stream synchronisation failed"};
   }
 };
 
