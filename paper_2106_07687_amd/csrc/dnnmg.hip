@@ -218,7 +218,8 @@ void rhs_and_restrict(Net &n, State &st, double dt) {
     DevLevel &Cl = *c.levels[l - 1];
     TransferView tv{Fl.h.Nc, Fl.h.Ec, Fl.h.N, Fl.edge_ends.p, Cl.cells.p, Fl.rptr.p, Fl.ridx.p, Cl.flag.p};
     double *dst = (l - 1 == n.L) ? st.pending_rhs.p : n.rchain[l - 1 - n.L].p;
-    hipLaunchKernelGGL(k_restrict<double>, dim3(blocks(Fl.h.Nc, 256)), dim3(256), 0, s, tv, src, dst);
+    hipLaunchKernelGGL(k_restrict<double>, dim3(blocks(Fl.h.Nc, 256)), dim3(256), 0, s, tv, src, dst,
+                       Cl.large_order());
     src = dst;
   }
   check(hipGetLastError(), "restrict chain");

@@ -1120,10 +1120,14 @@ __device__ __forceinline__ void restrict_item(const TransferView &tv, const T *_
   rc[3 * j + 2] = a2;
 }
 
+// order: the coarse nodes in cell order (large levels, as for the Vanka
+// update: the fine centres and edge midpoints a coarse node gathers are then
+// close to those of its neighbours in the wavefront), or null.
 template <typename T>
-__global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < tv.Nc) restrict_item(tv, rf, rc, j);
+__global__ void k_restrict(TransferView tv, const T *__restrict__ rf, T *__restrict__ rc,
+                           const int *__restrict__ order) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < tv.Nc) restrict_item(tv, rf, rc, order ? order[g] : g);
 }
 
 // r_coarse = P^T (b - J x) without storing the fine residual: each coarse

@@ -553,7 +553,8 @@ void Solver<T>::autotune() {
       OpLevel<T> &oc = ops_[l - 1];
       TransferView tv{L.h.Nc, L.h.Ec, L.h.N, L.edge_ends.p, Cl.cells.p, L.rptr.p, L.ridx.p, Cl.flag.p};
       o.bs_restrict = pick([&](int bs) {
-        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bs)), dim3(bs), 0, s, tv, o.r.p, oc.t.p);
+        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bs)), dim3(bs), 0, s, tv, o.r.p, oc.t.p,
+                           Cl.large_order());
       });
       o.bs_prolong = pick([&](int bs) {
         hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks(L.h.N, bs)), dim3(bs), 0, s, tv, oc.x.p, o.t.p);
@@ -579,7 +580,8 @@ void Solver<T>::autotune() {
       const int bsr = o.bs_restrict;
       pick([&](int) {
         launch_spmv<T>(s, L.h.N, bsp, v, o.JQ.p, o.JX.p, o.x.p, o.b.p, o.r.p);
-        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bsr)), dim3(bsr), 0, s, tv, o.r.p, oc.t.p);
+        hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(L.h.Nc, bsr)), dim3(bsr), 0, s, tv, o.r.p, oc.t.p,
+                           Cl.large_order());
       });
       const float t_sep2 = last_t;
       const int bsrr = pick([&](int bs) {
@@ -776,7 +778,7 @@ void Solver<T>::restrict_to(int l, const T *rf, T *rc) {
   ProfScope ps(ctx_->prof, ctx_->stream, "restrict", l);
   const int bs = ops_[l].bs_restrict;
   hipLaunchKernelGGL(k_restrict<T>, dim3(blocks(F.h.Nc, bs)), dim3(bs), 0, ctx_->stream, tv, rf,
-                     rc);
+                     rc, Cl.large_order());
   LAUNCH_CHECK("k_restrict");
 }
 
