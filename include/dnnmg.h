@@ -50,14 +50,18 @@ typedef struct dnnmg_batch dnnmg_batch;
 
 /* Solver parameters.  Defaults (dnnmg_params_default) follow the readings of
  * the paper's unstated constants: theta = 1/2 (Crank-Nicolson, Sec. 2.1),
- * LPS parameter alpha_T = alpha0 / (nu / h_T^2 + 1/k) with alpha0 = 0.5,
+ * LPS parameter alpha_T = alpha0 Re h_T^2 (Sec. 2.1; Re = 1/nu, h_T^2 the
+ * cell area) with alpha0 = 0.5 on the level whose discrete problem is solved
+ * (and in every residual); the re-discretised coarser levels of its multigrid
+ * preconditioner use alpha0 / (nu / h_T^2 + 1/k), which changes how fast the
+ * linear solves converge, not the solution,
  * Newton with full steps and absolute tolerance 1e-10 on the l2 norm of the
  * nonlinear residual, started from the linear extrapolation of the last two
  * states, GMRES(30) with relative tolerance 1e-2 and at most 100 iterations,
  * V(2,2) cycles with additive cell-Vanka (omega = 0.6); graphs, autotuning. */
 typedef struct {
   double nu;              /* kinematic viscosity (the paper's 1/Re)              */
-  double alpha0;          /* LPS scale                                           */
+  double alpha0;          /* LPS scale alpha0 of alpha_T = alpha0 h_T^2 / nu      */
   double theta;           /* time-stepping weight, 0.5 = Crank-Nicolson          */
   double u_mean;          /* mean inflow velocity of the parabolic profile       */
   double channel_h;       /* channel height H of the inflow profile              */
@@ -201,6 +205,10 @@ int dnnmg_state_create(dnnmg_ctx *ctx, int level, dnnmg_state **out);
 int dnnmg_state_destroy(dnnmg_state *s);
 int dnnmg_state_set(dnnmg_state *s, const double *uvp, double t);
 int dnnmg_state_get(const dnnmg_state *s, double *uvp, double *t);
+/* Device-to-device copy of the state's vector (3 doubles per node) into
+ * caller-owned device memory, enqueued on the context's stream (no
+ * synchronisation; the copy is ordered before later work on that stream). */
+int dnnmg_state_get_dev(const dnnmg_state *s, double *uvp_dev);
 /* Device address of the state's vector (owned by the state). */
 int dnnmg_state_device_ptr(dnnmg_state *s, double **uvp_dev);
 
@@ -216,7 +224,8 @@ int dnnmg_step(dnnmg_ctx *ctx, dnnmg_state *s, double dt, dnnmg_step_stats *stat
 /* Assembles the Jacobian A'(x) (eq. newton) on levels 0..level at the state
  * x (injected to coarser levels: their nodes are a prefix of the fine
  * numbering), factorises the Vanka blocks and the level-0 LU.  dt enters
- * through the mass term 1/k and alpha_T. */
+ * through the mass term 1/k and the bounded alpha_T of the levels below
+ * `level`. */
 int dnnmg_linearize(dnnmg_ctx *ctx, const dnnmg_state *s, int level, double dt);
 /* Solves A'(x) w = rhs on `level` with the operators of the last
  * dnnmg_linearize by GMRES + V-cycle; host in/out, 3 doubles per node. */
@@ -308,6 +317,14 @@ typedef struct {
 int dnnmg_correct(dnnmg_ctx *ctx, dnnmg_state *coarse, dnnmg_net *net, double dt,
                   dnnmg_correct_out *dbg);
 
+/* Device address (owned by the net) of the fine-level state the next
+ * correction starts from: after dnnmg_correct the corrected velocity
+ * v~ + d of Algorithm 1 (3 doubles per fine node, pressure entries 0), after
+ * dnnmg_rhs_from_fine the given fine velocity, after dnnmg_net_reset P^m x.
+ * Valid until the next call that changes it.  DNNMG_ESTATE before the first
+ * dnnmg_net_reset. */
+int dnnmg_net_fine_velocity(dnnmg_net *net, const double **v_dev);
+
 /* The Rhs and restriction of Algorithm 1 for a given fine velocity (teacher forcing when
  * generating training data from fine solutions): b^F = Rhs(v_fine) on level
  * F, b^L = (P^m)^T b^F stored as the coarse state's pending right-hand side,
@@ -356,6 +373,19 @@ int dnnmg_functionals(dnnmg_ctx *ctx, const dnnmg_state *s, double *jdiv, double
 /* The same for a host state vector (3 N doubles, node-interleaved) on level. */
 int dnnmg_functionals_host(dnnmg_ctx *ctx, int level, const double *uvp, double *jdiv, double *drag,
                            double *lift, int n_obstacles);
+
+/* Velocity error of a nodal field against a reference (Sec. 3.4: relative
+ * errors of the velocity against the fine solution).  x_dev: 3 doubles per
+ * node on `level`, prolongated bilinearly to ref_level when coarser (the Q1
+ * field itself; level <= ref_level); ref_dev: 3 doubles per node on
+ * ref_level.  Both device pointers (e.g. dnnmg_state_device_ptr,
+ * dnnmg_net_fine_velocity), borrowed for the call.  out[4] (host) receives
+ * the squared norms int |v - v_ref|^2 dx and int |v_ref|^2 dx (2x2 Gauss per
+ * cell, the mass-weighted L2 norm of the Q1 fields) and the nodal sums
+ * sum_i |v_i - v_ref,i|^2 and sum_i |v_ref,i|^2.  Pressure is ignored.  FP64;
+ * synchronises the stream. */
+int dnnmg_velocity_error(dnnmg_ctx *ctx, int level, const double *x_dev, int ref_level, const double *ref_dev,
+                         double *out);
 
 /* ------------------------------------------------------------------ batches
  * Many independent simulations of the plain method (Sec. 2: each one the

@@ -20,11 +20,12 @@ The Jacobian A_n'(x) (eq. newton) is the analytic linearisation.
 Readings (paper silent or garbled): G1 Q1/Q1 elements, 3 unknowns per vertex;
 G2 p trial / xi test; G3 two-level projection: on each patch of 2x2 sibling
 cells pi is bilinear interpolation from the 4 patch corners in the parent's
-reference coordinates; G4 alpha_T = alpha0 / (nu / h_T^2 + 1/k) with
-h_T^2 = area(T) and alpha0 = 0.5: the paper's alpha0 * Re * h_T^2 (Re read as
-1/nu) wherever h_T^2 / nu << k, bounded by alpha0 * k on coarse cells (with the
-unbounded form the multigrid preconditioner of Sec. 2.2 fails to converge);
-G6 theta = 1/2, pressure fully implicit; G7 inflow U(y,t) = 6 s(t) y (H - y) / H^2
+reference coordinates; G4 alpha_T = alpha0 * Re * h_T^2 as in Sec. 2.1, with
+Re read as 1/nu, h_T^2 = area(T) and the free constant alpha0 = 0.5
+(`lps_mode="paper"`, the default).  The re-discretised coarse operators of the
+multigrid preconditioner (solver.MGHierarchy) use the bounded form
+alpha0 / (nu / h_T^2 + 1/k) (`lps_mode="bounded"`); they do not change the
+discrete solution, only how fast the linear solves converge; G6 theta = 1/2, pressure fully implicit; G7 inflow U(y,t) = 6 s(t) y (H - y) / H^2
 with ramp s(t) = (1 - cos(pi t)) / 2 for t < 1, else 1, no-slip walls and
 obstacle, do-nothing outflow (no boundary term); G8 2x2 Gauss quadrature.
 
@@ -34,7 +35,7 @@ Jacobian.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 from typing import Callable, Optional
 
 import numpy as np
@@ -77,7 +78,7 @@ class Problem:
     alpha0: float = 0.5
     H: float = CHANNEL_H
     u_mean: float = 1.0
-    lps_mode: str = "dt"                    # "dt": alpha0/(nu/h^2 + 1/k); "paper": alpha0 h^2/nu
+    lps_mode: str = "paper"                 # "paper": alpha0 h^2/nu; "bounded": alpha0/(nu/h^2 + 1/k)
     force: Optional[Callable] = None        # f(x, y, t) -> (fx, fy)
     dirichlet: Optional[Callable] = None    # g(x, y, t) -> (u, v) on Dirichlet nodes
 
@@ -130,13 +131,22 @@ def geometry(xy, cells):
 
 
 def lps_alpha(prob: "Problem", area):
-    """alpha_T per cell (reading G4): alpha0 / (nu / h_T^2 + 1 / k) with
-    h_T^2 = area(T).  On cells with h_T^2 / nu << k this is the paper's
-    alpha0 * Re * h_T^2 (Re = 1/nu); the time-step term bounds it by alpha0 * k
-    on coarse cells.  `prob.lps_mode == "paper"` selects alpha0 * h_T^2 / nu."""
+    """alpha_T per cell with h_T^2 = area(T) (Sec. 2.1, reading G4).
+    "paper": alpha0 * Re * h_T^2 = alpha0 * h_T^2 / nu, the stabilisation of
+    the discrete problem.  "bounded": alpha0 / (nu / h_T^2 + 1/k), which equals
+    the paper's value where h_T^2 / nu << k and is at most alpha0 * k; used
+    only for the coarse operators of the multigrid preconditioner."""
     if prob.lps_mode == "paper":
         return prob.alpha0 * area / prob.nu
-    return prob.alpha0 / (prob.nu / area + prob.inv_dt)
+    if prob.lps_mode == "bounded":
+        return prob.alpha0 / (prob.nu / area + prob.inv_dt)
+    raise ValueError(f"unknown lps_mode {prob.lps_mode!r}")
+
+
+def coarse_operator_problem(prob: "Problem") -> "Problem":
+    """The problem whose Jacobian a multigrid preconditioner re-discretises on
+    the levels below the one it solves on: the bounded LPS parameter."""
+    return replace(prob, lps_mode="bounded")
 
 
 def _lps_patch_matrices(level: Level, prob: Problem, det, grad):

@@ -118,7 +118,9 @@ def vanka_sweep_coloured(J, blocks, cells, colours, x, b, omega=0.6):
 class MGHierarchy:
     """Operators of all levels at one linearisation point (the fine iterate
     injected to each level: coarse vertices keep their ids, so injection is
-    the prefix of the fine vector)."""
+    the prefix of the fine vector).  The finest level carries the Jacobian of
+    the problem being solved; the levels below it are re-discretised with the
+    bounded LPS parameter (fem.coarse_operator_problem, reading G4)."""
 
     def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0,
                  coarse=0):
@@ -131,9 +133,10 @@ class MGHierarchy:
         self.colours = [cell_colours(L.cells) for L in levels] if smoother == "coloured" else None
         self.J = []
         self.blocks = []
-        for L in levels:
+        cprob = fem.coarse_operator_problem(prob)
+        for l, L in enumerate(levels):
             xl = x_fine[:3 * L.n_nodes]
-            Jl = fem.jacobian(L, prob, xl)
+            Jl = fem.jacobian(L, prob if l == len(levels) - 1 else cprob, xl)
             self.J.append(Jl)
             self.blocks.append(cell_blocks(Jl, L.cells))
         self.P = [None] + [levels[l].prolongation() for l in range(1, len(levels))]

@@ -88,6 +88,7 @@ _SIGS = {
     "dnnmg_state_set": (C.c_int, [_P, _DP, C.c_double]),
     "dnnmg_state_get": (C.c_int, [_P, _DP, _DP]),
     "dnnmg_state_device_ptr": (C.c_int, [_P, C.POINTER(_P)]),
+    "dnnmg_state_get_dev": (C.c_int, [_P, _P]),
     "dnnmg_step": (C.c_int, [_P, _P, C.c_double, C.POINTER(StepStats)]),
     "dnnmg_linearize": (C.c_int, [_P, _P, C.c_int, C.c_double]),
     "dnnmg_solve": (C.c_int, [_P, C.c_int, _DP, _DP, C.POINTER(SolveStats)]),
@@ -119,6 +120,8 @@ _SIGS = {
     "dnnmg_launch_config": (C.c_int, [_P, C.c_int, _IP]),
     "dnnmg_functionals": (C.c_int, [_P, _P, _DP, _DP, _DP, C.c_int]),
     "dnnmg_functionals_host": (C.c_int, [_P, C.c_int, _DP, _DP, _DP, _DP, C.c_int]),
+    "dnnmg_velocity_error": (C.c_int, [_P, C.c_int, _P, C.c_int, _P, _DP]),
+    "dnnmg_net_fine_velocity": (C.c_int, [_P, C.POINTER(_P)]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
@@ -309,6 +312,15 @@ class Context:
                                                     n_obstacles))
         return float(j[0]), d[:n_obstacles], l[:n_obstacles]
 
+    def velocity_error(self, level, x_ptr, ref_level, ref_ptr):
+        """Squared velocity norms {"l2_err2", "l2_ref2", "nodal_err2",
+        "nodal_ref2"} of the device field at x_ptr on `level` (prolongated to
+        ref_level) against the device field at ref_ptr (mass-weighted L2 and
+        nodal sums)."""
+        out = np.zeros(4)
+        self._check(self.lib.dnnmg_velocity_error(self.h, level, x_ptr, ref_level, ref_ptr, _dp(out)))
+        return dict(zip(("l2_err2", "l2_ref2", "nodal_err2", "nodal_ref2"), (float(v) for v in out)))
+
     def launch_config(self, level):
         """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong,
         vanka_smooth, vcycle_small, restrict_residual, spmv4} (vanka_smooth 0:
@@ -434,6 +446,13 @@ class Net:
         self.ctx._check(self.ctx.lib.dnnmg_net_forward(self.h, _fp(X), _fp(Y)))
         return Y
 
+    def fine_velocity_ptr(self):
+        """Device address of the fine state the next correction starts from
+        (the corrected velocity after correct())."""
+        p = _P()
+        self.ctx._check(self.ctx.lib.dnnmg_net_fine_velocity(self.h, C.byref(p)))
+        return p.value
+
     def rhs_from_fine(self, state, v_fine, dt):
         v = _f64(v_fine)
         self.ctx._check(self.ctx.lib.dnnmg_rhs_from_fine(self.ctx.h, state.h, self.h, _dp(v), dt))
@@ -518,6 +537,11 @@ class State:
         self.ctx._check(self.ctx.lib.dnnmg_functionals(self.ctx.h, self.h, _dp(j), _dp(d), _dp(l),
                                                        n_obstacles))
         return float(j[0]), d[:n_obstacles], l[:n_obstacles]
+
+    def get_dev(self, dst_ptr):
+        """Device-to-device copy of the state vector to dst_ptr (e.g. a torch
+        tensor's data_ptr()), ordered on the context's stream."""
+        self.ctx._check(self.ctx.lib.dnnmg_state_get_dev(self.h, dst_ptr))
 
     def device_ptr(self):
         p = _P()

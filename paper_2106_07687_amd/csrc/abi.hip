@@ -510,6 +510,17 @@ int dnnmg_state_get(const dnnmg_state *s, double *uvp, double *t) {
   });
 }
 
+int dnnmg_state_get_dev(const dnnmg_state *s, double *uvp_dev) {
+  if (!s || !uvp_dev) return DNNMG_EINVAL;
+  dnnmg_ctx *ctx = s->impl.ctx->owner;
+  return guarded(ctx, [&]() {
+    Ctx &c = *s->impl.ctx;
+    check(hipMemcpyAsync(uvp_dev, s->impl.x.p, sizeof(double) * s->impl.x.n, hipMemcpyDeviceToDevice, c.stream),
+          "state D2D");
+    return DNNMG_OK;
+  });
+}
+
 int dnnmg_state_device_ptr(dnnmg_state *s, double **p) {
   if (!s || !p) return DNNMG_EINVAL;
   *p = s->impl.x.p;
@@ -777,6 +788,18 @@ int dnnmg_functionals_host(dnnmg_ctx *ctx, int level, const double *uvp, double 
     xd.alloc(n);
     check(hipMemcpyAsync(xd.p, uvp, n * sizeof(double), hipMemcpyHostToDevice, c.stream), "H2D");
     c.functionals(level, xd.p, jdiv, drag, lift);
+    return DNNMG_OK;
+  });
+}
+
+int dnnmg_velocity_error(dnnmg_ctx *ctx, int level, const double *x_dev, int ref_level, const double *ref_dev,
+                         double *out) {
+  const int e = check_level(ctx, ref_level);
+  if (e) return e;
+  if (level < 0 || level > ref_level || !x_dev || !ref_dev || !out)
+    return fail(ctx, DNNMG_EINVAL, "velocity_error: need 0 <= level <= ref_level and non-null pointers");
+  return guarded(ctx, [&]() {
+    ctx->impl.velocity_error(level, x_dev, ref_level, ref_dev, out);
     return DNNMG_OK;
   });
 }

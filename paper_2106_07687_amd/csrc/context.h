@@ -116,7 +116,13 @@ struct DevLevel {
     return h.N >= (1 << 18) && node_order.n == static_cast<size_t>(h.N) ? node_order.p : nullptr;
   }
   DevBuf<int> edge_ends, rptr, ridx;   // transfer from the coarser level
-  DevBuf<double> sP;                   // LPS patch matrices (81 per patch)
+  // LPS patch matrices (81 per patch) in two roles: [0] the level's own
+  // discrete problem (alpha0 h_T^2 / nu), [1] the level as a coarse level of a
+  // finer level's multigrid preconditioner (alpha0 / (nu / h_T^2 + 1/k))
+  struct LpsCache {
+    DevBuf<double> m;
+    double dt = -1.0, nu = -1.0, alpha0 = -1.0;
+  } lps[2];
   DevBuf<double> nnu;                  // per-node viscosity (batches only; else empty)
   // obstacle boundary edges (cell, side) grouped by obstacle (ptr CSR), built
   // on the first functional evaluation of the level
@@ -127,7 +133,6 @@ struct DevLevel {
   // reductions (starts/lengths in unknowns, grouped by simulation: seg_ptr)
   int nseg = 1, nchunk = 0;
   DevBuf<int> segn, cstart, clen, seg_ptr;
-  double sP_dt = -1.0, sP_nu = -1.0, sP_alpha0 = -1.0;
   LevelView view() const;
 };
 
@@ -313,7 +318,10 @@ class Ctx {
     p.t = t;
     return p;
   }
-  void ensure_lps(int l, double dt);
+  // LPS patch matrices of level l in the given role (0: the level's own
+  // problem, 1: coarse operator of a finer level's preconditioner), built on
+  // first use and when nu, alpha0 or (role 1) the time step change
+  const double *ensure_lps(int l, double dt, int role);
   double norm2_f64(const double *x, int n);   // ||x||_2, synchronising
   // largest per-simulation ||x||_2 on a batch level (= ||x||_2 otherwise)
   double norm2_max_seg(int l, const double *x);
@@ -324,6 +332,11 @@ class Ctx {
   void functionals(int l, const double *x, double *jdiv, double *drag, double *lift);
   void residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                 double dt, double *R);
+  // Velocity error of x on level l (prolongated to ref_level if coarser)
+  // against ref on ref_level: out = {int |v - v_ref|^2, int |v_ref|^2,
+  // sum_i |v_i - v_ref,i|^2, sum_i |v_ref,i|^2} (synchronising)
+  void velocity_error(int l, const double *x, int ref_level, const double *ref, double out[4]);
+  DevBuf<double> verr_a, verr_b;   // prolongation chain of velocity_error
 };
 
 struct State {

@@ -204,7 +204,6 @@ void rhs_and_restrict(Net &n, State &st, double dt) {
   const DevLevel &LF = *c.levels[n.F];
   {
     ProfScope ps(c.prof, s, "dnnmg_rhs", n.F);
-    c.ensure_lps(n.F, dt);
     double *E = c.cell_vectors(n.F);
     hipLaunchKernelGGL(k_cell_vectors<1>, dim3(blocks(LF.h.C, 256)), dim3(256), 0, s, LF.view(),
                        c.phys(dt, st.t + dt), n.vc.p, nullptr, 0, E);
@@ -256,6 +255,17 @@ int dnnmg_net_targets(dnnmg_ctx *ctx, const dnnmg_state *coarse, dnnmg_net *net,
     c.last_error = e.msg;
     return e.code;
   }
+  return DNNMG_OK;
+}
+
+int dnnmg_net_fine_velocity(dnnmg_net *net, const double **v_dev) {
+  if (!net || !v_dev) return DNNMG_EINVAL;
+  Net &n = net->impl;
+  if (!n.has_vprev) {
+    n.ctx->last_error = "no corrected fine velocity yet (dnnmg_net_reset first)";
+    return DNNMG_ESTATE;
+  }
+  *v_dev = n.vprev.p;
   return DNNMG_OK;
 }
 

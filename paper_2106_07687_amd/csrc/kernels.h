@@ -117,8 +117,12 @@ __device__ __constant__ double kK[9][9] = {
 __device__ __constant__ int kChildToPatch[4][4] = {{0, 1, 4, 3}, {1, 2, 5, 4}, {4, 5, 8, 7}, {3, 4, 7, 6}};
 
 // Patch matrix s_P = K^T (sum_T alpha_T S_T) K of the LPS term, one thread per
-// patch, stored SoA: sP[(9 q + m) * NP + P].
-__global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *__restrict__ sP) {
+// patch, stored SoA: sP[(9 q + m) * NP + P].  alpha_T (Sec. 2.1, h_T^2 =
+// area(T), Re = 1/nu): bounded = 0 gives the paper's alpha0 Re h_T^2, the
+// stabilisation of the level's own discrete problem; bounded = 1 gives
+// alpha0 / (nu / h_T^2 + 1/k), used only for the re-discretised operators a
+// finer level's multigrid preconditioner solves with on this level.
+__global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, int bounded, double *__restrict__ sP) {
   const int P = blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= L.NP) return;
   const double nu = L.nnu ? L.nnu[L.cells[4 * P].x] : ph.nu;
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(64) k_lps_patch(LevelView L, Phys ph, double *
 #pragma unroll
         for (int b = 0; b < 4; ++b) St[a][b] += det * (gx[a] * gx[b] + gy[a] * gy[b]);
     }
-    const double alpha = ph.alpha0 / (nu / area + ph.inv_dt);
+    const double alpha = bounded ? ph.alpha0 / (nu / area + ph.inv_dt) : ph.alpha0 * area / nu;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1707,6 +1711,65 @@ __global__ void __launch_bounds__(256) k_jdiv_partial(LevelView L, const double 
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Velocity error of a field a against a reference b on one level (Sec. 3.4:
+// relative errors of the velocity against the fine solution), partial sums per
+// workgroup: partial[4 w + 0] = int |v_a - v_b|^2, [1] = int |v_b|^2 (2x2 Gauss
+// per cell, the Q1 fields of the nodal values), [2] = sum_i |v_a,i - v_b,i|^2,
+// [3] = sum_i |v_b,i|^2 over the nodes.  Thread i covers cell i and node i.
+__global__ void __launch_bounds__(256) k_vel_error_partial(LevelView L, const double *__restrict__ a,
+                                                           const double *__restrict__ b,
+                                                           double *__restrict__ partial) {
+  __shared__ double sh[4][256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < L.C) {
+    const int4 cn = L.cells[i];
+    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+    double X[4], Y[4], DU[4], DV[4], BU[4], BV[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 p = L.xy[nn[k]];
+      X[k] = p.x;
+      Y[k] = p.y;
+      BU[k] = b[3 * nn[k]];
+      BV[k] = b[3 * nn[k] + 1];
+      DU[k] = a[3 * nn[k]] - BU[k];
+      DV[k] = a[3 * nn[k] + 1] - BV[k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double N[4], gx[4], gy[4], det;
+      q1_point(X, Y, q, N, gx, gy, det);
+      double du = 0.0, dv = 0.0, bu = 0.0, bv = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        du += N[k] * DU[k];
+        dv += N[k] * DV[k];
+        bu += N[k] * BU[k];
+        bv += N[k] * BV[k];
+      }
+      s[0] += det * (du * du + dv * dv);
+      s[1] += det * (bu * bu + bv * bv);
+    }
+  }
+  if (i < L.N) {
+    const double bu = b[3 * i], bv = b[3 * i + 1];
+    const double du = a[3 * i] - bu, dv = a[3 * i + 1] - bv;
+    s[2] = du * du + dv * dv;
+    s[3] = bu * bu + bv * bv;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Drag and lift contributions of each obstacle edge (Sec. 3.3):

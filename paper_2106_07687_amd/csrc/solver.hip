@@ -127,16 +127,19 @@ Ctx::~Ctx() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
-void Ctx::ensure_lps(int l, double dt) {
+const double *Ctx::ensure_lps(int l, double dt, int role) {
   DevLevel &L = *levels[l];
-  if (L.sP.p && L.sP_dt == dt && L.sP_nu == prm.nu && L.sP_alpha0 == prm.alpha0) return;
-  if (!L.sP.p) L.sP.alloc(static_cast<size_t>(81) * L.h.NP);
-  hipLaunchKernelGGL(k_lps_patch, dim3(blocks(L.h.NP, 64)), dim3(64), 0, stream, L.view(),
-                     phys(dt, 0.0), L.sP.p);
+  DevLevel::LpsCache &c = L.lps[role ? 1 : 0];
+  const double key_dt = role ? dt : 0.0;   // the paper's alpha_T does not depend on k
+  if (c.m.p && c.dt == key_dt && c.nu == prm.nu && c.alpha0 == prm.alpha0) return c.m.p;
+  if (!c.m.p) c.m.alloc(static_cast<size_t>(81) * L.h.NP);
+  hipLaunchKernelGGL(k_lps_patch, dim3(blocks(L.h.NP, 64)), dim3(64), 0, stream, L.view(), phys(dt, 0.0),
+                     role ? 1 : 0, c.m.p);
   LAUNCH_CHECK("k_lps_patch");
-  L.sP_dt = dt;
-  L.sP_nu = prm.nu;
-  L.sP_alpha0 = prm.alpha0;
+  c.dt = key_dt;
+  c.nu = prm.nu;
+  c.alpha0 = prm.alpha0;
+  return c.m.p;
 }
 
 double Ctx::norm2_f64(const double *x, int n) {
@@ -233,16 +236,46 @@ void Ctx::functionals(int l, const double *x, double *jdiv, double *drag, double
   }
 }
 
+void Ctx::velocity_error(int l, const double *x, int ref_level, const double *ref, double out[4]) {
+  DevLevel &R = *levels[ref_level];
+  const size_t nr = 3 * static_cast<size_t>(R.h.N);
+  const double *a = x;
+  if (l < ref_level) {   // bilinear prolongation level by level (FP64)
+    if (verr_a.n < nr) verr_a.alloc(nr);
+    if (verr_b.n < nr) verr_b.alloc(nr);
+    double *bufs[2] = {verr_a.p, verr_b.p};
+    for (int k = l + 1; k <= ref_level; ++k) {
+      DevLevel &Fl = *levels[k];
+      DevLevel &Cl = *levels[k - 1];
+      TransferView tv{Fl.h.Nc, Fl.h.Ec, Fl.h.N, Fl.edge_ends.p, Cl.cells.p, Fl.rptr.p, Fl.ridx.p, Cl.flag.p};
+      double *dst = bufs[k & 1];
+      const size_t nf = 3 * static_cast<size_t>(Fl.h.N);
+      hipLaunchKernelGGL(k_fill<double>, dim3(std::min(blocks(nf, 256), 1024)), dim3(256), 0, stream, dst, nf,
+                         0.0);
+      hipLaunchKernelGGL(k_prolong_add<double>, dim3(blocks(Fl.h.N, 256)), dim3(256), 0, stream, tv, a, dst);
+      a = dst;
+    }
+  }
+  const int nb = blocks(std::max(R.h.C, R.h.N), 256);
+  if (red_partial.n < 4 * static_cast<size_t>(nb)) red_partial.alloc(4 * static_cast<size_t>(nb));
+  if (!red_out.p) red_out.alloc(64);
+  hipLaunchKernelGGL(k_vel_error_partial, dim3(nb), dim3(256), 0, stream, R.view(), a, ref, red_partial.p);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(4), dim3(256), 0, stream, nb, 4, red_partial.p, red_out.p);
+  LAUNCH_CHECK("velocity error");
+  check(hipMemcpyAsync(out, red_out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, stream), "D2H");
+  check(hipStreamSynchronize(stream), "velocity error sync");
+}
+
 void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, double t_new,
                    double dt, double *Rout) {
-  ensure_lps(l, dt);
+  const double *sP = ensure_lps(l, dt, 0);
   DevLevel &L = *levels[l];
   double *E = cell_vectors(l);
   double *S = E + 12 * static_cast<size_t>(L.h.C);
   ProfScope ps(prof, stream, "residual", l);
   hipLaunchKernelGGL(k_cell_vectors<0>, dim3(blocks(L.h.C, 256)), dim3(256), 0, stream, L.view(),
                      phys(dt, t_new), x, xo, rhs ? 0 : 1, E);
-  hipLaunchKernelGGL(k_lps_vectors, dim3(blocks(L.h.NP, 256)), dim3(256), 0, stream, L.view(), L.sP.p, x, S);
+  hipLaunchKernelGGL(k_lps_vectors, dim3(blocks(L.h.NP, 256)), dim3(256), 0, stream, L.view(), sP, x, S);
   hipLaunchKernelGGL(k_residual_nodes, dim3(blocks(L.h.N, 256)), dim3(256), 0, stream, L.view(),
                      phys(dt, t_new), x, rhs, S, E, Rout, L.large_order());
   LAUNCH_CHECK("residual");
@@ -624,7 +657,9 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
   if (level < c_) throw DnnmgError{DNNMG_EINVAL, "solve level below coarse_level"};
   if (lin_level_ < level) full = true;   // never factorised at this depth
   for (int l = full ? c_ : level; l <= level; ++l) {
-    ctx_->ensure_lps(l, dt);
+    // the level solved on carries its own problem's stabilisation; the
+    // coarser levels of its preconditioner the bounded form
+    const double *sP = ctx_->ensure_lps(l, dt, l < level ? 1 : 0);
     DevLevel &L = *ctx_->levels[l];
     OpLevel<T> &o = ops_[l];
     hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, o.JQ.p, o.JQ.n, T(0));
@@ -632,7 +667,7 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
     {
       ProfScope ps(ctx_->prof, s, "assemble", l);
       hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(L.h.N, 64)), dim3(64), 0, s, L.view(),
-                         ctx_->phys(dt, 0.0), x_dev, L.sP.p, o.JQ.p, o.JX.p);
+                         ctx_->phys(dt, 0.0), x_dev, sP, o.JQ.p, o.JX.p);
     }
     LAUNCH_CHECK("k_assemble");
     if (full && l > c_) {

@@ -309,3 +309,50 @@ def test_switch_off_redoes_slow_steps_with_the_plain_rhs(setup):
     assert rel(results[1][1], results[None][1]) < 1e-10
     assert rel(results[0][1], results[None][1]) > 1e-8     # the network's step differs
     net.close()
+
+
+@pytest.mark.parametrize("L,m,patch", [(1, 2, "block"), (2, 1, "cell")])
+def test_training_targets_and_teacher_forced_rhs_match_oracle(setup, L, m, patch):
+    """Training data of Sec. 3.1 (eq. loss), through the C-ABI: the targets
+    d* = v_F - P^m x^L at every patch node in the network's output layout,
+    divided by the output scales (dnnmg_net_targets, FP32 output), and the
+    teacher-forced right-hand side b^L = (P^m)^T Rhs(v_F)
+    (dnnmg_rhs_from_fine), checked through the coarse Newton step it drives
+    against the oracle's direct Newton with that right-hand side (FP64)."""
+    P, macro, lev, ctx, prob = setup
+    kind = dnnmg.PATCH_BLOCK if patch == "block" else dnnmg.PATCH_CELL
+    D = dnnmg.DnnmgOracle(lev, prob, L, m, kind)
+    net = P.Net(ctx, L, m, hidden=32, layers=1, patch=patch)
+    osc = np.array([2e-3, 5e-4], dtype=np.float32)
+    net.set_weights(out_scale=osc)
+    print(f"[targets] {patch} L={L} m={m} patches={net.n_patches}", flush=True)
+    st = ctx.state(L)
+    xL = random_state(lev[L].n_nodes, 14) * 0.2
+    t0 = 0.2
+    st.set(xL, t0)
+    vF = random_state(lev[D.F].n_nodes, 15) * 0.2
+    Dg = net.targets(st, vF)
+    xt = D.prolong(xL).reshape(-1, 3)
+    vf3 = vF.reshape(-1, 3)
+    Dref = np.concatenate([(vf3[D.grid, f] - xt[D.grid, f]) / float(osc[f]) for f in range(2)], axis=1)
+    assert Dg.shape == Dref.shape
+    assert rel(Dg, Dref) < 1e-6, rel(Dg, Dref)
+    # teacher forcing as in training-data generation: the coarse state is the
+    # fine solution at t_{n-1} injected to level L, its right-hand side is
+    # restricted from that fine velocity
+    sf = ctx.state(D.F)
+    for _ in range(5):
+        ctx.step(sf, DT)
+    xf, tf = sf.get()
+    sf.close()
+    xL = xf[:3 * lev[L].n_nodes].copy()
+    st.set(xL, tf)
+    net.rhs_from_fine(st, xf, DT)
+    info = ctx.step(st, DT)
+    bL = D.restrict(D.rhs(xf))
+    x_ref = dnnmg.dnnmg_newton(lev, prob, L, xL, bL, tf + DT, tol=1e-14)
+    e = rel(st.get()[0], x_ref)
+    print(f"[targets] teacher-forced step vs oracle {e:.2e} ({info})", flush=True)
+    assert e < 1e-10
+    st.close()
+    net.close()

@@ -73,7 +73,10 @@ def test_jacobian_parity_all_levels(c1):
     ctx.linearize(st, 3, DT)
     for l in range(4):
         L = lev[l]
-        J = fem.jacobian(L, prob, x[:3 * L.n_nodes])
+        # level 3 carries the problem's own LPS parameter, the coarser levels
+        # of its preconditioner the bounded one (reading G4)
+        pl = prob if l == 3 else fem.coarse_operator_problem(prob)
+        J = fem.jacobian(L, pl, x[:3 * L.n_nodes])
         w = random_state(L.n_nodes, 30 + l)
         y = ctx.jacobian_apply(l, w)
         assert rel(y, J @ w) < 1e-13, (l, rel(y, J @ w))
@@ -146,7 +149,9 @@ def test_fp64_time_steps_match_oracle(c1):
     macro, lev, ctx, prob = c1
     L = lev[3]
     # parity runs: tolerances well below the 1e-10 relative bar (the velocity
-    # is O(1e-4) during the first steps of the inflow ramp)
+    # is O(1e-4) during the first steps of the inflow ramp); the oracle's
+    # Newton stops at 5e-15, above its rounding floor (up to 2.1e-15 over these
+    # ten steps)
     ctx.set_params(newton_tol=1e-14)
     st = ctx.state(3)
     x_ref = np.zeros(3 * L.n_nodes)
@@ -154,7 +159,7 @@ def test_fp64_time_steps_match_oracle(c1):
     try:
         for n in range(1, 11):
             info = ctx.step(st, DT)
-            x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=1e-15)
+            x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=5e-15)
             xg, t = st.get()
             assert abs(t - n * DT) < 1e-15
             for f in range(3):
@@ -241,18 +246,20 @@ def test_coloured_vanka_and_vcycle_parity(c1):
 @pytest.mark.parametrize("precision,bar", [(0, 1e-10), (1, 1e-5)])
 def test_coloured_smoother_steps_match_oracle(precision, bar):
     """Time steps with the coloured smoother reach the oracle's x_n (FP64
-    1e-10 at Newton 1e-14; mixed 1e-5 per step)."""
+    1e-10 at Newton 5e-15; mixed 1e-5 per step).  In the first ramp steps the
+    velocity is O(1e-4), so the 1e-10 relative bar needs the FP64 residual
+    below ~1e-14 (the rounding floor of these three steps is below 1e-15)."""
     macro = channel_obstacle(0)
     lev = mesh.hierarchy(macro, 3)
     L = lev[3]
     prob = fem.Problem(nu=macro.nu, dt=DT)
-    ctx = _ctx(precision, nu=macro.nu, smoother=1, newton_tol=1e-14 if precision == 0 else 1e-10)
+    ctx = _ctx(precision, nu=macro.nu, smoother=1, newton_tol=5e-15 if precision == 0 else 1e-10)
     ctx.setup_mesh(macro, 3)
     st = ctx.state(3)
     x_ref = np.zeros(3 * L.n_nodes)
     for n in range(1, 4):
         info = ctx.step(st, DT)
-        x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=1e-15)
+        x_ref = solver.newton_step(L, prob, x_ref, n * DT, tol=5e-15)
         xg, _ = st.get()
         e = max(rel(xg.reshape(-1, 3)[:, f], x_ref.reshape(-1, 3)[:, f]) for f in range(3))
         print(f"[coloured] precision {precision} step {n}: {e:.2e}, gmres {info['gmres_iters']}", flush=True)
@@ -289,7 +296,7 @@ def test_coarse_sweep_count_parity(c1):
         x_ref = np.zeros(3 * lev[3].n_nodes)
         for n in range(1, 3):
             ctx.step(s2, DT)
-            x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=1e-15)
+            x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=5e-15)
             e = rel(s2.get()[0], x_ref)
             print(f"[nu_coarse] step {n}: {e:.2e}", flush=True)
             assert e < 1e-10
@@ -337,7 +344,7 @@ def test_coarse_level_direct_solve_parity(coarse):
     x_ref = np.zeros(3 * lev[3].n_nodes)
     for n in range(1, 3):
         info = ctx.step(s2, DT)
-        x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=1e-15)
+        x_ref = solver.newton_step(lev[3], prob, x_ref, n * DT, tol=5e-15)
         e = rel(s2.get()[0], x_ref)
         print(f"[coarse_level {coarse}] step {n}: {e:.2e}, gmres {info['gmres_iters']}", flush=True)
         assert e < 1e-10

@@ -168,3 +168,33 @@ def test_cell_patch_inputs_channels_and_peclet():
         np.testing.assert_array_equal(X[:, (2 + k) * n:(3 + k) * n], r[D.grid, f])
     np.testing.assert_allclose(X[:, 5 * n + 3], D.h / prob.nu, rtol=1e-14)
     assert X.shape[1] == 5 * n + 6 == 51
+
+
+def test_static_features_of_known_quadrilaterals():
+    """Aspect ratio, mid-line skew |cos| and h_P (reading N5) on patches whose
+    values are known by hand: a parallelogram with sides a and sqrt(s^2 + b^2)
+    (mid-lines (a, 0) and (s, b), area a b) and a symmetric trapezoid with
+    parallel sides 4 and 2 and height 2 (mid-lines (3, 0) and (0, 2), area 6).
+    Patch nodes are lexicographic in an S x S grid; only the corners enter."""
+    S = 3
+    a, s, b = 2.0, 0.5, 1.0
+    para = {0: (0.0, 0.0), 2: (a, 0.0), 6: (s, b), 8: (a + s, b)}
+    trap = {0: (0.0, 0.0), 2: (4.0, 0.0), 6: (1.0, 2.0), 8: (3.0, 2.0)}
+    xy = np.zeros((2 * S * S, 2))
+    for k, (px, py) in para.items():
+        xy[k] = (px, py)
+    for k, (px, py) in trap.items():
+        xy[S * S + k] = (px, py)
+    grid = np.arange(2 * S * S).reshape(2, S * S)
+    aspect, skew, h = dnnmg.static_features(xy, grid, S)
+    side2 = np.hypot(s, b)
+    np.testing.assert_allclose(aspect, [a / side2, 4.0 / 2.0], rtol=1e-15)
+    np.testing.assert_allclose(skew, [s / side2, 0.0], atol=1e-15)
+    np.testing.assert_allclose(h, [np.sqrt(a * b), np.sqrt(6.0)], rtol=1e-15)
+    # a rotated and scaled copy keeps aspect and skew, scales h
+    c, sn = np.cos(0.7), np.sin(0.7)
+    xr = 3.0 * xy @ np.array([[c, sn], [-sn, c]])
+    a2, s2, h2 = dnnmg.static_features(xr, grid, S)
+    np.testing.assert_allclose(a2, aspect, rtol=1e-13)
+    np.testing.assert_allclose(s2, skew, atol=1e-13)
+    np.testing.assert_allclose(h2, 3.0 * h, rtol=1e-13)
