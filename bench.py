@@ -1,22 +1,38 @@
-"""Benchmark: time steps/s of DNN-MG against full-depth GMG on one MI355X.
+"""Benchmark: time steps/s of DNN-MG against full-depth GMG on one MI355X, at
+a stated velocity error against the fine solution.
 
-Workload: channel with one seeded circular obstacle (seed 0), Re = 100,
-dt = 0.005, mixed precision (FP32 smoother, transfers and Krylov vectors;
-FP64 Newton residual, update, coarse solve and Gram-Schmidt dots).
-  * full-depth GMG: Newton-GMRES-multigrid on level 7 (1.38M cells, ~4.1M
-    DoFs), W untimed steps from rest, then K timed steps;
-  * DNN-MG: Newton-GMRES-multigrid on level 5 plus the patch GRU (hidden 128,
-    2 layers, BF16 MFMA) correcting level 7 (Algorithm 1), W + K steps;
-`value` is the DNN-MG rate; the GMG rate, the speed-up and the velocity
-errors of DNN-MG and of the plain level-5 method against the level-7
-solution are reported in `config`.  `train` times BPTT iterations at the
-training batch shape (8192 sequences x 32 steps).
+Workload (seeded synthetic stand-in for the paper's flow around an obstacle,
+Sec. 3.1): channel with one circular obstacle (seed 0), Re = 100, dt = 0.005,
+mixed precision (FP32 smoother, transfers and Krylov vectors; FP64 Newton
+residual, update, coarse solve and Gram-Schmidt dots).
 
-Prints one JSON line (see the field list at the bottom).  `roofline` is
-computed from per-kernel HIP-event timings recorded by the library on its
-stream over the timed region; `cpu_baseline` times the FP64 oracle on a
-bounded sample (one Newton-direct step on a coarser level of the same
-geometry, scaled to the level-7 step by the DoF ratio).
+1. Developed flow: the plain method on level 5 from rest to t_dev (past the
+   inflow ramp), prolongated to level 7 and relaxed by a few level-7 steps.
+   Every leg below starts from that state x7.
+2. Network: the patch GRU (hidden 128, 2 layers, BF16 MFMA) is trained on the
+   GPU (untimed) on other geometries of the training generator (seeds 200..,
+   Re ~ U[80, 120], each spun up the same way): teacher-forced sequences
+   (Sec. 3.1 training data, eq. loss) plus rounds that add the states of free
+   DNN-MG runs, with targets from one fine step started from each such
+   state.  The evaluated geometry is never seen in training.
+3. Timed legs (the benchmark contract): full-depth GMG on level 7, and DNN-MG
+   (Newton-GMRES-GMG on level 5 + the network correcting level 7,
+   Algorithm 1), W untimed + K timed steps each from x7.  `value` is the
+   DNN-MG rate.
+4. Evaluation window (untimed for the contract, each step clocked): the
+   level-7 GMG reference, MG(5) and DNN-MG run E steps from x7; velocity
+   errors (mass-weighted L2 and nodal) of MG(5) and DNN-MG against level 7,
+   Newton / GMRES counts, Jacobian rebuilds, switch-offs and the sustained
+   rate of each leg over the window; and the mixed-precision reference
+   against the GPU FP64 mode for a few steps.
+
+`roofline` comes from per-kernel HIP-event timings the library records on its
+stream over the timed GMG steps (the dominant kernel by total time, its
+launches of both forms merged); `cpu_baseline` times the FP64 oracle on the
+host: the FP64 parity workload (level 3, 10 steps) in full on one core and,
+as independent runs, on all cores (optionally also level-5 steps).
+Optional legs: batched plain solves (--batch-sims) and the network-size sweep
+of Table 1 (--table1).
 """
 from __future__ import annotations
 
@@ -51,101 +67,9 @@ def kernel_bytes(ctx, key, level):
     return None
 
 
-def run_batch(P, args, log):
-    """Batched plain solves: seeded multi-obstacle channels (seeds 100, 101, ...),
-    each at its own Re and depth (4-7), all advanced together."""
-    import torch
-
-    from synthetic import channel_obstacles
-    macros = [channel_obstacles(s) for s in range(100, 100 + args.batch_sims)]
-    t0 = time.perf_counter()
-    batch = P.Batch([(m, m.nu, m.info["depth"]) for m in macros], precision=1)
-    setup_s = time.perf_counter() - t0
-    groups = [batch.group_info(g) for g in range(batch.n_groups())]
-    log(f"batch: {args.batch_sims} simulations in {len(groups)} depth groups {groups}, "
-        f"setup {setup_s:.1f} s")
-    for k in range(args.batch_warmup):
-        log(f"batch warmup {k}: {batch.step(args.dt)}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = [batch.step(args.dt) for _ in range(args.batch_steps)]
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    for k, st in enumerate(stats):
-        log(f"batch step {k}: {st}")
-    dofs = sum(3 * g["n_nodes"] for g in groups)
-    out = {"simulations": args.batch_sims, "seeds": f"100..{99 + args.batch_sims}",
-           "groups": [dict(g, newton_iters=sum(st[i]["newton_iters"] for st in stats),
-                           gmres_iters=sum(st[i]["gmres_iters"] for st in stats))
-                      for i, g in enumerate(groups)],
-           "dofs": dofs, "steps": args.batch_steps, "warmup": args.batch_warmup,
-           "steps_per_s": round(args.batch_steps / sec, 4),
-           "sim_steps_per_s": round(args.batch_sims * args.batch_steps / sec, 3),
-           "dof_updates_per_s": round(dofs * args.batch_steps / sec, 1),
-           "setup_s": round(setup_s, 2), "precision": "mixed"}
-    batch.close()
-    return out
-
-
-def cpu_baseline(seed: int, level: int, fine_level: int, dt: float):
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
-    from oracle import fem, mesh, solver
-    from synthetic import channel_obstacle
-    macro = channel_obstacle(seed)
-    lev = mesh.hierarchy(macro, level)
-    L = lev[level]
-    prob = fem.Problem(nu=macro.nu, dt=dt)
-    x = np.zeros(3 * L.n_nodes)
-    x = solver.newton_step(L, prob, x, dt, tol=1e-10)      # untimed first step
-    t0 = time.perf_counter()
-    x = solver.newton_step(L, prob, x, 2 * dt, tol=1e-10)
-    sec = time.perf_counter() - t0
-    cells_fine = L.n_cells * 4 ** (fine_level - level)
-    scale = cells_fine / L.n_cells
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": 1.0 / (sec * scale), "unit": "time steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": (f"one FP64 Newton step with direct sparse solves at level {level} "
-                       f"({3 * L.n_nodes} DoFs, {sec:.2f} s), scaled by the cell ratio "
-                       f"{scale:.0f} to the level-{fine_level} step")}
-
-
-def run_steps(ctx, st, steps, dt, net=None):
-    """`steps` time steps (plain, or DNN-MG: coarse step + correction)."""
-    stats = []
-    for _ in range(steps):
-        stats.append(ctx.step(st, dt))
-        if net is not None:
-            net.correct(st, dt)
-    return stats
-
-
-def fine_state(ctx, xl, level, fine_level, corr=None):
-    """P^m x^L on the fine level, with the network's velocity correction added."""
-    x = xl
-    for l in range(level + 1, fine_level + 1):
-        x = ctx.prolong(l, x)
-    if corr is not None:
-        x = x.reshape(-1, 3).copy()
-        x[:, :2] += corr
-        x = x.reshape(-1)
-    return x
-
-
-def velocity_error(ctx, xl, level, fine_level, x_fine, corr=None):
-    """Relative l2 error of the fine-level velocity (P^m v^L [+ d]) against
-    the fine solution."""
-    import numpy as np
-    x = xl
-    for l in range(level + 1, fine_level + 1):
-        x = ctx.prolong(l, x)
-    v = x.reshape(-1, 3)[:, :2]
-    if corr is not None:
-        v = v + corr
-    ref = x_fine.reshape(-1, 3)[:, :2]
-    return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+# profiling keys that time the same kernel (merged for the roofline)
+KERNEL_GROUPS = {"k_spmv": ("spmv", "residual_spmv"), "k_vanka_apply": ("vanka_apply",),
+                 "k_vanka_update_ordered": ("vanka_update",)}
 
 
 # the kernels that run these keys on level 7 of the benchmark mesh (the
@@ -205,28 +129,213 @@ def measured_traffic(name, level):
     return None
 
 
-def roofline_from(prof, ctx, level, kernels_with_bytes, log=None):
+
+
+def roofline_from(prof, ctx, level, log=None):
+    """Roofline of the kernel with the largest total time among the level's
+    streaming kernels (launches under several profiling keys merged):
+    achieved = algorithmic bytes / time over all its launches."""
     rows = []
-    for key, (cnt, ms) in prof.items():
-        name, lv = key.split("@L")
-        if int(lv) != level or name not in kernels_with_bytes:
-            continue
-        b = kernel_bytes(ctx, name, level)
-        if b is None:
+    for kernel, keys in KERNEL_GROUPS.items():
+        ms = cnt = 0
+        nbytes = 0.0
+        traffic = []
+        for k in keys:
+            key = f"{k}@L{level}"
+            if key not in prof:
+                continue
+            c, t = prof[key]
+            b = kernel_bytes(ctx, k, level)
+            ms += t
+            cnt += c
+            nbytes += b * c
+            traffic.append((measured_traffic(k, level), c))
+        if cnt == 0:
             continue
         avg_s = ms / cnt / 1e3
-        rows.append((ms, name, cnt, avg_s, b))
+        per_launch = nbytes / cnt
+        if traffic and all(t is not None for t, _ in traffic):
+            meas = int(sum(t * c for t, c in traffic) / sum(c for _, c in traffic))
+        else:
+            meas = None
+        rows.append((ms, kernel, cnt, avg_s, per_launch, meas, keys))
         if log:
-            log(f"roofline {name}@L{level}: {b / 1e6:.1f} MB/launch algorithmic, {avg_s * 1e6:.1f} us, "
-                f"{b / avg_s / 1e9:.0f} GB/s, measured traffic {measured_traffic(name, level)}")
+            log(f"roofline {kernel}@L{level} ({', '.join(keys)}): {cnt} launches, {ms:.1f} ms, "
+                f"{per_launch / 1e6:.1f} MB/launch algorithmic, {avg_s * 1e6:.1f} us, "
+                f"{per_launch / avg_s / 1e9:.0f} GB/s, measured traffic {meas}")
     if not rows:
         return None
-    _, name, cnt, avg_s, b = max(rows)
+    ms, kernel, cnt, avg_s, b, meas, keys = max(rows)
     ach = b / avg_s / 1e9
-    return {"bound": "hbm", "kernel": f"{name}@L{level}", "achieved": round(ach, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(name, level), "avg_us": round(avg_s * 1e6, 2),
-            "launches": cnt, "bytes_per_launch": b}
+    return {"bound": "hbm", "kernel": f"{kernel}@L{level}", "profile_keys": list(keys),
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": meas, "avg_us": round(avg_s * 1e6, 2), "launches": cnt,
+            "total_ms": round(ms, 2), "bytes_per_launch": int(b)}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_run(job):
+    """Plain FP64 oracle run (Newton with direct sparse solves) on one core:
+    (seed, level, dt, steps) -> (seconds, DoFs, Newton iterations)."""
+    seed, level, dt, steps = job
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+
+    from oracle import fem, mesh, solver
+    from synthetic import channel_obstacle
+    macro = channel_obstacle(seed)
+    L = mesh.hierarchy(macro, level)[level]
+    prob = fem.Problem(nu=macro.nu, dt=dt)
+    x = np.zeros(3 * L.n_nodes)
+    newton = 0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for n in range(1, steps + 1):
+            x, hist = solver.newton_step(L, prob, x, n * dt, tol=1e-10, return_history=True)
+            newton += len(hist) - 1
+        sec = time.perf_counter() - t0
+    return sec, 3 * L.n_nodes, newton
+
+
+def cpu_baseline(args, log):
+    """The FP64 oracle on the host's cores.  Config 1 (the FP64 parity
+    workload: seed 0, level 3, dt 0.01, 10 steps from rest) in full on one
+    core; the same run for seeds 0..P-1 as P independent single-core processes
+    (all cores); optionally level-5 steps of the same geometry (dt 0.005)."""
+    import multiprocessing as mp
+    nproc = os.cpu_count() or 1
+    sec, dofs, newton = _oracle_run((0, 3, 0.01, 10))
+    out = {"value": round(10 / sec, 4), "unit": "time steps/s", "cores": 1, "kind": "oracle",
+           "sample": (f"config 1 in full: FP64 oracle (numpy einsum assembly, SuperLU direct solves), seed 0, "
+                      f"level 3 ({dofs} DoFs), dt 0.01, 10 steps from rest, {newton} Newton iterations, "
+                      f"{sec:.2f} s on one core; not the headline's level-5/7 workload (one oracle DNN-MG "
+                      f"step there takes minutes)"),
+           "dof_updates_per_s": round(dofs * 10 / sec, 1), "nproc": nproc, "cpu_model": _cpu_model()}
+    procs = max(1, min(args.cpu_procs, nproc))
+    if procs > 1:
+        jobs = [(s, 3, 0.01, 10) for s in range(procs)]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(procs) as pool:
+            res = pool.map(_oracle_run, jobs)
+        wall = time.perf_counter() - t0
+        out["all_cores"] = {"processes": procs, "threads_per_process": 1, "seeds": f"0..{procs - 1}",
+                            "steps_per_s": round(10 * procs / wall, 4),
+                            "dof_updates_per_s": round(sum(r[1] for r in res) * 10 / wall, 1),
+                            "wall_s": round(wall, 2)}
+    if args.cpu_c2_steps > 0:
+        sec5, dofs5, newton5 = _oracle_run((0, 5, args.dt, args.cpu_c2_steps))
+        out["level5"] = {"steps": args.cpu_c2_steps, "dofs": dofs5, "seconds": round(sec5, 2),
+                         "steps_per_s": round(args.cpu_c2_steps / sec5, 5), "newton_iters": newton5,
+                         "cores": 1}
+    log(f"cpu baseline: {out}")
+    return out
+
+
+def run_steps(ctx, st, steps, dt, net=None):
+    """`steps` time steps (plain, or DNN-MG: coarse step + correction)."""
+    stats = []
+    for _ in range(steps):
+        stats.append(ctx.step(st, dt))
+        if net is not None:
+            net.correct(st, dt)
+    return stats
+
+
+def fine_state(ctx, xl, level, fine_level, corr=None):
+    """P^m x^L on the fine level (host), with the network's velocity
+    correction added."""
+    x = xl
+    for l in range(level + 1, fine_level + 1):
+        x = ctx.prolong(l, x)
+    if corr is not None:
+        x = x.reshape(-1, 3).copy()
+        x[:, :2] += corr
+        x = x.reshape(-1)
+    return x
+
+
+def velocity_error(ctx, xl, level, fine_level, x_fine, corr=None):
+    """Relative l2 error of the fine-level velocity (P^m v^L [+ d]) against
+    the fine solution (host arrays; used by the small network-size sweep)."""
+    import numpy as np
+    v = fine_state(ctx, xl, level, fine_level, corr).reshape(-1, 3)[:, :2]
+    ref = x_fine.reshape(-1, 3)[:, :2]
+    return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+
+
+def make_context(P, macro, args, stream, precision=1):
+    return P.Context(precision=precision, nu=macro.nu, stream=stream,
+                     use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
+                     jacobian_reuse=args.jacobian_reuse, smoother=args.smoother, nu_coarse=args.nu_coarse,
+                     coarse_level=args.direct_level)
+
+
+def spin_up(ctx, L, F, t_dev, relax, dt, log, tag):
+    """Developed flow: the plain method on level L from rest to t_dev,
+    prolongated to level F and relaxed by `relax` level-F steps; returns the
+    host state on level F and its time."""
+    sc = ctx.state(L)
+    n = int(round(t_dev / dt))
+    t0 = time.perf_counter()
+    newton = 0
+    for _ in range(n):
+        newton += ctx.step(sc, dt)["newton_iters"]
+    xl, t = sc.get()
+    sc.close()
+    sf = ctx.state(F)
+    sf.set(fine_state(ctx, xl, L, F), t)
+    for _ in range(relax):
+        ctx.step(sf, dt)
+    x, t = sf.get()
+    sf.close()
+    log(f"{tag}: level-{L} run from rest, {n} steps to t = {n * dt:.3f} ({newton} Newton iterations), "
+        f"prolongated to level {F} and relaxed by {relax} steps, {time.perf_counter() - t0:.1f} s")
+    return x, t
+
+
+def run_batch(P, args, log):
+    """Batched plain solves: seeded multi-obstacle channels (seeds 100, 101, ...),
+    each at its own Re and depth (4-7), all advanced together."""
+    import torch
+
+    from synthetic import channel_obstacles
+    macros = [channel_obstacles(s) for s in range(100, 100 + args.batch_sims)]
+    t0 = time.perf_counter()
+    batch = P.Batch([(m, m.nu, m.info["depth"]) for m in macros], precision=1)
+    setup_s = time.perf_counter() - t0
+    groups = [batch.group_info(g) for g in range(batch.n_groups())]
+    log(f"batch: {args.batch_sims} simulations in {len(groups)} depth groups {groups}, "
+        f"setup {setup_s:.1f} s")
+    for k in range(args.batch_warmup):
+        log(f"batch warmup {k}: {batch.step(args.dt)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [batch.step(args.dt) for _ in range(args.batch_steps)]
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    for k, st in enumerate(stats):
+        log(f"batch step {k}: {st}")
+    dofs = sum(3 * g["n_nodes"] for g in groups)
+    out = {"simulations": args.batch_sims, "seeds": f"100..{99 + args.batch_sims}",
+           "groups": [dict(g, newton_iters=sum(st[i]["newton_iters"] for st in stats),
+                           gmres_iters=sum(st[i]["gmres_iters"] for st in stats))
+                      for i, g in enumerate(groups)],
+           "dofs": dofs, "steps": args.batch_steps, "warmup": args.batch_warmup,
+           "steps_per_s": round(args.batch_steps / sec, 4),
+           "sim_steps_per_s": round(args.batch_sims * args.batch_steps / sec, 3),
+           "dof_updates_per_s": round(dofs * args.batch_steps / sec, 1),
+           "setup_s": round(setup_s, 2), "precision": "mixed"}
+    batch.close()
+    return out
 
 
 def teacher_data(ctx, net, xF, L, dt, n0=1, t0=0.0):
@@ -252,22 +361,194 @@ def teacher_data(ctx, net, xF, L, dt, n0=1, t0=0.0):
 
 def standardisation(net, Xr, Dr):
     """Per-channel (mu, sigma) of the raw inputs and the two output scales,
-    and their per-column expansions."""
+    and their per-column expansions.  Xr, Dr: lists of (T, B, .) arrays."""
     import numpy as np
     S2 = net.n_out // 2
     nch = (net.n_in - net.n_stats) // (S2 - 1)        # nodal channels (6 block, 5 cell)
     nft = net.n_stats - nch
-    mu = np.array([Xr[..., c * S2:(c + 1) * S2].mean() for c in range(nch)] +
-                  [Xr[..., nch * S2 + k].mean() for k in range(nft)])
-    sg = np.array([Xr[..., c * S2:(c + 1) * S2].std() for c in range(nch)] +
-                  [Xr[..., nch * S2 + k].std() for k in range(nft)])
+    cols = [slice(c * S2, (c + 1) * S2) for c in range(nch)] + [slice(nch * S2 + k, nch * S2 + k + 1)
+                                                                for k in range(nft)]
+
+    def moments(arrs, sl):
+        n = sum(a[..., sl].size for a in arrs)
+        mean = sum(float(a[..., sl].sum(dtype=np.float64)) for a in arrs) / n
+        var = sum(float(((a[..., sl].astype(np.float64) - mean) ** 2).sum()) for a in arrs) / n
+        return mean, np.sqrt(var)
+
+    st = [moments(Xr, sl) for sl in cols]
+    mu = np.array([m for m, _ in st])
+    sg = np.array([s for _, s in st])
     sg = np.where(sg > 1e-30, sg, 1.0)
-    osc = np.array([Dr[..., :S2].std(), Dr[..., S2:].std()])
+    osc = np.array([moments(Dr, slice(0, S2))[1], moments(Dr, slice(S2, 2 * S2))[1]])
     osc = np.where(osc > 1e-30, osc, 1.0)
     mu_f = np.concatenate([np.repeat(mu[:nch], S2), mu[nch:]]).astype(np.float32)
     sg_f = np.concatenate([np.repeat(sg[:nch], S2), sg[nch:]]).astype(np.float32)
     os_f = np.concatenate([np.repeat(osc[0], S2), np.repeat(osc[1], S2)]).astype(np.float32)
     return (mu, sg, osc), (mu_f, sg_f, os_f)
+
+
+def sequences(A, seq):
+    """(T, B, n) -> (seq, (T // seq) B, n): consecutive windows of `seq` steps
+    of every patch as separate sequences."""
+    import numpy as np
+    T = A.shape[0] // seq * seq
+    A = A[:T].reshape(T // seq, seq, *A.shape[1:])
+    return np.ascontiguousarray(A.transpose(1, 0, 2, 3).reshape(seq, -1, A.shape[-1]))
+
+
+class Minibatches:
+    """Device-resident training sequences in minibatch-major layout
+    (nb, seq, B, n): each minibatch is contiguous, as the training entry point
+    takes it (T x B rows, step-major).  Sequences are shuffled into
+    minibatches with a seeded permutation; the remainder is dropped."""
+
+    def __init__(self, X, D, batch, seed):
+        import torch
+        self.X, self.D = X, D              # (seq, Btot, n) device tensors
+        self.batch, self.seed = batch, seed
+        self.build()
+
+    def add(self, X, D):
+        import torch
+        self.X = torch.cat([self.X, X], dim=1)
+        self.D = torch.cat([self.D, D], dim=1)
+        self.build()
+
+    def build(self):
+        import torch
+        seq, tot = self.X.shape[0], self.X.shape[1]
+        B = min(self.batch, tot)
+        self.nb = tot // B
+        g = torch.Generator(device="cpu").manual_seed(self.seed + tot)
+        perm = torch.randperm(tot, generator=g)[:self.nb * B].to(self.X.device)
+
+        def mb(A):
+            return A.index_select(1, perm).reshape(seq, self.nb, B, A.shape[2]).permute(1, 0, 2, 3).contiguous()
+        self.Xm, self.Dm, self.B = mb(self.X), mb(self.D), B
+
+    def fit(self, net, iters, lr, ckpt=8):
+        """Adam iterations over the minibatches in turn (lr drops to 0.3 lr for
+        the last quarter); returns (last loss, seconds, iterations)."""
+        import torch
+        seq = self.Xm.shape[1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = None
+        for it in range(iters):
+            k = it % self.nb
+            loss = net.train_step_dev(self.Xm[k].data_ptr(), self.Dm[k].data_ptr(), seq, self.B,
+                                      lr=lr if it < 0.75 * iters else 0.3 * lr, ckpt=min(ckpt, seq))
+        torch.cuda.synchronize()
+        return loss, time.perf_counter() - t0, iters
+
+
+def train_on_geometries(P, args, log, stream):
+    """Training workload stand-in (config 5 at reduced count): for each seed
+    of the training generator, the developed flow on level F, a fine
+    trajectory of train_steps steps, teacher-forced coarse steps (inputs and
+    targets), then BPTT + Adam on the GPU; `dagger` rounds add the states of
+    free DNN-MG runs on the same geometries, each step's target the
+    correction that one fine step started from the run's own fine state gives
+    (targets from the original fine trajectory would ask the network to undo
+    the run's accumulated drift in one step).  Returns the trained weights, standardisation and a
+    summary."""
+    import numpy as np
+    import torch
+
+    from synthetic import gru_weights, training_channel
+    L, F, dt, seq = args.coarse_level, args.level, args.dt, args.train_seq
+    m = F - L
+    geoms, Xr, Dr = [], [], []
+    t_all = time.perf_counter()
+    for k in range(args.train_geoms):
+        seed = args.train_seed0 + k
+        macro = training_channel(seed)
+        ctx = make_context(P, macro, args, stream.cuda_stream)
+        ctx.setup_mesh(macro, F)
+        net = P.Net(ctx, L, m, args.hidden, args.layers)
+        x0, t0 = spin_up(ctx, L, F, args.t_dev, args.relax, dt, log, f"train seed {seed} (Re {0.1 / macro.nu:.1f})")
+        sf = ctx.state(F)
+        sf.set(x0, t0)
+        xF = [x0]
+        for _ in range(args.train_steps):
+            ctx.step(sf, dt)
+            xF.append(sf.get()[0])
+        sf.close()
+        X, D = teacher_data(ctx, net, xF, L, dt, t0=t0)
+        Xr.append(X)
+        Dr.append(D)
+        geoms.append({"seed": seed, "re": round(0.1 / macro.nu, 2), "ctx": ctx, "net": net, "xF": xF, "t0": t0})
+        log(f"train seed {seed}: {args.train_steps} fine steps + teacher-forced coarse steps, "
+            f"{X.shape[1]} patches, {time.perf_counter() - t_all:.1f} s so far")
+    net0 = geoms[0]["net"]
+    (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net0, Xr, Dr)
+    dev = torch.device("cuda")
+    Xd = torch.cat([torch.from_numpy(sequences((X - mu_f) / sg_f, seq)).to(dev) for X in Xr], dim=1)
+    Dd = torch.cat([torch.from_numpy(sequences(D / os_f, seq)).to(dev) for D in Dr], dim=1)
+    del Xr, Dr
+    data = Minibatches(Xd, Dd, args.train_batch, args.seed)
+    w0 = gru_weights(net0.n_in, args.hidden, args.layers, net0.n_out, seed=args.seed, scale=0.5)
+    net0.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
+    loss, sec, its = data.fit(net0, args.train_net_iters, 2e-3)
+    fit_sec, fit_its = sec, its
+    log(f"net training (teacher forcing): loss {loss:.2f}, {data.X.shape[1]} sequences of {seq} steps, "
+        f"{data.nb} minibatches of {data.B}, {1e3 * sec / its:.2f} ms per iteration")
+    for rnd in range(args.dagger):
+        # free DNN-MG runs with the current network; the target of each step is
+        # the correction that one fine step, started from the run's own fine
+        # state (the corrected velocity of the previous step), gives
+        w = net0.get_weights()
+        Xc_all, Dc_all = [], []
+        for g in geoms:
+            ctx, net, x0, t0 = g["ctx"], g["net"], g["xF"][0], g["t0"]
+            if net is not net0:
+                net.set_weights(w, mu=mu, sigma=sg, out_scale=osc)
+            nL = ctx.level_info(L)[0]
+            st = ctx.state(L)
+            st.set(x0[:3 * nL], t0)
+            net.reset(st)
+            net.rhs_from_fine(st, x0, dt)
+            sf = ctx.state(F)
+            vc = x0
+            Xc, Dc = [], []
+            for n in range(args.dagger_steps):
+                t = st.get()[1]
+                sf.set(vc, t)
+                ctx.step(sf, dt)
+                xstar = sf.get()[0]
+                ctx.step(st, dt)
+                out = net.correct(st, dt, debug=True)
+                Xc.append(out["inputs"])
+                Dc.append(net.targets(st, xstar))
+                xt = fine_state(ctx, st.get()[0], L, F).reshape(-1, 3).copy()
+                xt[:, :2] += out["correction"]
+                vc = xt.reshape(-1)
+            sf.close()
+            st.close()
+            Xc_all.append(torch.from_numpy(sequences(np.stack(Xc), seq)).to(dev))
+            Dc_all.append(torch.from_numpy(sequences(np.stack(Dc), seq)).to(dev))
+            log(f"free-run round {rnd + 1}, seed {g['seed']}: {args.dagger_steps} steps, "
+                f"{time.perf_counter() - t_all:.1f} s so far")
+        data.add(torch.cat(Xc_all, dim=1), torch.cat(Dc_all, dim=1))
+        loss, sec, its = data.fit(net0, args.dagger_iters, 1e-3)
+        fit_sec += sec
+        fit_its += its
+        log(f"net training (round {rnd + 1}, free DNN-MG states added): loss {loss:.2f}, "
+            f"{data.X.shape[1]} sequences")
+    w = net0.get_weights()
+    info = {"geometries": [{"seed": g["seed"], "re": g["re"]} for g in geoms],
+            "t_start": round(geoms[0]["t0"], 4), "fine_steps_per_geometry": args.train_steps,
+            "sequences": int(data.X.shape[1]), "seq": seq, "batch": data.B, "rounds": 1 + args.dagger,
+            "free_run_steps_per_round": args.dagger_steps,
+            "adam_iters": fit_its, "final_loss": round(float(loss), 4),
+            "bptt_ms_per_iter": round(1e3 * fit_sec / fit_its, 3),
+            "wall_s": round(time.perf_counter() - t_all, 1)}
+    for g in geoms:
+        g["net"].close()
+        g["ctx"].close()
+    del data, Xd, Dd
+    torch.cuda.empty_cache()
+    return w, (mu, sg, osc), info
 
 
 class Fitter:
@@ -291,45 +572,6 @@ class Fitter:
         self.sec += time.perf_counter() - t0
         self.iters += n_it
         return loss
-
-
-def train_dnnmg(ctx, net, xF, L, dt, iters, dagger, seed, log):
-    """Trains the patch network on the GPU (untimed in the step benchmark):
-    teacher-forced inputs and targets, BPTT with Adam, then DAgger rounds that
-    add the states of free DNN-MG runs."""
-    import numpy as np
-    import torch
-
-    from synthetic import gru_weights
-    N = len(xF) - 1
-    Xr, Dr = teacher_data(ctx, net, xF, L, dt)
-    (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net, Xr, Dr)
-    w0 = gru_weights(net.n_in, net.hidden, net.layers, net.n_out, seed=seed, scale=0.5)
-    net.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
-    X = torch.from_numpy((Xr - mu_f) / sg_f).cuda()
-    D = torch.from_numpy(Dr / os_f).cuda()
-    del Xr, Dr
-    fit = Fitter(net, X, D)
-    first = net.train_step_dev(X.data_ptr(), D.data_ptr(), N, X.shape[1], lr=2e-3, ckpt=fit.ckpt)
-    loss = fit(iters, 2e-3)
-    log(f"net training (teacher forcing): loss {first:.1f} -> {loss:.1f}, {X.shape[1]} sequences")
-    for rnd in range(dagger):
-        st = ctx.state(L)
-        net.reset(st)
-        Xc, Dc = [], []
-        for n in range(1, N + 1):
-            ctx.step(st, dt)
-            Xc.append(net.correct(st, dt, debug=True)["inputs"])
-            Dc.append(net.targets(st, xF[n]))
-        st.close()
-        fit.X = torch.cat([fit.X, torch.from_numpy(np.stack(Xc)).cuda()], dim=1).contiguous()
-        fit.D = torch.cat([fit.D, torch.from_numpy(np.stack(Dc)).cuda()], dim=1).contiguous()
-        loss = fit(iters // 2, 1e-3)
-        log(f"net training (DAgger round {rnd}): loss {loss:.1f}, {fit.X.shape[1]} sequences")
-    del fit
-    torch.cuda.empty_cache()
-    return {"sequences_per_round": net.n_patches, "steps": N, "rounds": 1 + dagger,
-            "final_loss": round(float(loss), 3)}
 
 
 TABLE1_SHAPES = ((32, 1), (64, 1), (32, 2), (64, 2), (32, 3), (64, 3))
@@ -445,7 +687,7 @@ def run_table1(P, args, log):
     Dr = Dr[:nseq * seq].reshape(nseq, seq, *Dr.shape[1:]).transpose(1, 0, 2, 3).reshape(seq, -1, Dr.shape[2])
     for H, layers in TABLE1_SHAPES:
         net = P.Net(ctx, L, 1, H, layers, patch="cell")
-        (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net, Xr, Dr)
+        (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net, [Xr], [Dr])
         net.set_weights(gru_weights(net.n_in, H, layers, net.n_out, seed=args.seed, scale=0.5),
                         mu=mu, sigma=sg, out_scale=osc)
         X = torch.from_numpy(np.ascontiguousarray((Xr - mu_f) / sg_f)).cuda()
@@ -471,6 +713,33 @@ def run_table1(P, args, log):
     return out
 
 
+
+
+def clocked(stream, fn):
+    """Runs fn() between two stream synchronisations; (result, seconds)."""
+    stream.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    stream.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def err_summary(errs):
+    import numpy as np
+    out = {}
+    for k in ("l2", "nodal"):
+        v = np.array([e[k] for e in errs])
+        out[f"{k}_mean"] = round(float(v.mean()), 7)
+        out[f"{k}_max"] = round(float(v.max()), 7)
+        out[f"{k}_last"] = round(float(v[-1]), 7)
+    return out
+
+
+def rel_errors(e):
+    import math
+    return {"l2": math.sqrt(e["l2_err2"] / e["l2_ref2"]), "nodal": math.sqrt(e["nodal_err2"] / e["nodal_ref2"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -481,30 +750,45 @@ def main():
     ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--layers", type=int, default=2)
     ap.add_argument("--dt", type=float, default=0.005)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-level", type=int, default=4)
-    ap.add_argument("--train-iters", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0, help="evaluated geometry (channel_obstacle seed)")
+    ap.add_argument("--t-dev", type=float, default=3.0,
+                    help="developed flow: the level-L run from rest reaches this time before the legs start")
+    ap.add_argument("--relax", type=int, default=10, help="level-F steps after prolongating the level-L state")
+    ap.add_argument("--eval-steps", type=int, default=200,
+                    help="evaluation window: steps of the reference, MG(L) and DNN-MG runs from the start state")
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="steps of the GPU FP64 mode compared with the mixed-precision reference")
+    ap.add_argument("--train-net", type=int, default=1, choices=(0, 1),
+                    help="train the patch network on held-out geometries (untimed); 0: random weights")
+    ap.add_argument("--train-geoms", type=int, default=4, help="training geometries (seeds train-seed0..)")
+    ap.add_argument("--train-seed0", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=64, help="fine steps per training geometry")
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
-    ap.add_argument("--train-net", type=int, default=1,
-                    help="train the patch network on the GPU before the DNN-MG run (untimed)")
-    ap.add_argument("--train-net-iters", type=int, default=150)
-    ap.add_argument("--dagger", type=int, default=2)
+    ap.add_argument("--train-net-iters", type=int, default=400)
+    ap.add_argument("--dagger", type=int, default=2,
+                    help="training rounds on free DNN-MG runs of the training geometries (targets from one "
+                         "fine step started from the run's own state)")
+    ap.add_argument("--dagger-steps", type=int, default=64)
+    ap.add_argument("--dagger-iters", type=int, default=300)
+    ap.add_argument("--zero-net-control", type=int, default=1, choices=(0, 1),
+                    help="also run the DNN-MG window with a zero network (d = 0): the coupling's own error")
+    ap.add_argument("--switchoff-study", type=int, default=0, choices=(0, 1),
+                    help="DNN-MG over the window for each switch-off threshold, trained and hostile network")
+    ap.add_argument("--switchoff-thresholds", default="0,3,5,7,10")
+    ap.add_argument("--hostile-scale", type=float, default=20.0,
+                    help="hostile network: the trained weights with every correction scaled by this factor")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="independent single-core oracle runs for the all-cores figure (capped at nproc)")
+    ap.add_argument("--cpu-c2-steps", type=int, default=0,
+                    help="also time this many oracle steps on level 5 of the evaluated geometry")
     ap.add_argument("--profile", choices=("roofline", "all"), default="roofline",
                     help="roofline: HIP events only around the fine-level GMG kernels and "
                          "the network kernels; all: every kernel of every level, launched "
                          "directly (no graphs; events add launch overhead to the timings)")
     ap.add_argument("--newton-predictor", type=int, default=1, choices=(0, 1),
                     help="1: Newton starts from the linear extrapolation of the last two states")
-    ap.add_argument("--table1", type=int, default=1, choices=(0, 1),
-                    help="network-size sweep (Table 1 shapes on cell patches, untimed leg)")
-    ap.add_argument("--t1-level", type=int, default=3)
-    ap.add_argument("--t1-dt", type=float, default=0.01)
-    ap.add_argument("--t1-train-from", type=float, default=4.0)
-    ap.add_argument("--t1-start", type=float, default=7.0)
-    ap.add_argument("--t1-end", type=float, default=10.0)
-    ap.add_argument("--t1-iters", type=int, default=600)
     ap.add_argument("--jacobian-reuse", type=int, default=1, choices=(0, 1),
                     help="keep Newton's Jacobians across iterations and steps while the "
                          "residual contracts by 0.1 or better (0: rebuild every step)")
@@ -512,21 +796,27 @@ def main():
                     help="full-depth GMG leg: sweeps before and after on the V-cycle levels below the "
                          "one GMRES works on (0: the same V(2,2) on every level)")
     ap.add_argument("--dnnmg-sweeps", default="2,1,1",
-                    help="pre,post,coarse sweeps of the V-cycles of the DNN-MG leg's level-5 solves "
-                         "(measured on level 5: V(2,1) with V(1,1) below is the fastest schedule; the "
-                         "GMG leg keeps V(2,2) throughout)")
+                    help="pre,post,coarse sweeps of the V-cycles of the level-L solves (MG(L) and "
+                         "DNN-MG legs; the GMG leg keeps V(2,2) throughout)")
     ap.add_argument("--direct-level", type=int, default=1, choices=(0, 1, 2),
-                    help="level of the direct (FP64 dense inverse) solve at the bottom of every V-cycle, "
-                         "both legs (level 1: 1,140 unknowns, one 10 MB mat-vec instead of level-1 "
-                         "sweeps and the level-0 solve)")
+                    help="level of the direct (FP64 dense inverse) solve at the bottom of every V-cycle")
     ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
                     help="0: additive cell-Vanka, 1: coloured multiplicative cell-Vanka")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel directly instead of replaying captured graphs")
-    ap.add_argument("--batch-sims", type=int, default=64,
+    ap.add_argument("--batch-sims", type=int, default=0,
                     help="batched plain solves: simulations (0 skips the leg)")
-    ap.add_argument("--batch-steps", type=int, default=2)
-    ap.add_argument("--batch-warmup", type=int, default=1)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-solve leg")
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--table1", type=int, default=0, choices=(0, 1),
+                    help="network-size sweep (Table 1 shapes on cell patches, untimed leg)")
+    ap.add_argument("--t1-level", type=int, default=3)
+    ap.add_argument("--t1-dt", type=float, default=0.01)
+    ap.add_argument("--t1-train-from", type=float, default=4.0)
+    ap.add_argument("--t1-start", type=float, default=7.0)
+    ap.add_argument("--t1-end", type=float, default=10.0)
+    ap.add_argument("--t1-iters", type=int, default=600)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="device copy of this many MiB before the run (calibrates "
                          "hardware traffic counters against a known byte count)")
@@ -541,6 +831,7 @@ def main():
     import paper_2106_07687_amd as P
     from synthetic import channel_obstacle, gru_weights
 
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     if args.calib_copy_mb > 0:
@@ -549,120 +840,201 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    macro = channel_obstacle(args.seed)
-    ctx = P.Context(precision=1, nu=macro.nu, stream=stream.cuda_stream,
-                    use_graphs=0 if args.no_graphs else 1, newton_predictor=args.newton_predictor,
-                    jacobian_reuse=args.jacobian_reuse, smoother=args.smoother, nu_coarse=args.nu_coarse,
-                    coarse_level=args.direct_level)
-    F = args.level
+    L, F, dt, W, K, E = args.coarse_level, args.level, args.dt, args.warmup, args.steps, args.eval_steps
+    m = F - L
+    pre, post, coarse = (int(v) for v in args.dnnmg_sweeps.split(","))
     if args.profile == "all":
         gmg_keys = dnn_keys = None
     else:
         gmg_keys = [f"{k}@L{F}" for k in ("spmv", "residual_spmv", "vanka_apply", "vanka_update",
                                           "assemble", "vanka_factor", "residual", "gs_dots")]
-        dnn_keys = [f"{k}{l}@L{F}" for l in range(args.layers)
-                    for k in ("gru_gemm_in", "gru_step")]
-        dnn_keys += [f"{k}@L{F}" for k in ("gru_head", "dnnmg_rhs", "dnnmg_prolong",
-                                           "patch_gather", "patch_scatter")]
-    t0 = time.perf_counter()
-    ctx.setup_mesh(macro, args.level)
-    setup_s = time.perf_counter() - t0
-    nF, cF, _ = ctx.level_info(args.level)
-    nL = ctx.level_info(args.coarse_level)[0]
-    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
-    log(f"setup levels 0..{args.level}: fine {nF} nodes / {cF} cells, {setup_s:.1f} s")
-    for l in range(args.level + 1):
-        log(f"workgroup sizes level {l}: {ctx.launch_config(l)}")
+        dnn_keys = [f"{k}{l}@L{F}" for l in range(args.layers) for k in ("gru_gemm_in", "gru_step")]
+        dnn_keys += [f"{k}@L{F}" for k in ("gru_head", "dnnmg_rhs", "dnnmg_prolong", "patch_gather",
+                                           "patch_scatter")]
 
-    # ---- full-depth GMG on the fine level (reference and baseline)
-    sf = ctx.state(args.level)
-    for k, s_ in enumerate(run_steps(ctx, sf, args.warmup, args.dt)):
-        log(f"gmg warmup {k}: {s_}")
-    ctx.profile_select(gmg_keys)
-    ctx.profile_enable(True)
-    stream.synchronize()
-    t0 = time.perf_counter()
-    g_stats = run_steps(ctx, sf, args.steps, args.dt)
-    stream.synchronize()
-    g_sec = time.perf_counter() - t0
-    g_prof = ctx.profile_report()
-    ctx.profile_enable(False)
-    for k, s_ in enumerate(g_stats):
-        log(f"gmg step {k}: {s_}")
-    x_fine, _ = sf.get()
+    if args.batch_only:     # only the batched-solve leg (profiling runs)
+        print(json.dumps({"batch": run_batch(P, args, log)}), flush=True)
+        return
 
-    # ---- DNN-MG: Newton-GMRES-MG on the coarse level + patch GRU on the fine level
-    m = args.level - args.coarse_level
-    net = P.Net(ctx, args.coarse_level, m, args.hidden, args.layers)
-    nsteps = args.warmup + args.steps
-    # fine reference at every step (untimed replay of the GMG run above)
-    sfr = ctx.state(args.level)
-    xF = [sfr.get()[0]]
-    for _ in range(nsteps):
-        ctx.step(sfr, args.dt)
-        xF.append(sfr.get()[0])
-    sfr.close()
-    pre, post, coarse = (int(v) for v in args.dnnmg_sweeps.split(","))
-    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse)   # coarse solves of the DNN-MG leg
+    # ---- network training on held-out geometries (untimed)
     train_info = None
     if args.train_net:
-        train_info = train_dnnmg(ctx, net, xF, args.coarse_level, args.dt, args.train_net_iters,
-                                 args.dagger, args.seed, log)
+        w_net, (mu, sg, osc), train_info = train_on_geometries(P, args, log, stream)
+
+    # ---- the evaluated geometry: developed flow on level F
+    macro = channel_obstacle(args.seed)
+    ctx = make_context(P, macro, args, stream.cuda_stream)
+    t0 = time.perf_counter()
+    ctx.setup_mesh(macro, F)
+    setup_s = time.perf_counter() - t0
+    nF, cF, _ = ctx.level_info(F)
+    nL = ctx.level_info(L)[0]
+    log(f"setup levels 0..{F}: fine {nF} nodes / {cF} cells, {setup_s:.1f} s")
+    for lv in range(F + 1):
+        log(f"workgroup sizes level {lv}: {ctx.launch_config(lv)}")
+    x7, t7 = spin_up(ctx, L, F, args.t_dev, args.relax, dt, log, f"seed {args.seed}")
+    net = P.Net(ctx, L, m, args.hidden, args.layers)
+    if args.train_net:
+        net.set_weights(w_net, mu=mu, sigma=sg, out_scale=osc)
     else:
         w = gru_weights(net.n_in, args.hidden, args.layers, net.n_out, seed=args.seed, scale=0.5)
         net.set_weights(w, mu=np.zeros(10), sigma=np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
                         out_scale=np.array([1e-3, 1e-3]))
-    sc = ctx.state(args.coarse_level)
-    net.reset(sc)
-    for k, s_ in enumerate(run_steps(ctx, sc, args.warmup, args.dt, net)):
+
+    def start_coarse(with_net):
+        st = ctx.state(L)
+        st.set(x7[:3 * nL], t7)
+        if with_net:
+            net.reset(st)
+            net.rhs_from_fine(st, x7, dt)     # the first correction starts from the fine state
+        return st
+
+    # ---- A. timed full-depth GMG on level F
+    sf = ctx.state(F)
+    sf.set(x7, t7)
+    for k, s_ in enumerate(run_steps(ctx, sf, W, dt)):
+        log(f"gmg warmup {k}: {s_}")
+    ctx.profile_select(gmg_keys)
+    ctx.profile_enable(True)
+    g_stats, g_sec = clocked(stream, lambda: run_steps(ctx, sf, K, dt))
+    g_prof = ctx.profile_report()
+    ctx.profile_enable(False)
+    sf.close()
+    for k, s_ in enumerate(g_stats):
+        log(f"gmg step {k}: {s_}")
+
+    # ---- B. reference trajectory over the evaluation window (level F, on the device)
+    ref = torch.empty((E, 3 * nF), dtype=torch.float64, device="cuda")
+    sf = ctx.state(F)
+    sf.set(x7, t7)
+    ref_stats, ref_sec = [], 0.0
+    for n in range(E):
+        s_, sec = clocked(stream, lambda: ctx.step(sf, dt))
+        ref_stats.append(s_)
+        ref_sec += sec
+        sf.get_dev(ref[n].data_ptr())
+    stream.synchronize()
+    sf.close()
+    log(f"reference: {E} level-{F} steps, {E / ref_sec:.2f} steps/s sustained, "
+        f"{sum(s['jacobian_builds'] for s in ref_stats)} hierarchy builds")
+
+    # ---- C. GPU FP64 mode against the mixed-precision reference
+    fp64 = None
+    if args.fp64_steps > 0:
+        c64 = make_context(P, macro, args, stream.cuda_stream, precision=0)
+        c64.setup_mesh(macro, F)
+        s64 = c64.state(F)
+        s64.set(x7, t7)
+        tmp = torch.empty(3 * nF, dtype=torch.float64, device="cuda")
+        worst = {"u": 0.0, "v": 0.0, "p": 0.0}
+        for n in range(min(args.fp64_steps, E)):
+            c64.step(s64, dt)
+            s64.get_dev(tmp.data_ptr())
+            stream.synchronize()
+            a, b = tmp.view(-1, 3), ref[n].view(-1, 3)
+            for f, name in enumerate("uvp"):
+                e = float(torch.linalg.norm(a[:, f] - b[:, f]) / torch.linalg.norm(b[:, f]))
+                worst[name] = max(worst[name], e)
+        fp64 = {"steps": min(args.fp64_steps, E), "max_rel_l2": {k: float(f"{v:.3e}") for k, v in worst.items()}}
+        log(f"mixed precision vs GPU FP64 mode on level {F}: {fp64}")
+        s64.close()
+        c64.close()
+        del tmp
+
+    # ---- D. MG(L) over the window: errors against the reference
+    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse)
+    sc = start_coarse(False)
+    mgl_stats, mgl_sec, mgl_err = [], 0.0, []
+    for n in range(E):
+        s_, sec = clocked(stream, lambda: ctx.step(sc, dt))
+        mgl_stats.append(s_)
+        mgl_sec += sec
+        mgl_err.append(rel_errors(ctx.velocity_error(L, sc.device_ptr(), F, ref[n].data_ptr())))
+    sc.close()
+    n_off = max(1, int(round(2 * np.median([s_["newton_iters"] for s_ in mgl_stats[:10]]))))
+    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse, switch_off_newton=n_off)
+
+    # ---- E. timed DNN-MG
+    sc = start_coarse(True)
+    for k, s_ in enumerate(run_steps(ctx, sc, W, dt, net)):
         log(f"dnnmg warmup {k}: {s_}")
     ctx.profile_select(dnn_keys)
     ctx.profile_enable(True)
-    stream.synchronize()
-    t0 = time.perf_counter()
-    d_stats = run_steps(ctx, sc, args.steps, args.dt, net)
-    stream.synchronize()
-    d_sec = time.perf_counter() - t0
+    d_stats, d_sec = clocked(stream, lambda: run_steps(ctx, sc, K, dt, net))
     d_prof = ctx.profile_report()
     ctx.profile_enable(False)
+    sc.close()
     for k, s_ in enumerate(d_stats):
         log(f"dnnmg step {k}: {s_}")
-    sc.close()
-    # velocity errors against the fine solution at every timed step (untimed
-    # replays of the same deterministic runs)
-    err_dnn, err_mgl = [], []
-    n_obs = len(macro.curves)
-    funcs = {}
 
-    def fdict(x):
-        j, d, lf = ctx.functionals(args.level, x, n_obs)
-        return {"j_div": j, "drag": float(d[0]), "lift": float(lf[0])}
-    for with_net in (True, False):
-        st = ctx.state(args.coarse_level)
-        if with_net:
-            net.reset(st)
-        for n in range(1, nsteps + 1):
-            ctx.step(st, args.dt)
-            xl, _ = st.get()
-            corr = net.correct(st, args.dt, debug=True)["correction"] if with_net else None
-            if n > args.warmup:
-                e = velocity_error(ctx, xl, args.coarse_level, args.level, xF[n], corr)
-                (err_dnn if with_net else err_mgl).append(e)
-            if n == nsteps:   # functionals of the last step (Sec. 3.3)
-                funcs["dnnmg" if with_net else "mg_coarse"] = fdict(
-                    fine_state(ctx, xl, args.coarse_level, args.level, corr))
-        st.close()
-    funcs["reference_fine_gmg"] = fdict(xF[nsteps])
-    err_dnn, err_mgl = float(np.mean(err_dnn)), float(np.mean(err_mgl))
-    log(f"velocity error (mean over timed steps): DNN-MG {err_dnn:.3e}, MG(L) {err_mgl:.3e}")
-    log(f"functionals at t = {nsteps * args.dt:.3f}: {funcs}")
+    def leg(stats, sec):
+        return {"steps_per_s": round(len(stats) / sec, 3),
+                "newton_iters": sum(s_["newton_iters"] for s_ in stats),
+                "gmres_iters": sum(s_["gmres_iters"] for s_ in stats),
+                "jacobian_builds": sum(s_["jacobian_builds"] for s_ in stats),
+                "fallbacks": sum(s_["fallback"] for s_ in stats)}
+
+    # ---- F. DNN-MG over the window (and, as a control, with d = 0)
+    def dnnmg_window(the_net):
+        sc = start_coarse(False)
+        the_net.reset(sc)
+        the_net.rhs_from_fine(sc, x7, dt)
+        stats, total, errs = [], 0.0, []
+        for n in range(E):
+            def one():
+                s_ = ctx.step(sc, dt)
+                the_net.correct(sc, dt)
+                return s_
+            s_, sec = clocked(stream, one)
+            stats.append(s_)
+            total += sec
+            errs.append(rel_errors(ctx.velocity_error(F, the_net.fine_velocity_ptr(), F, ref[n].data_ptr())))
+        sc.close()
+        return stats, total, errs
+
+    dnn_stats, dnn_sec, dnn_err = dnnmg_window(net)
+    zero_err = None
+    if args.zero_net_control:
+        znet = P.Net(ctx, L, m, args.hidden, args.layers)
+        znet.set_weights(np.zeros(znet.n_params, dtype=np.float32), mu=np.zeros(10), sigma=np.ones(10),
+                         out_scale=np.ones(2))
+        zero_err = dnnmg_window(znet)[2]
+        znet.close()
+    # ---- switch-off study (Sec. 3.3): DNN-MG over the window for a range of
+    # Newton-count thresholds, with the trained network and a hostile one
+    # (the same weights with every correction scaled by --hostile-scale)
+    switchoff = None
+    if args.switchoff_study:
+        switchoff = {"thresholds": [int(v) for v in args.switchoff_thresholds.split(",")],
+                     "hostile_scale": args.hostile_scale, "runs": []}
+        hnet = P.Net(ctx, L, m, args.hidden, args.layers)
+        w_cur = net.get_weights()
+        hnet.set_weights(w_cur, mu=mu if args.train_net else np.zeros(10),
+                         sigma=sg if args.train_net else np.array([1, 1, 1, 10, 10, 10, 1, 1, 1, 100.0]),
+                         out_scale=(osc if args.train_net else np.array([1e-3, 1e-3])) * args.hostile_scale)
+        for kind, the_net in (("trained", net), ("hostile", hnet)):
+            for thr in switchoff["thresholds"]:
+                ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse, switch_off_newton=thr)
+                st_, sec_, er_ = dnnmg_window(the_net)
+                row = dict(net=kind, threshold=thr, **leg(st_, sec_), **{k: v for k, v in err_summary(er_).items()
+                                                                      if k in ("l2_mean", "l2_last")})
+                log(f"switch-off study: {row}")
+                switchoff["runs"].append(row)
+        hnet.close()
+        ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse, switch_off_newton=n_off)
+    del ref
+    err_d, err_l = err_summary(dnn_err), err_summary(mgl_err)
+    err_z = err_summary(zero_err) if zero_err else None
+    trace = {name: [round(e[n]["l2"], 7) for n in range(0, E, max(1, E // 10))] + [round(e[-1]["l2"], 7)]
+             for name, e in (("dnnmg", dnn_err), ("mg_coarse", mgl_err), ("dnnmg_zero_net", zero_err)) if e}
+    log(f"velocity error over {E} steps: DNN-MG {err_d}, MG({L}) {err_l}, DNN-MG with d = 0 {err_z}")
+    log(f"l2 error trace (every {max(1, E // 10)} steps): {trace}")
 
     for name, prof in (("gmg", g_prof), ("dnnmg", d_prof)):
         for key in sorted(prof, key=lambda k: -prof[k][1])[:14]:
             cnt, ms = prof[key]
             log(f"{name} kernel {key}: {cnt} launches, {ms:.2f} ms total, {1e3 * ms / cnt:.1f} us avg")
-    roof = roofline_from(g_prof, ctx, args.level, ("spmv", "residual_spmv", "vanka_apply", "vanka_update"),
-                         log)
+    roof = roofline_from(g_prof, ctx, F, log)
     # MFMA utilisation of the network's input GEMM (layer 0)
     mfma = None
     mkey = f"gru_gemm_in0@L{F}"
@@ -672,79 +1044,66 @@ def main():
         tf = flop / (ms / cnt / 1e3) / 1e12
         mfma = {"kernel": mkey, "achieved": round(tf, 2), "peak": 2500.0,
                 "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5), "avg_us": round(1e3 * ms / cnt, 2)}
-    # ---- batched plain solves
-    batch_info = run_batch(P, args, log) if args.batch_sims > 0 else None
-    # ---- network-size sweep (Table 1 / Table 2 analogue)
-    table1 = run_table1(P, args, log) if args.table1 else None
-    # ---- BPTT training throughput at the training batch shape (synthetic rows)
     train = None
-    if args.train_iters > 0:
-        T, B = args.train_seq, args.train_batch
-        gX = torch.randn(T, B, net.n_in, device="cuda", dtype=torch.float32)
-        gD = 0.1 * torch.randn(T, B, net.n_out, device="cuda", dtype=torch.float32)
-        torch.cuda.synchronize()
-        net.train_step_dev(gX.data_ptr(), gD.data_ptr(), T, B, lr=1e-4, ckpt=8)   # warm-up / allocation
-        stream.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.train_iters):
-            net.train_step_dev(gX.data_ptr(), gD.data_ptr(), T, B, lr=1e-4, ckpt=8)
-        stream.synchronize()
-        tsec = (time.perf_counter() - t0) / args.train_iters
-        H, I, O, Lr = args.hidden, net.n_in, net.n_out, args.layers
+    if train_info:
+        H, I, O, Lr, T = args.hidden, net.n_in, net.n_out, args.layers, args.train_seq
         fwd = 2.0 * (3 * H * ((I + 31) // 32 * 32) + 3 * H * H + (Lr - 1) * 6 * H * H + O * H)
         nseg = (T + 7) // 8                   # checkpoints every 8 steps
         # forward, recompute of all segments but the last, backward (2x forward)
-        flop = T * B * fwd * (1 + (nseg - 1) / nseg + 2)
-        train = {"seq": T, "batch": B, "hidden": H, "layers": Lr, "ms_per_iter": round(1e3 * tsec, 2),
-                 "model_tflop_per_iter": round(flop / 1e12, 4),
-                 "tflops": round(flop / tsec / 1e12, 2), "mfma_frac": round(flop / tsec / 2.5e15, 5)}
-        log(f"train: {train}")
-        del gX, gD
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.seed, args.cpu_level, args.level, args.dt)
-    ms_step = 1e3 * d_sec / args.steps
+        flop = T * train_info["batch"] * fwd * (1 + (nseg - 1) / nseg + 2)
+        tsec = train_info["bptt_ms_per_iter"] / 1e3
+        train = {"seq": T, "batch": train_info["batch"], "hidden": H, "layers": Lr,
+                 "ms_per_iter": train_info["bptt_ms_per_iter"], "data": "solver trajectories (training leg)",
+                 "model_tflop_per_iter": round(flop / 1e12, 4), "tflops": round(flop / tsec / 1e12, 2),
+                 "mfma_frac": round(flop / tsec / 2.5e15, 5)}
+    net.close()
+    ctx.close()
+    torch.cuda.empty_cache()
+    batch_info = run_batch(P, args, log) if args.batch_sims > 0 else None
+    table1 = run_table1(P, args, log) if args.table1 else None
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args, log)
     result = {
         "metric": METRIC,
-        "value": round(args.steps / d_sec, 4),
+        "value": round(K / d_sec, 4),
         "unit": "time steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * d_sec / K, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64+bf16",
         "data": "synthetic",
-        "config": {"workload": (f"DNN-MG: Newton-GMRES-GMG on level {args.coarse_level} + GRU "
-                                f"{args.hidden}x{args.layers} patch net correcting level {args.level}; "
-                                f"channel+obstacle seed {args.seed}, Re 100, dt {args.dt}, mixed precision"),
-                   "coarse_level": args.coarse_level, "fine_level": args.level,
-                   "fine_dofs": 3 * nF, "coarse_dofs": 3 * nL, "patches": net.n_patches,
-                   "gmg_steps_per_s": round(args.steps / g_sec, 4),
-                   "gmg_ms_per_step": round(1e3 * g_sec / args.steps, 3),
+        "config": {"workload": (f"DNN-MG: Newton-GMRES-GMG on level {L} + GRU {args.hidden}x{args.layers} "
+                                f"patch net correcting level {F}; channel+obstacle seed {args.seed}, Re 100, "
+                                f"dt {dt}, developed flow from t = {t7:.3f}, mixed precision"),
+                   "coarse_level": L, "fine_level": F, "fine_dofs": 3 * nF, "coarse_dofs": 3 * nL,
+                   "patches": net.n_patches, "t_start": round(t7, 4),
+                   "gmg_steps_per_s": round(K / g_sec, 4), "gmg_ms_per_step": round(1e3 * g_sec / K, 3),
                    "dnnmg_speedup_vs_gmg": round(g_sec / d_sec, 3),
-                   "velocity_rel_l2_err_dnnmg": round(err_dnn, 6),
-                   "velocity_rel_l2_err_mg_coarse": round(err_mgl, 6),
-                   "net": "trained on the GPU (teacher forcing + DAgger)" if train_info else "random init",
+                   "gmg_dof_updates_per_s": round(3 * nF * K / g_sec, 1),
+                   "timed": {"gmg": leg(g_stats, g_sec), "dnnmg": leg(d_stats, d_sec)},
+                   "eval_steps": E,
+                   "velocity_rel_err": {"dnnmg": err_d, "mg_coarse": err_l, "dnnmg_zero_net": err_z,
+                                        "l2_trace": trace,
+                                        "norms": "l2: mass-weighted (2x2 Gauss) on level F; nodal: over "
+                                                 "the level-F nodes; relative to the level-F reference"},
+                   "velocity_rel_l2_err_dnnmg": err_d["l2_mean"],
+                   "velocity_rel_l2_err_mg_coarse": err_l["l2_mean"],
+                   "sustained": {"gmg": leg(ref_stats, ref_sec), "mg_coarse": leg(mgl_stats, mgl_sec),
+                                 "dnnmg": leg(dnn_stats, dnn_sec)},
+                   "switch_off_newton": n_off,
+                   "switch_off_study": switchoff,
+                   "mixed_vs_fp64": fp64,
+                   "net": ("trained on the GPU on held-out geometries (teacher forcing + free-run rounds); "
+                           "the evaluated geometry is not in the training set") if train_info else "random init",
                    "net_training": train_info,
-                   "gmg_dof_updates_per_s": round(3 * nF * args.steps / g_sec, 1),
-                   "gmg_newton_iters": sum(s_["newton_iters"] for s_ in g_stats),
-                   "gmg_gmres_iters": sum(s_["gmres_iters"] for s_ in g_stats),
-                   "gmg_jacobian_builds": sum(s_["jacobian_builds"] for s_ in g_stats),
-                   "dnnmg_newton_iters": sum(s_["newton_iters"] for s_ in d_stats),
-                   "dnnmg_gmres_iters": sum(s_["gmres_iters"] for s_ in d_stats),
-                   "dnnmg_jacobian_builds": sum(s_["jacobian_builds"] for s_ in d_stats),
-                   "dnnmg_fallbacks": sum(s_["fallback"] for s_ in d_stats),
-                   "functionals_last_step": funcs,
                    "graphs": not args.no_graphs, "profile": args.profile,
-                   "newton_predictor": args.newton_predictor,
-                   "jacobian_reuse": args.jacobian_reuse, "smoother": args.smoother, "direct_solve_level": args.direct_level,
+                   "newton_predictor": args.newton_predictor, "jacobian_reuse": args.jacobian_reuse,
+                   "smoother": args.smoother, "direct_solve_level": args.direct_level,
                    "v_cycle": {"gmg": f"V(2,2), {args.nu_coarse or 'same'} below the top",
-                               "dnnmg": "V({},{}), V({c},{c}) below the top".format(
-                                   *args.dnnmg_sweeps.split(",")[:2], c=args.dnnmg_sweeps.split(",")[2])}},
+                               "mg_coarse_and_dnnmg": f"V({pre},{post}), V({coarse},{coarse}) below the top"}},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

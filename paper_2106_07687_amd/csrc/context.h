@@ -237,6 +237,7 @@ class Solver {
   bool will_defer(int l) const;
   void coarse_inverse();
   std::vector<OpLevel<T>> ops_;
+  DevBuf<T> cblk_;   // 12x12 cell blocks written by the assembly for the Vanka factorisation
   DevBuf<double> W_, prow_, colk_;
   int c_ = 0;    // level of the coarse direct solve
   int n0_ = 0;

@@ -378,101 +378,141 @@ __global__ void k_fill(T *__restrict__ a, size_t n, T v) {
   for (; i < n; i += stride) a[i] = v;
 }
 
-// A_n'(x) (eq. newton): one thread per node row; each of the node's cells
-// contributes row a of its element matrix, each of its patches row q of s_P.
-// Values are computed in FP64 and stored as T into the thread's own row
-// (zeroed beforehand), so there are no write conflicts.
+// A_n'(x) (eq. newton) in the node-row SELL layout, written once.  One
+// wavefront per slice of 64 node rows (lane = row): each of the row's cells
+// contributes row a of its element matrix (2x2 Gauss, FP64), each of its
+// patches row q of s_P.  A lane accumulates its own row in a private column of
+// LDS, acc[(k * 9 + r) * 64 + lane] for slot k and entry r of the 3x3 block
+// (plus the LPS-extra slots), so lanes never touch each other's data and no
+// barrier is needed; every contribution is added as
+// acc = T(double(acc) + value) in cell then patch order.  The slice's slots,
+// padding included, are then stored with one 64-lane contiguous store per
+// (slot, entry): no zero fill and no read-modify-write of the operator.
+// With cblk, the lane also copies, for each of its cells c (local vertex a),
+// its row restricted to the cell's 12 unknowns into the cell's 12x12 block:
+// cblk[144 c + 12 (3 a + f) + 3 b + g] (rows of the cell block contiguous,
+// for the Vanka factorisation).
+// Dynamic LDS: (maxwq * 9 + maxwx) * 64 * sizeof(T) bytes.
 template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
-                           const double *__restrict__ sP, T *__restrict__ JQ, T *__restrict__ JX) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.N) return;
-  const int s = i / kS, lane = i % kS;
-  const double th = ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
-  const size_t base = static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
-  const uint8_t fl = L.flag[i];
-  const bool dir = fl & 1;
-  for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
-    const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
-    const int4 cn = L.cells[c];
-    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
-    double X[4], Y[4], U[4], V[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double2 p = L.xy[nn[b]];
-      X[b] = p.x;
-      Y[b] = p.y;
-      U[b] = x[3 * nn[b]];
-      V[b] = x[3 * nn[b] + 1];
-    }
-    double blk[4][9];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) blk[b][k] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double N[4], gx[4], gy[4], det;
-      q1_point(X, Y, q, N, gx, gy, det);
-      double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
+                                                 const double *__restrict__ sP, T *__restrict__ JQ,
+                                                 T *__restrict__ JX, T *__restrict__ cblk) {
+  extern __shared__ unsigned char lds_raw[];
+  T *accq = reinterpret_cast<T *>(lds_raw);
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int i = s * kS + lane;
+  const int wq = L.wq[s], wx = L.wx[s];
+  T *accx = accq + static_cast<size_t>(wq) * 9 * kS;
+  for (int k = 0; k < 9 * wq; ++k) accq[k * kS + lane] = T(0);
+  for (int k = 0; k < wx; ++k) accx[k * kS + lane] = T(0);
+  auto add = [&](T *a, double v) { *a = static_cast<T>(static_cast<double>(*a) + v); };
+  if (i < L.N) {
+    const double th = ph.theta, nu = L.nnu ? L.nnu[i] : ph.nu, idt = ph.inv_dt;
+    const bool dir = L.flag[i] & 1;
+    for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
+      const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+      const int4 cn = L.cells[c];
+      const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+      double X[4], Y[4], U[4], V[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        u += N[b] * U[b];
-        v += N[b] * V[b];
-        ux += gx[b] * U[b];
-        uy += gy[b] * U[b];
-        vx += gx[b] * V[b];
-        vy += gy[b] * V[b];
+        const double2 p = L.xy[nn[b]];
+        X[b] = p.x;
+        Y[b] = p.y;
+        U[b] = x[3 * nn[b]];
+        V[b] = x[3 * nn[b] + 1];
       }
-      const double Na = N[a], ga = gx[a], ha = gy[a];
+      double blk[4][8];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) blk[b][k] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double N[4], gx[4], gy[4], det;
+        q1_point(X, Y, q, N, gx, gy, det);
+        double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          u += N[b] * U[b];
+          v += N[b] * V[b];
+          ux += gx[b] * U[b];
+          uy += gy[b] * U[b];
+          vx += gx[b] * V[b];
+          vy += gy[b] * V[b];
+        }
+        double Na = 0.0, ga = 0.0, ha = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (b == a) {
+            Na = N[b];
+            ga = gx[b];
+            ha = gy[b];
+          }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double Nb = N[b];
+          const double d = det * (idt * Nb * Na + th * (u * gx[b] + v * gy[b]) * Na +
+                                  th * nu * (gx[b] * ga + gy[b] * ha));
+          const double r = det * th * Nb * Na;
+          blk[b][0] += d + r * ux;       // (u,u)
+          blk[b][1] += r * uy;           // (u,v)
+          blk[b][2] -= det * Nb * ga;    // (u,p)
+          blk[b][3] += r * vx;           // (v,u)
+          blk[b][4] += d + r * vy;       // (v,v)
+          blk[b][5] -= det * Nb * ha;    // (v,p)
+          blk[b][6] += det * gx[b] * Na;  // (p,u)
+          blk[b][7] += det * gy[b] * Na;  // (p,v)
+        }
+      }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const double Nb = N[b];
-        const double d = det * (idt * Nb * Na + th * (u * gx[b] + v * gy[b]) * Na +
-                                th * nu * (gx[b] * ga + gy[b] * ha));
-        const double r = det * th * Nb * Na;
-        blk[b][0] += d + r * ux;   // (u,u)
-        blk[b][1] += r * uy;       // (u,v)
-        blk[b][2] -= det * Nb * ga;  // (u,p)
-        blk[b][3] += r * vx;       // (v,u)
-        blk[b][4] += d + r * vy;   // (v,v)
-        blk[b][5] -= det * Nb * ha;  // (v,p)
-        blk[b][6] += det * gx[b] * Na;  // (p,u)
-        blk[b][7] += det * gy[b] * Na;  // (p,v)
+        T *dst = accq + static_cast<size_t>(L.cslot[4 * e + b]) * 9 * kS + lane;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          if (dir && r < 6) continue;
+          add(dst + r * kS, blk[b][r]);
+        }
       }
     }
+    for (int e = L.padj_ptr[i]; e < L.padj_ptr[i + 1]; ++e) {
+      const int Pp = L.padj[e] / 9, q = L.padj[e] % 9;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int k = L.cslot[4 * e + b];
-      T *dst = JQ + base + static_cast<size_t>(k) * 9 * kS;
+      for (int m = 0; m < 9; ++m) {
+        const double v = sP[(9 * q + m) * L.NP + Pp];
+        const int sl = L.pslot[9 * e + m];
+        T *dst = (sl & 0x80) ? accx + (sl & 0x7f) * kS + lane : accq + (static_cast<size_t>(sl) * 9 + 8) * kS + lane;
+        add(dst, v);
+      }
+    }
+    if (dir) {
+      // identity velocity rows: the self slot holds 1 on (u,u) and (v,v)
+      for (int k = 0; k < wq; ++k)
+        if (L.colq[(L.oq[s] + k) * kS + lane] == i) {
+          accq[(k * 9) * kS + lane] = T(1);
+          accq[(k * 9 + 4) * kS + lane] = T(1);
+          break;
+        }
+    }
+  }
+  if (cblk && i < L.N) {
+    for (int e = L.cadj_ptr[i]; e < L.cadj_ptr[i + 1]; ++e) {
+      const int c = L.cadj[e] >> 2, a = L.cadj[e] & 3;
+      T *dst = cblk + static_cast<size_t>(c) * 144 + 36 * a;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        if (dir && r < 6) continue;
-        dst[r * kS] = static_cast<T>(static_cast<double>(dst[r * kS]) + blk[b][r]);
+      for (int b = 0; b < 4; ++b) {
+        const T *src = accq + static_cast<size_t>(L.cslot[4 * e + b]) * 9 * kS + lane;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+          for (int g = 0; g < 3; ++g) dst[12 * f + 3 * b + g] = src[(3 * f + g) * kS];
       }
     }
   }
-  const size_t xbase = static_cast<size_t>(L.ox[s]) * kS + lane;
-  for (int e = L.padj_ptr[i]; e < L.padj_ptr[i + 1]; ++e) {
-    const int Pp = L.padj[e] / 9, q = L.padj[e] % 9;
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      const double v = sP[(9 * q + m) * L.NP + Pp];
-      const int sl = L.pslot[9 * e + m];
-      T *dst = (sl & 0x80) ? JX + xbase + static_cast<size_t>(sl & 0x7f) * kS
-                           : JQ + base + (static_cast<size_t>(sl) * 9 + 8) * kS;
-      *dst = static_cast<T>(static_cast<double>(*dst) + v);
-    }
-  }
-  if (dir) {
-    // identity velocity rows: the self slot holds 1 on (u,u) and (v,v)
-    for (int k = 0; k < L.wq[s]; ++k)
-      if (L.colq[(L.oq[s] + k) * kS + lane] == i) {
-        JQ[base + static_cast<size_t>(k) * 9 * kS] = static_cast<T>(1);
-        JQ[base + (static_cast<size_t>(k) * 9 + 4) * kS] = static_cast<T>(1);
-        break;
-      }
-  }
+  T *oq = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+  for (int k = 0; k < 9 * wq; ++k) oq[static_cast<size_t>(k) * kS] = accq[k * kS + lane];
+  T *ox = JX + static_cast<size_t>(L.ox[s]) * kS + lane;
+  for (int k = 0; k < wx; ++k) ox[static_cast<size_t>(k) * kS] = accx[k * kS + lane];
 }
 
 // -------------------------------------------------------------- SpMV
@@ -670,12 +710,14 @@ __global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict_
 // -------------------------------------------------------------- Vanka
 // Factorisation of the 12x12 cell blocks J|_{c,c} (4 nodes x 3 fields) by
 // Gauss-Jordan elimination with partial pivoting.  A group of 16 lanes works
-// on one cell; lane r < 12 holds row r = 3 a + f.  Pivot search and pivot-row
-// broadcast use wavefront shuffles.  The inverse is stored SoA:
-// inv[(12 r + j) * C + c] (entry-major: each of the 144 loads of a wavefront
-// reads one contiguous 256-byte segment).
+// on one cell; lane r < 12 holds row r = 3 a + f, read from the cell blocks
+// the assembly wrote (cblk[144 c + 12 r + j]: a group reads 576 contiguous
+// bytes).  Pivot search and pivot-row broadcast use wavefront shuffles.  The
+// inverse is stored SoA: inv[(12 r + j) * C + c] (entry-major: each of the
+// 144 loads of a wavefront in the apply reads one contiguous 256-byte
+// segment).
 template <typename T>
-__global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ JQ, T *__restrict__ inv) {
+__global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ cblk, T *__restrict__ inv) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = gid >> 4;
   const int r = threadIdx.x & 15;
@@ -687,19 +729,9 @@ __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__re
     E[j] = (j == r) ? 1.0 : 0.0;
   }
   if (live) {
-    const int a = r / 3, f = r % 3;
-    const int4 cn = L.cells[c];
-    const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
-    const int na = nn[a];
-    const int s = na / kS, lane = na % kS;
-    const T *row = JQ + static_cast<size_t>(L.oq[s]) * 9 * kS + lane;
+    const T *row = cblk + static_cast<size_t>(c) * 144 + 12 * r;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int k = L.vslot[16 * c + 4 * a + b];
-#pragma unroll
-      for (int g = 0; g < 3; ++g)
-        A[3 * b + g] = static_cast<double>(row[(static_cast<size_t>(k) * 9 + 3 * f + g) * kS]);
-    }
+    for (int j = 0; j < 12; ++j) A[j] = static_cast<double>(row[j]);
   } else {
     if (r < 12) A[r] = 1.0;
   }

@@ -26,8 +26,18 @@ struct PatchView {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// gfx950 MFMA 16x16x32 BF16 -> FP32.  Operand layout: lane l supplies row
+// (or column) l % 16 and the 8 consecutive k = 8 (l / 16) .. 8 (l / 16) + 7 of
+// the 32-wide k step; the accumulator holds rows 4 (l / 16) .. + 3 of column
+// l % 16.  frag8 reads a lane's 8 BF16 with one 16-byte LDS load (rows of the
+// LDS tiles are 16-byte aligned and k offsets multiples of 8).
+__device__ __forceinline__ bf16x8 frag8(const uint16_t *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+__device__ __forceinline__ f32x4 mfma32(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -42,7 +52,7 @@ __device__ __forceinline__ float sigmoidf_(float a) { return 1.0f / (1.0f + __ex
 // C[M x N] (fp32, ldc) = A[M x K] * B[N x K]^T (+ C if accumulate), A and B
 // BF16 row-major with leading dimensions lda, ldb (elements, multiples of 8),
 // K a multiple of 32.  64 x 64 tile per workgroup of 256 threads (4 waves,
-// each 32 x 32 as 2 x 2 MFMA 16x16x16 blocks), BK = 32 staged through LDS.
+// each 32 x 32 as 2 x 2 MFMA 16x16x32 blocks), BK = 32 staged through LDS.
 constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
 
 __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const uint16_t *__restrict__ A,
@@ -69,23 +79,18 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const
     *reinterpret_cast<uint4 *>(&Bs[lr][lc]) = vb;
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      bf16x4 a[2], b[2];
-      const int kq = kk + 4 * (lane >> 4);
+    for (int kk = 0; kk < GBK; kk += 32) {
+      bf16x8 a[2], b[2];
+      const int kq = kk + 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
-        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
-        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
-                      static_cast<short>(pa[3])};
-        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
-                      static_cast<short>(pb[3])};
+        a[i] = frag8(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+        b[i] = frag8(&Bs[wn * 32 + i * 16 + (lane & 15)][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
   }
 #pragma unroll
@@ -106,11 +111,11 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16(int M, int N, int K, const
 }
 
 // The same product with a 128 x 128 tile per workgroup (4 waves, each 64 x 64
-// as 4 x 4 MFMA 16x16x16 blocks) and 64-wide K chunks, the next chunk loaded
+// as 4 x 4 MFMA 16x16x32 blocks) and 64-wide K chunks, the next chunk loaded
 // into registers while the current one is multiplied out of LDS: four times
 // the MFMA work per LDS byte and a quarter of the barriers, for products
 // with enough tiles to fill the chip.  Every element's MFMA sequence over K
-// (16-wide steps in order; a chunk past K is cut at K, a multiple of 32) is
+// (32-wide steps in order; a chunk past K is cut at K, a multiple of 32) is
 // that of k_gemm_nt_bf16, so the two give bitwise the same C.
 constexpr int GBM2 = 128, GBN2 = 128, GBK2 = 64;
 __global__ void __launch_bounds__(256) k_gemm_nt_bf16_128(int M, int N, int K, const uint16_t *__restrict__ A,
@@ -154,24 +159,19 @@ __global__ void __launch_bounds__(256) k_gemm_nt_bf16_128(int M, int N, int K, c
     if (k0 + GBK2 < K) load(k0 + GBK2);
     const int kend = min(GBK2, K - k0);
 #pragma unroll
-    for (int kk = 0; kk < GBK2; kk += 16) {
+    for (int kk = 0; kk < GBK2; kk += 32) {
       if (kk >= kend) break;
-      bf16x4 a[4], b[4];
-      const int kq = kk + 4 * (lane >> 4);
+      bf16x8 a[4], b[4];
+      const int kq = kk + 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint16_t *pa = &As[wm * 64 + i * 16 + (lane & 15)][kq];
-        const uint16_t *pb = &Bs[wn * 64 + i * 16 + (lane & 15)][kq];
-        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
-                      static_cast<short>(pa[3])};
-        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
-                      static_cast<short>(pb[3])};
+        a[i] = frag8(&As[wm * 64 + i * 16 + (lane & 15)][kq]);
+        b[i] = frag8(&Bs[wn * 64 + i * 16 + (lane & 15)][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
   }
 #pragma unroll
@@ -207,7 +207,7 @@ inline void launch_gemm_nt(hipStream_t s, int M, int N, int K, const uint16_t *A
 
 // One GRU time step of a layer (gate rows r, z, n): the recurrent product
 // Gh = h_in W_hh^T for a tile of 64 rows x 32 hidden units and all three
-// gates (MFMA 16x16x16 BF16, the K loop in 32-wide chunks as in
+// gates (MFMA 16x16x32 BF16, the K loop in 32-wide chunks as in
 // k_gemm_nt_bf16), then, on the accumulators, with Gi = x W_ih^T from that
 // kernel: r = s(gi_r + gh_r), z = s(gi_z + gh_z), n = tanh(gi_n + r gh_n),
 // h = (1 - z) n + z h_in (FP32; h may be hin), its BF16 copy into hb_out (not
@@ -248,20 +248,13 @@ __global__ void __launch_bounds__(256) k_gru_step_fused(int B, int H, const floa
     if (lr < 32) *reinterpret_cast<uint4 *>(&Bs[64 + lr][lc]) = vb1;
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-      const uint16_t *pa = &As[wave * 16 + (lane & 15)][kq];
-      const bf16x4 a = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
-                              static_cast<short>(pa[3])};
+    for (int kk = 0; kk < GBK; kk += 32) {
+      const int kq = kk + 8 * (lane >> 4);
+      const bf16x8 a = frag8(&As[wave * 16 + (lane & 15)][kq]);
 #pragma unroll
       for (int g = 0; g < 3; ++g)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const uint16_t *pb = &Bs[g * 32 + j * 16 + (lane & 15)][kq];
-          const bf16x4 b = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]),
-                                  static_cast<short>(pb[2]), static_cast<short>(pb[3])};
-          acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[g][j], 0, 0, 0);
-        }
+        for (int j = 0; j < 2; ++j) acc[g][j] = mfma32(a, frag8(&Bs[g * 32 + j * 16 + (lane & 15)][kq]), acc[g][j]);
     }
   }
 #pragma unroll
@@ -421,23 +414,18 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_strided(int M, int N, int K, 
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      bf16x4 a[2], b[2];
-      const int kq = kk + 4 * (lane >> 4);
+    for (int kk = 0; kk < GBK; kk += 32) {
+      bf16x8 a[2], b[2];
+      const int kq = kk + 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
-        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
-        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
-                      static_cast<short>(pa[3])};
-        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
-                      static_cast<short>(pb[3])};
+        a[i] = frag8(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+        b[i] = frag8(&Bs[wn * 32 + i * 16 + (lane & 15)][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
   }
   float *Cz = Cm + blockIdx.z * zstride;
@@ -507,23 +495,18 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_tn(int M, int N, int Nl, int 
     __syncthreads();
     if (k0 + GBK < ke) load(k0 + GBK);
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      bf16x4 a[2], b[2];
-      const int kq = kk + 4 * (lane >> 4);
+    for (int kk = 0; kk < GBK; kk += 32) {
+      bf16x8 a[2], b[2];
+      const int kq = kk + 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
-        const uint16_t *pb = &Bs[wn * 32 + i * 16 + (lane & 15)][kq];
-        a[i] = bf16x4{static_cast<short>(pa[0]), static_cast<short>(pa[1]), static_cast<short>(pa[2]),
-                      static_cast<short>(pa[3])};
-        b[i] = bf16x4{static_cast<short>(pb[0]), static_cast<short>(pb[1]), static_cast<short>(pb[2]),
-                      static_cast<short>(pb[3])};
+        a[i] = frag8(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+        b[i] = frag8(&Bs[wn * 32 + i * 16 + (lane & 15)][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
   }
   float *Cz = Cm + blockIdx.z * zstride;

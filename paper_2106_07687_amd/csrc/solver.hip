@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "context.h"
@@ -293,12 +294,31 @@ int Solver<T>::ctx_coarse_sweeps() const {
   return ctx_->prm.nu_coarse;
 }
 
+namespace {
+// HIP graph calls (capture, instantiate, launch, destroy) are made under one
+// process-wide lock: simulation batches step their groups from several host
+// threads at once, and the library does not rely on the graph API being safe
+// to call concurrently.
+std::mutex &graph_api_mutex() {
+  static std::mutex m;
+  return m;
+}
+}  // namespace
+
+// Executables launched earlier may still run on the context's stream: it is
+// synchronised before any of them is destroyed.
 template <typename T>
 void Solver<T>::clear_graphs() {
-  for (auto &kv : vgraphs_)
-    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  bool any = ginv_.exec != nullptr;
+  for (auto &kv : vgraphs_) any = any || kv.second.exec != nullptr;
+  if (any) {
+    (void)hipStreamSynchronize(ctx_->stream);
+    std::lock_guard<std::mutex> lock(graph_api_mutex());
+    for (auto &kv : vgraphs_)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (ginv_.exec) (void)hipGraphExecDestroy(ginv_.exec);
+  }
   vgraphs_.clear();
-  if (ginv_.exec) (void)hipGraphExecDestroy(ginv_.exec);
   ginv_ = GraphSlot{};
 }
 
@@ -316,9 +336,14 @@ bool Solver<T>::use_graph(int level) const {
 template <typename T>
 template <class F>
 void Solver<T>::graph_run(GraphSlot &g, F &&body) {
-  if (!g.exec || g.gen != ctx_->graph_gen) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.exec && g.gen != ctx_->graph_gen) {   // stale: wait for its last launch, then destroy it
+    check(hipStreamSynchronize(ctx_->stream), "graph sync");
+    std::lock_guard<std::mutex> lock(graph_api_mutex());
+    (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
+  }
+  std::lock_guard<std::mutex> lock(graph_api_mutex());
+  if (!g.exec) {
     hipStream_t cap = ctx_->capture_stream();
     hipStream_t saved = ctx_->stream;
     const bool prof_on = ctx_->prof.on;
@@ -368,6 +393,9 @@ void Solver<T>::setup(int finest) {
     o.x.alloc(3 * static_cast<size_t>(h.N));
     o.t.alloc(3 * static_cast<size_t>(h.N));
   }
+  // cell blocks of the Vanka factorisation, shared by the levels (each level
+  // is assembled and factorised before the next)
+  cblk_.alloc(static_cast<size_t>(144) * ctx_->levels[finest]->h.C);
   // the direct solve at the bottom of the V-cycle: level c_ (0 unless set)
   c_ = ctx_->prm.coarse_level;
   if (c_ > finest) throw DnnmgError{DNNMG_EINVAL, "coarse_level above the finest level"};
@@ -662,18 +690,19 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
     const double *sP = ctx_->ensure_lps(l, dt, l < level ? 1 : 0);
     DevLevel &L = *ctx_->levels[l];
     OpLevel<T> &o = ops_[l];
-    hipLaunchKernelGGL(k_fill<T>, dim3(1024), dim3(256), 0, s, o.JQ.p, o.JQ.n, T(0));
-    hipLaunchKernelGGL(k_fill<T>, dim3(256), dim3(256), 0, s, o.JX.p, o.JX.n, T(0));
     {
+      // one wavefront per slice, the slice's rows accumulated in LDS
+      const size_t lds = static_cast<size_t>(L.h.maxwq * 9 + L.h.maxwx) * kS * sizeof(T);
+      if (lds > 65536) throw DnnmgError{DNNMG_EINVAL, "node rows too wide for the LDS assembly"};
       ProfScope ps(ctx_->prof, s, "assemble", l);
-      hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(L.h.N, 64)), dim3(64), 0, s, L.view(),
-                         ctx_->phys(dt, 0.0), x_dev, sP, o.JQ.p, o.JX.p);
+      hipLaunchKernelGGL(k_assemble<T>, dim3(L.h.nslice), dim3(kS), lds, s, L.view(), ctx_->phys(dt, 0.0), x_dev,
+                         sP, o.JQ.p, o.JX.p, full && l > c_ ? cblk_.p : nullptr);
     }
     LAUNCH_CHECK("k_assemble");
     if (full && l > c_) {
       ProfScope ps(ctx_->prof, s, "vanka_factor", l);
       hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 16, 256)),
-                         dim3(256), 0, s, L.view(), o.JQ.p, o.inv.p);
+                         dim3(256), 0, s, L.view(), cblk_.p, o.inv.p);
       LAUNCH_CHECK("k_vanka_factor");
     }
   }

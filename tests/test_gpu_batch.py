@@ -101,3 +101,56 @@ def test_batch_set_get_is_per_member():
         x, t = batch.get(j)
         assert np.array_equal(x, xs[j]) and t == 0.5
     batch.close()
+
+
+# config 3's depths: seeds with depth 4 (two members: one group of two), 5, 6, 7
+DEEP = [(102, 4), (111, 4), (103, 5), (105, 6), (100, 7)]
+
+
+def test_batch_at_config3_depths_follows_lone_runs():
+    """Members at config 3's depths 4-7 (seeds 102 and 111 at depth 4, 103 at
+    5, 105 at 6 and 100, three obstacles, at 7; Re 60-198): in mixed
+    precision every member of the batch follows its lone context's trajectory
+    to 1e-5 relative L2 per field over two steps of dt 0.005."""
+    import paper_2106_07687_amd as P
+    macros = [channel_obstacles(s) for s, _ in DEEP]
+    assert [m.info["depth"] for m in macros] == [d for _, d in DEEP]
+    batch = P.Batch([(m, m.nu, d) for m, (_, d) in zip(macros, DEEP)], precision=1)
+    infos = [batch.group_info(g) for g in range(batch.n_groups())]
+    print(f"[batch-deep] groups {infos}", flush=True)
+    assert sorted(i["depth"] for i in infos) == [4, 5, 6, 7]
+    lone = []
+    for m, (_, d) in zip(macros, DEEP):
+        ctx = P.Context(precision=1, nu=m.nu)
+        ctx.setup_mesh(m, d)
+        lone.append((ctx, ctx.state(d)))
+    for k in range(2):
+        stats = batch.step(0.005)
+        assert all(s["converged"] == 1 for s in stats), stats
+        for j, (ctx, st) in enumerate(lone):
+            ctx.step(st, 0.005)
+            err = _fields(batch.get(j)[0], st.get()[0])
+            print(f"[batch-deep] step {k} seed {DEEP[j][0]} depth {DEEP[j][1]}: rel {err:.2e}", flush=True)
+            assert err <= 1e-5, (k, j, err)
+    for ctx, st in lone:
+        st.close()
+        ctx.close()
+    batch.close()
+
+
+def test_batch_depth4_member_matches_oracle():
+    """FP64 batch of the two depth-4 members of config 3 (seeds 102, 111):
+    the first member's first step equals the oracle's direct Newton step to
+    1e-10 relative L2 per field (GPU Newton 1e-14; oracle floor 4e-17)."""
+    import paper_2106_07687_amd as P
+    macros = [channel_obstacles(s) for s, _ in DEEP[:2]]
+    batch = P.Batch([(m, m.nu, 4) for m in macros], precision=0, newton_tol=1e-14)
+    assert batch.n_groups() == 1
+    batch.step(DT)
+    L = mesh.hierarchy(macros[0], 4)[4]
+    prob = fem.Problem(nu=macros[0].nu, dt=DT)
+    x = solver.newton_step(L, prob, np.zeros(3 * L.n_nodes), DT, tol=1e-15)
+    err = _fields(batch.get(0)[0], x)
+    print(f"[batch-deep] depth-4 member vs oracle: rel {err:.2e}", flush=True)
+    assert err <= 1e-10
+    batch.close()
