@@ -387,6 +387,20 @@ int dnnmg_functionals_host(dnnmg_ctx *ctx, int level, const double *uvp, double 
 int dnnmg_velocity_error(dnnmg_ctx *ctx, int level, const double *x_dev, int ref_level, const double *ref_dev,
                          double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * dnnmg_velocity_error for a field on the reference's own level, allocating
+ * nothing.  Its reduction's partial sums live in a fixed static device array
+ * of the library (1 MiB per GPU, held until the process ends) instead of
+ * memory the context allocates; the four sums (same order and meaning as
+ * dnnmg_velocity_error's out) are written to out_dev, a device pointer to 4
+ * doubles.  Enqueued on the context's stream without synchronisation.  Limit:
+ * max(cells, nodes) of the level at most 8,388,352 (32,767 workgroups of 256
+ * threads), else DNNMG_EINVAL.  All calls on one GPU share the array:
+ * overlapping calls (other threads or streams) race. */
+int dnnmg_velocity_error_noalloc(dnnmg_ctx *ctx, int level, const double *x_dev, const double *ref_dev,
+                                 double *out_dev);
+
 /* ------------------------------------------------------------------ batches
  * Many independent simulations of the plain method (Sec. 2: each one the
  * time step of eqs. nonlinearshort/newton on its own mesh and viscosity),

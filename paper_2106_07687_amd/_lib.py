@@ -122,6 +122,7 @@ _SIGS = {
     "dnnmg_functionals_host": (C.c_int, [_P, C.c_int, _DP, _DP, _DP, _DP, C.c_int]),
     "dnnmg_velocity_error": (C.c_int, [_P, C.c_int, _P, C.c_int, _P, _DP]),
     "dnnmg_net_fine_velocity": (C.c_int, [_P, C.POINTER(_P)]),
+    "dnnmg_velocity_error_noalloc": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "dnnmg_profile_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "dnnmg_level_stats": (C.c_int, [_P, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
                                     C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
@@ -320,6 +321,12 @@ class Context:
         out = np.zeros(4)
         self._check(self.lib.dnnmg_velocity_error(self.h, level, x_ptr, ref_level, ref_ptr, _dp(out)))
         return dict(zip(("l2_err2", "l2_ref2", "nodal_err2", "nodal_ref2"), (float(v) for v in out)))
+
+    def velocity_error_noalloc(self, level, x_ptr, ref_ptr, out_ptr):
+        """dnnmg_velocity_error_noalloc: the four sums of velocity_error for
+        device fields on `level`, written to the device pointer out_ptr
+        (4 doubles), enqueued without synchronisation."""
+        self._check(self.lib.dnnmg_velocity_error_noalloc(self.h, level, x_ptr, ref_ptr, out_ptr))
 
     def launch_config(self, level):
         """Workgroup sizes {spmv, vanka_apply, vanka_update, restrict, prolong,

@@ -4,9 +4,19 @@
 #include <cstdio>
 #include <cstring>
 
+#include <mutex>
+
 #include "context.h"
 
 using namespace dnnmg;
+
+// Scratch of dnnmg_velocity_error_noalloc: the per-workgroup partial sums of
+// its reduction (4 doubles per workgroup of 256 threads).  One copy per GPU,
+// held until the process ends.  Host code never passes this name to a
+// kernel: the device address of each GPU's copy is taken with
+// hipGetSymbolAddress (scratch_address) and used instead.
+static constexpr int kScratchDoubles = 131072;   // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -30,6 +40,26 @@ int guarded(dnnmg_ctx *ctx, F &&f) {
 int fail(dnnmg_ctx *ctx, int code, const char *msg) {
   if (ctx) ctx->impl.last_error = msg;
   return code;
+}
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) on the first allocation-free call
+// there.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double *scratch_ptr[kMaxDevices] = {};
+
+double *scratch_address() {
+  int dev = 0;
+  check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) throw DnnmgError{DNNMG_EDEVICE, "device index out of range"};
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  return scratch_ptr[dev];
 }
 
 bool params_ok(const dnnmg_params *p) {
@@ -800,6 +830,25 @@ int dnnmg_velocity_error(dnnmg_ctx *ctx, int level, const double *x_dev, int ref
     return fail(ctx, DNNMG_EINVAL, "velocity_error: need 0 <= level <= ref_level and non-null pointers");
   return guarded(ctx, [&]() {
     ctx->impl.velocity_error(level, x_dev, ref_level, ref_dev, out);
+    return DNNMG_OK;
+  });
+}
+
+int dnnmg_velocity_error_noalloc(dnnmg_ctx *ctx, int level, const double *x_dev, const double *ref_dev,
+                                 double *out_dev) {
+  const int e = check_level(ctx, level);
+  if (e) return e;
+  if (!x_dev || !ref_dev || !out_dev) return fail(ctx, DNNMG_EINVAL, "velocity_error_noalloc: null pointer");
+  const DevLevel &R = *ctx->impl.levels[level];
+  const int nb = blocks(std::max(R.h.C, R.h.N), 256);
+  if (4 * static_cast<size_t>(nb) > static_cast<size_t>(kScratchDoubles))
+    return fail(ctx, DNNMG_EINVAL, "velocity_error_noalloc: level larger than the static scratch allows");
+  return guarded(ctx, [&]() {
+    double *partial = scratch_address();
+    hipStream_t s = ctx->impl.stream;
+    hipLaunchKernelGGL(k_vel_error_partial, dim3(nb), dim3(256), 0, s, R.view(), x_dev, ref_dev, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(4), dim3(256), 0, s, nb, 4, partial, out_dev);
+    check(hipGetLastError(), "velocity_error_noalloc");
     return DNNMG_OK;
   });
 }
