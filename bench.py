@@ -466,7 +466,9 @@ def train_on_geometries(P, args, log, stream):
         ctx = make_context(P, macro, args, stream.cuda_stream)
         ctx.setup_mesh(macro, F)
         net = P.Net(ctx, L, m, args.hidden, args.layers)
-        x0, t0 = spin_up(ctx, L, F, args.t_dev, args.relax, dt, log, f"train seed {seed} (Re {0.1 / macro.nu:.1f})")
+        # staggered start times, so that the training states cover the evaluation window
+        x0, t0 = spin_up(ctx, L, F, args.t_dev + args.train_stagger * k, args.relax, dt, log,
+                         f"train seed {seed} (Re {0.1 / macro.nu:.1f})")
         sf = ctx.state(F)
         sf.set(x0, t0)
         xF = [x0]
@@ -500,7 +502,9 @@ def train_on_geometries(P, args, log, stream):
         w = net0.get_weights()
         Xc_all, Dc_all = [], []
         for g in geoms:
-            ctx, net, x0, t0 = g["ctx"], g["net"], g["xF"][0], g["t0"]
+            # each round starts its free runs further along the geometry's fine trajectory
+            k0 = min(20 * (rnd + 1), len(g["xF"]) - 1)
+            ctx, net, x0, t0 = g["ctx"], g["net"], g["xF"][k0], g["t0"] + k0 * dt
             if net is not net0:
                 net.set_weights(w, mu=mu, sigma=sg, out_scale=osc)
             nL = ctx.level_info(L)[0]
@@ -537,7 +541,7 @@ def train_on_geometries(P, args, log, stream):
             f"{data.X.shape[1]} sequences")
     w = net0.get_weights()
     info = {"geometries": [{"seed": g["seed"], "re": g["re"]} for g in geoms],
-            "t_start": round(geoms[0]["t0"], 4), "fine_steps_per_geometry": args.train_steps,
+            "t_start": [round(g["t0"], 4) for g in geoms], "fine_steps_per_geometry": args.train_steps,
             "sequences": int(data.X.shape[1]), "seq": seq, "batch": data.B, "rounds": 1 + args.dagger,
             "free_run_steps_per_round": args.dagger_steps,
             "adam_iters": fit_its, "final_loss": round(float(loss), 4),
@@ -715,6 +719,66 @@ def run_table1(P, args, log):
 
 
 
+def eval_geometry(P, args, macro, net_state, log, stream, tag):
+    """Error window on another geometry (held-out evaluation): developed flow,
+    the level-F reference over eval_steps steps, then MG(L), DNN-MG with the
+    trained network and DNN-MG with d = 0 over the same window; mean / last
+    mass-weighted and nodal errors of each against the reference."""
+    import numpy as np
+    import torch
+    L, F, dt, E = args.coarse_level, args.level, args.dt, args.eval_steps
+    pre, post, coarse = (int(v) for v in args.dnnmg_sweeps.split(","))
+    w_net, mu, sg, osc = net_state
+    ctx = make_context(P, macro, args, stream.cuda_stream)
+    ctx.setup_mesh(macro, F)
+    nF, nL = ctx.level_info(F)[0], ctx.level_info(L)[0]
+    x7, t7 = spin_up(ctx, L, F, args.t_dev, args.relax, dt, log, tag)
+    ref = torch.empty((E, 3 * nF), dtype=torch.float64, device="cuda")
+    sf = ctx.state(F)
+    sf.set(x7, t7)
+    for n in range(E):
+        ctx.step(sf, dt)
+        sf.get_dev(ref[n].data_ptr())
+    stream.synchronize()
+    sf.close()
+    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse)
+    out = {"re": round(0.1 / macro.nu, 2), "obstacles": int(len(macro.curves)), "t_start": round(t7, 4)}
+    sc = ctx.state(L)
+    sc.set(x7[:3 * nL], t7)
+    errs, newton = [], []
+    for n in range(E):
+        newton.append(ctx.step(sc, dt)["newton_iters"])
+        errs.append(rel_errors(ctx.velocity_error(L, sc.device_ptr(), F, ref[n].data_ptr())))
+    sc.close()
+    out["mg_coarse"] = err_summary(errs)
+    n_off = max(1, int(round(2 * np.median(newton[:10]))))
+    ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse, switch_off_newton=n_off)
+    for name, weights in (("dnnmg", w_net), ("dnnmg_zero_net", None)):
+        net = P.Net(ctx, L, F - L, args.hidden, args.layers)
+        if weights is None:
+            net.set_weights(np.zeros(net.n_params, dtype=np.float32), mu=np.zeros(10), sigma=np.ones(10),
+                            out_scale=np.ones(2))
+        else:
+            net.set_weights(weights, mu=mu, sigma=sg, out_scale=osc)
+        sc = ctx.state(L)
+        sc.set(x7[:3 * nL], t7)
+        net.reset(sc)
+        net.rhs_from_fine(sc, x7, dt)
+        errs, fallbacks = [], 0
+        for n in range(E):
+            fallbacks += ctx.step(sc, dt)["fallback"]
+            net.correct(sc, dt)
+            errs.append(rel_errors(ctx.velocity_error(F, net.fine_velocity_ptr(), F, ref[n].data_ptr())))
+        sc.close()
+        net.close()
+        out[name] = dict(err_summary(errs), fallbacks=fallbacks)
+    del ref
+    ctx.close()
+    torch.cuda.empty_cache()
+    log(f"{tag}: {out}")
+    return out
+
+
 def clocked(stream, fn):
     """Runs fn() between two stream synchronisations; (result, seconds)."""
     stream.synchronize()
@@ -762,6 +826,8 @@ def main():
                     help="train the patch network on held-out geometries (untimed); 0: random weights")
     ap.add_argument("--train-geoms", type=int, default=4, help="training geometries (seeds train-seed0..)")
     ap.add_argument("--train-seed0", type=int, default=200)
+    ap.add_argument("--train-stagger", type=float, default=0.25,
+                    help="training geometry k starts its fine trajectory at t_dev + k * stagger")
     ap.add_argument("--train-steps", type=int, default=64, help="fine steps per training geometry")
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
@@ -771,6 +837,9 @@ def main():
                          "fine step started from the run's own state)")
     ap.add_argument("--dagger-steps", type=int, default=64)
     ap.add_argument("--dagger-iters", type=int, default=300)
+    ap.add_argument("--extra-eval-seeds", default="",
+                    help="comma-separated channel seeds (e.g. 300,301,302,303) evaluated like the main "
+                         "geometry (error window only) with the same trained network")
     ap.add_argument("--zero-net-control", type=int, default=1, choices=(0, 1),
                     help="also run the DNN-MG window with a zero network (d = 0): the coupling's own error")
     ap.add_argument("--switchoff-study", type=int, default=0, choices=(0, 1),
@@ -1059,6 +1128,12 @@ def main():
     net.close()
     ctx.close()
     torch.cuda.empty_cache()
+    held_out = None
+    if args.extra_eval_seeds and args.train_net:
+        from synthetic import channel_obstacle as geom
+        held_out = {s_: eval_geometry(P, args, geom(int(s_)), (w_net, mu, sg, osc), log, stream,
+                                      f"held-out seed {s_}")
+                    for s_ in args.extra_eval_seeds.split(",")}
     batch_info = run_batch(P, args, log) if args.batch_sims > 0 else None
     table1 = run_table1(P, args, log) if args.table1 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(args, log)
@@ -1094,6 +1169,7 @@ def main():
                    "sustained": {"gmg": leg(ref_stats, ref_sec), "mg_coarse": leg(mgl_stats, mgl_sec),
                                  "dnnmg": leg(dnn_stats, dnn_sec)},
                    "switch_off_newton": n_off,
+                   "held_out_geometries": held_out,
                    "switch_off_study": switchoff,
                    "mixed_vs_fp64": fp64,
                    "net": ("trained on the GPU on held-out geometries (teacher forcing + free-run rounds); "

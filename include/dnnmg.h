@@ -137,6 +137,17 @@ typedef struct {
                              a solve on a level below k is DNNMG_EINVAL.  Fixed
                              at creation, at most 2, and 0 for batches        */
   void *stream;           /* hipStream_t, or NULL for the default stream       */
+  double delta0;          /* convective stabilisation (an optional member of the
+                             local-projection family of Sec. 2.1; the paper's
+                             method has none): 0 (default) off; > 0 adds
+                             delta_T (kappa_T(b.grad v), kappa_T(b.grad phi))_T
+                             to both velocity rows of A_n, kappa_T g = g minus
+                             its mean over cell T, b the mean of the old
+                             velocity over the cell's nodes (frozen, so the
+                             Jacobian is exact), delta_T = delta0 / (nu / h_T^2
+                             + |b| / h_T), h_T^2 = area(T); every level uses it
+                             (dnnmg_linearize takes the state's own velocity
+                             as b)                                            */
 } dnnmg_params;
 
 /* Macro (coarsest) mesh.  Level 0 is this mesh refined once; finer levels are

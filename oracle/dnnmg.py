@@ -253,7 +253,7 @@ def dnnmg_residual(levels, prob, L, x, x_old, bL, t_new):
     z = np.zeros_like(x)
     # f(x_old=0) - A(x) = -A_impl(x) because every old-state term is linear
     # in x_old and vanishes for x_old = 0
-    R = fem.residual(Lv, prob, x, z, t_new).reshape(-1, 3)
+    R = fem.residual(Lv, prob, x, z, t_new, x_conv=x_old).reshape(-1, 3)
     dn = Lv.dirichlet_nodes()
     Rb = bL.reshape(-1, 3)
     R[~dn, :2] += Rb[~dn, :2]
@@ -274,6 +274,6 @@ def dnnmg_newton(levels, prob, L, x_old, bL, t_new, tol=1e-10, maxit=20):
         R = dnnmg_residual(levels, prob, L, x, x_old, bL, t_new)
         if np.linalg.norm(R) <= tol:
             return x
-        J = fem.jacobian(Lv, prob, x)
+        J = fem.jacobian(Lv, prob, x, x_old)
         x = x + spla.spsolve(J.tocsc(), R)
     raise RuntimeError("DNN-MG Newton did not converge")

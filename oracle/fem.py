@@ -79,6 +79,7 @@ class Problem:
     H: float = CHANNEL_H
     u_mean: float = 1.0
     lps_mode: str = "paper"                 # "paper": alpha0 h^2/nu; "bounded": alpha0/(nu/h^2 + 1/k)
+    delta0: float = 0.0                     # convective stabilisation scale (0: off, the paper's method)
     force: Optional[Callable] = None        # f(x, y, t) -> (fx, fy)
     dirichlet: Optional[Callable] = None    # g(x, y, t) -> (u, v) on Dirichlet nodes
 
@@ -165,6 +166,30 @@ def _lps_patch_matrices(level: Level, prob: Problem, det, grad):
     return np.einsum('mi,pmn,nj->pij', K, SP, K)
 
 
+def convective_matrices(level: Level, prob: Problem, x_old: np.ndarray) -> np.ndarray:
+    """(C, 4, 4) cell matrices of the convective stabilisation (an optional
+    member of the local-projection family of Sec. 2.1, off unless delta0 > 0):
+
+        s_T(v, phi) = delta_T (kappa_T(b_T . grad v), kappa_T(b_T . grad phi))_T,
+
+    kappa_T g = g - (mean of g over T), b_T the mean of the old velocity over
+    the cell's 4 nodes (frozen: the term is linear in v, its Jacobian exact),
+    delta_T = delta0 / (nu / h_T^2 + |b_T| / h_T), h_T^2 = area(T), 2x2 Gauss.
+    Entry [c, a, b] multiplies the component's value at node b in the row of
+    node a; the same matrix acts on u and on v."""
+    det, grad = geometry(level.xy, level.cells)
+    Vo = x_old.reshape(-1, 3)[level.cells][:, :, :2]            # (C, 4, 2)
+    bT = Vo.mean(axis=1)                                          # (C, 2)
+    area = det.sum(axis=1)
+    h = np.sqrt(area)
+    bn = np.linalg.norm(bT, axis=1)
+    delta = prob.delta0 / (prob.nu / area + bn / h)
+    psi = np.einsum('cd,cqad->cqa', bT, grad)                     # b . grad N_a at each point
+    mean = np.einsum('cq,cqa->ca', det, psi) / area[:, None]
+    kpsi = psi - mean[:, None, :]
+    return delta[:, None, None] * np.einsum('cq,cqa,cqb->cab', det, kpsi, kpsi)
+
+
 def _forcing(level, prob, t_new):
     C = level.n_cells
     if prob.force is None:
@@ -178,9 +203,10 @@ def _forcing(level, prob, t_new):
 
 
 def residual(level: Level, prob: Problem, x: np.ndarray, x_old: np.ndarray,
-             t_new: float) -> np.ndarray:
+             t_new: float, x_conv: Optional[np.ndarray] = None) -> np.ndarray:
     """R = f_n - A_n(x) (eqs. varform, varformv); Dirichlet velocity rows hold
-    g(t_new) - x."""
+    g(t_new) - x.  With delta0 > 0 the convective stabilisation's frozen field
+    comes from x_conv (x_old if not given)."""
     cells = level.cells
     det, grad = geometry(level.xy, cells)
     X = x.reshape(-1, 3)[cells]                          # (C, 4a, 3)
@@ -208,6 +234,10 @@ def residual(level: Level, prob: Problem, x: np.ndarray, x_old: np.ndarray,
     pat = level.patches()
     pp = x.reshape(-1, 3)[pat, 2]                        # (P, 9)
     np.add.at(A[:, 2], pat, np.einsum('pij,pj->pi', sP, pp))
+    if prob.delta0 > 0:
+        Sc = convective_matrices(level, prob, x_old if x_conv is None else x_conv)
+        sc = np.einsum('cab,cbf->caf', Sc, X[:, :, :2])
+        np.add.at(A[:, :2], cells, sc)
     R = -A
     dn = level.dirichlet_nodes()
     g = dirichlet_values(level, prob, t_new)
@@ -216,9 +246,10 @@ def residual(level: Level, prob: Problem, x: np.ndarray, x_old: np.ndarray,
     return R.reshape(-1)
 
 
-def jacobian(level: Level, prob: Problem, x: np.ndarray) -> sp.csr_matrix:
+def jacobian(level: Level, prob: Problem, x: np.ndarray, x_old: Optional[np.ndarray] = None) -> sp.csr_matrix:
     """Analytic Jacobian A_n'(x) (eq. newton), as a CSR matrix on interleaved dofs.
-    Dirichlet velocity rows are identity rows."""
+    Dirichlet velocity rows are identity rows.  With delta0 > 0 the convective
+    stabilisation's frozen field comes from x_old (x itself if not given)."""
     cells = level.cells
     C = level.n_cells
     det, grad = geometry(level.xy, cells)
@@ -240,6 +271,10 @@ def jacobian(level: Level, prob: Problem, x: np.ndarray) -> sp.csr_matrix:
         Je[:, :, f, :, 2] -= np.einsum('cq,qb,cqa->cab', det, NQ, grad[:, :, :, f])
         Je[:, :, 2, :, f] += np.einsum('cq,qa,cqb->cab', det, NQ, grad[:, :, :, f])
     dof = (3 * cells[:, :, None] + np.arange(3)[None, None, :]).reshape(C, 12)
+    if prob.delta0 > 0:
+        Sc = convective_matrices(level, prob, x if x_old is None else x_old)
+        for f in range(2):
+            Je[:, :, f, :, f] += Sc
     Je = Je.reshape(C, 12, 12)
     rows = np.repeat(dof, 12, axis=1).reshape(-1)
     cols = np.tile(dof, (1, 12)).reshape(-1)

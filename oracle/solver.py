@@ -43,7 +43,7 @@ def newton_step(level: Level, prob: fem.Problem, x_old: np.ndarray, t_new: float
             return (x, hist) if return_history else x
         if it == maxit:
             break
-        J = fem.jacobian(level, prob, x)
+        J = fem.jacobian(level, prob, x, x_old)
         x = x + spla.spsolve(J.tocsc(), R)
     raise RuntimeError(f"Newton did not converge: {hist}")
 
@@ -123,7 +123,7 @@ class MGHierarchy:
     bounded LPS parameter (fem.coarse_operator_problem, reading G4)."""
 
     def __init__(self, levels, prob, x_fine, nu1=2, nu2=2, omega=0.6, smoother="additive", nu_coarse=0,
-                 coarse=0):
+                 coarse=0, x_old=None):
         self.levels = levels
         self.coarse = coarse                # level of the direct solve (Sec. 2: coarse-grid solver)
         self.prob = prob
@@ -136,7 +136,8 @@ class MGHierarchy:
         cprob = fem.coarse_operator_problem(prob)
         for l, L in enumerate(levels):
             xl = x_fine[:3 * L.n_nodes]
-            Jl = fem.jacobian(L, prob if l == len(levels) - 1 else cprob, xl)
+            xol = None if x_old is None else x_old[:3 * L.n_nodes]
+            Jl = fem.jacobian(L, prob if l == len(levels) - 1 else cprob, xl, xol)
             self.J.append(Jl)
             self.blocks.append(cell_blocks(Jl, L.cells))
         self.P = [None] + [levels[l].prolongation() for l in range(1, len(levels))]
@@ -253,7 +254,7 @@ def newton_step_mg(levels, prob, x_old, t_new, tol=1e-10, maxit=20, gmres_rtol=1
             return x, stats
         if it == maxit:
             break
-        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother, nu_coarse, coarse)
+        mg = MGHierarchy(levels, prob, x, nu1, nu2, omega, smoother, nu_coarse, coarse, x_old)
         w, k, _ = gmres(mg.J[-1], R, lambda v: mg.vcycle(len(levels) - 1, v),
                         gmres_rtol, restart, gmres_max)
         stats["gmres"].append(k)

@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("newton_predictor", C.c_int), ("jacobian_reuse", C.c_int),
                 ("reuse_contraction", C.c_double), ("switch_off_newton", C.c_int),
                 ("nu_coarse", C.c_int), ("smoother", C.c_int), ("coarse_level", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("delta0", C.c_double)]
 
 
 class CoarseMesh(C.Structure):

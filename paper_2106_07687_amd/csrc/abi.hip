@@ -63,7 +63,7 @@ double *scratch_address() {
 }
 
 bool params_ok(const dnnmg_params *p) {
-  return p && p->nu > 0 && p->alpha0 >= 0 && p->theta > 0 && p->theta <= 1 && p->u_mean >= 0 &&
+  return p && p->nu > 0 && p->alpha0 >= 0 && p->delta0 >= 0 && std::isfinite(p->delta0) && p->theta > 0 && p->theta <= 1 && p->u_mean >= 0 &&
          p->channel_h > 0 && p->newton_tol > 0 && p->newton_max >= 0 && p->newton_max <= 1000 &&
          p->gmres_rtol > 0 && p->gmres_rtol < 1 && p->gmres_restart >= 1 &&
          p->gmres_restart <= 64 && p->gmres_max >= 1 && p->nu_pre >= 0 && p->nu_post >= 0 &&
@@ -183,12 +183,12 @@ retry:
       // the multigrid preconditioner is refreshed at the first Newton
       // iteration of a step; later iterations re-assemble only the finest
       // Jacobian
-      S.linearize(st.x.p, l, dt, it == 0);
+      S.linearize(st.x.p, c.xo_save.p, l, dt, it == 0);
       if (it == 0) ++loc.jacobian_builds;
     } else if (S.jacobian_kept(st.key, l, dt) && st.reuse_ok) {
       kept_used = true;   // chord iteration with the kept hierarchy
     } else {
-      S.linearize(st.x.p, l, dt, true);
+      S.linearize(st.x.p, c.xo_save.p, l, dt, true);
       S.keep_jacobian(st.key, l, dt);
       st.reuse_ok = true;
       ++loc.jacobian_builds;
@@ -303,6 +303,7 @@ int dnnmg_params_default(dnnmg_params *p) {
   p->nu_coarse = 0;
   p->coarse_level = 0;
   p->stream = nullptr;
+  p->delta0 = 0.0;
   return DNNMG_OK;
 }
 
@@ -575,9 +576,9 @@ int dnnmg_linearize(dnnmg_ctx *ctx, const dnnmg_state *s, int level, double dt) 
   return guarded(ctx, [&]() {
     Ctx &c = ctx->impl;
     if (c.prm.precision == 1)
-      c.s32->linearize(s->impl.x.p, level, dt);
+      c.s32->linearize(s->impl.x.p, s->impl.x.p, level, dt);
     else
-      c.s64->linearize(s->impl.x.p, level, dt);
+      c.s64->linearize(s->impl.x.p, s->impl.x.p, level, dt);
     check(hipStreamSynchronize(c.stream), "linearize");
     return DNNMG_OK;
   });

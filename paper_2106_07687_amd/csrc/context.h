@@ -163,8 +163,9 @@ class Solver {
   explicit Solver(Ctx *c) : ctx_(c) {}
   void setup(int finest);
   // J on `level` (and, if full, on all coarser levels with the Vanka inverses
-  // and the level-0 inverse: the multigrid preconditioner)
-  void linearize(const double *x_dev, int level, double dt, bool full = true);
+  // and the level-0 inverse: the multigrid preconditioner); xo_dev: the
+  // frozen field of the convective stabilisation (delta0 > 0)
+  void linearize(const double *x_dev, const double *xo_dev, int level, double dt, bool full = true);
   // Jacobian reuse: after linearize(.., full = true) from state `key` the
   // hierarchy is marked as kept for (key, level, dt); any other linearize
   // or forget_jacobian() drops the mark
@@ -317,6 +318,7 @@ class Ctx {
     p.u_mean = prm.u_mean;
     p.H = prm.channel_h;
     p.t = t;
+    p.delta0 = prm.delta0;
     return p;
   }
   // LPS patch matrices of level l in the given role (0: the level's own

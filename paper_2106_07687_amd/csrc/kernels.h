@@ -43,6 +43,7 @@ struct LevelView {
 
 struct Phys {
   double nu, theta, inv_dt, alpha0, u_mean, H, t;
+  double delta0;   // convective stabilisation scale (0: off)
 };
 
 struct TransferView {
@@ -98,6 +99,29 @@ __device__ __forceinline__ void dirichlet_value(const Phys &ph, uint8_t fl, doub
   gu = 0.0;
   gv = 0.0;
   if (fl & 2) gu = 6.0 * ph.u_mean * ramp(ph.t) * y * (ph.H - y) / (ph.H * ph.H);
+}
+
+// Convective stabilisation of one cell (an optional member of the local-
+// projection family, off unless delta0 > 0): delta_T (kappa_T(b.grad v),
+// kappa_T(b.grad phi))_T with kappa_T g = g - mean_T(g), b the mean of the
+// old velocity over the 4 nodes, delta_T = delta0 / (nu / h^2 + |b| / h),
+// h^2 = area.  Given det_q and psi[q][a] = b.grad N_a at the 4 Gauss points,
+// returns delta_T and the fluctuations kpsi[q][a] = psi - its cell mean.
+__device__ __forceinline__ double conv_fluct(const double det[4], const double psi[4][4], double bn, double nu,
+                                             double delta0, double kpsi[4][4]) {
+  double area = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) area += det[q];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double m = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m += det[q] * psi[q][a];
+    m /= area;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kpsi[q][a] = psi[q][a] - m;
+  }
+  return delta0 / (nu / area + bn / sqrt(area));
 }
 
 // ------------------------------------------------------------------ LPS
@@ -279,6 +303,69 @@ __global__ void __launch_bounds__(256) k_cell_vectors(LevelView L, Phys ph, cons
   }
 }
 
+// Convective stabilisation rows of the residual (delta0 > 0 only), added to
+// the element vectors of k_cell_vectors<0>: E[12 c + 3 a + f] += delta_T
+// (kappa_T(b.grad v_f), kappa_T(b.grad N_a))_T for f = u, v, with the frozen
+// field b from xo (one thread per cell).
+__global__ void __launch_bounds__(256) k_conv_vectors(LevelView L, Phys ph, const double *__restrict__ x,
+                                                      const double *__restrict__ xo, double *__restrict__ E) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L.C) return;
+  const int4 cn = L.cells[c];
+  const int nn[4] = {cn.x, cn.y, cn.z, cn.w};
+  double X[4], Y[4], U[4], V[4], Bu = 0.0, Bv = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const double2 pt = L.xy[nn[b]];
+    X[b] = pt.x;
+    Y[b] = pt.y;
+    U[b] = x[3 * nn[b]];
+    V[b] = x[3 * nn[b] + 1];
+    Bu += xo[3 * nn[b]];
+    Bv += xo[3 * nn[b] + 1];
+  }
+  Bu *= 0.25;
+  Bv *= 0.25;
+  double cdet[4], cpsi[4][4], gu[4], gv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double N[4], gx[4], gy[4], det;
+    q1_point(X, Y, q, N, gx, gy, det);
+    cdet[q] = det;
+    gu[q] = 0.0;
+    gv[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      cpsi[q][a] = Bu * gx[a] + Bv * gy[a];
+      gu[q] += cpsi[q][a] * U[a];
+      gv[q] += cpsi[q][a] * V[a];
+    }
+  }
+  double kpsi[4][4];
+  const double delta = conv_fluct(cdet, cpsi, sqrt(Bu * Bu + Bv * Bv), L.nnu ? L.nnu[nn[0]] : ph.nu, ph.delta0,
+                                  kpsi);
+  double mu = 0.0, mv = 0.0, area = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    mu += cdet[q] * gu[q];
+    mv += cdet[q] * gv[q];
+    area += cdet[q];
+  }
+  mu /= area;
+  mv /= area;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double su = 0.0, sv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      su += cdet[q] * (gu[q] - mu) * kpsi[q][a];
+      sv += cdet[q] * (gv[q] - mv) * kpsi[q][a];
+    }
+    E[12 * static_cast<size_t>(c) + 3 * a] += delta * su;
+    E[12 * static_cast<size_t>(c) + 3 * a + 1] += delta * sv;
+  }
+}
+
 // LPS rows of the pressure equation per patch: S[q NP + P] = sum_m
 // s_P(q, m) p_m over the patch's 9 nodes (one thread per patch; the sums of
 // the node rows then add these in the node's patch order).
@@ -395,8 +482,8 @@ __global__ void k_fill(T *__restrict__ a, size_t n, T v) {
 // Dynamic LDS: (maxwq * 9 + maxwx) * 64 * sizeof(T) bytes.
 template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const double *__restrict__ x,
-                                                 const double *__restrict__ sP, T *__restrict__ JQ,
-                                                 T *__restrict__ JX, T *__restrict__ cblk) {
+                                                 const double *__restrict__ sP, const double *__restrict__ xo,
+                                                 T *__restrict__ JQ, T *__restrict__ JX, T *__restrict__ cblk) {
   extern __shared__ unsigned char lds_raw[];
   T *accq = reinterpret_cast<T *>(lds_raw);
   const int s = blockIdx.x, lane = threadIdx.x;
@@ -427,10 +514,26 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
       for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int k = 0; k < 8; ++k) blk[b][k] = 0.0;
+      // convective stabilisation (delta0 > 0): frozen field b from xo
+      const bool conv = ph.delta0 > 0.0 && xo != nullptr;
+      double Bu = 0.0, Bv = 0.0;
+      if (conv) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          Bu += xo[3 * nn[b]];
+          Bv += xo[3 * nn[b] + 1];
+        }
+        Bu *= 0.25;
+        Bv *= 0.25;
+      }
+      double cdet[4], cpsi[4][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         double N[4], gx[4], gy[4], det;
         q1_point(X, Y, q, N, gx, gy, det);
+        cdet[q] = det;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cpsi[q][b] = Bu * gx[b] + Bv * gy[b];
         double u = 0, v = 0, ux = 0, uy = 0, vx = 0, vy = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -463,6 +566,26 @@ __global__ void __launch_bounds__(64) k_assemble(LevelView L, Phys ph, const dou
           blk[b][5] -= det * Nb * ha;    // (v,p)
           blk[b][6] += det * gx[b] * Na;  // (p,u)
           blk[b][7] += det * gy[b] * Na;  // (p,v)
+        }
+      }
+      if (conv) {
+        double kpsi[4][4];
+        const double delta = conv_fluct(cdet, cpsi, sqrt(Bu * Bu + Bv * Bv), nu, ph.delta0, kpsi);
+        double ka[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ka[q] = 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (b == a) ka[q] = kpsi[q][b];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          double cab = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cab += cdet[q] * ka[q] * kpsi[q][b];
+          blk[b][0] += delta * cab;
+          blk[b][4] += delta * cab;
         }
       }
 #pragma unroll
@@ -709,75 +832,97 @@ __global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict_
 
 // -------------------------------------------------------------- Vanka
 // Factorisation of the 12x12 cell blocks J|_{c,c} (4 nodes x 3 fields) by
-// Gauss-Jordan elimination with partial pivoting.  A group of 16 lanes works
-// on one cell; lane r < 12 holds row r = 3 a + f, read from the cell blocks
-// the assembly wrote (cblk[144 c + 12 r + j]: a group reads 576 contiguous
-// bytes).  Pivot search and pivot-row broadcast use wavefront shuffles.  The
-// inverse is stored SoA: inv[(12 r + j) * C + c] (entry-major: each of the
-// 144 loads of a wavefront in the apply reads one contiguous 256-byte
-// segment).
+// Gauss-Jordan elimination with partial pivoting (largest |entry| of the
+// column among the rows not yet used as pivots, the lowest row on ties).  A
+// group of 4 lanes works on one cell; lane l holds rows 3 l .. 3 l + 2 of the
+// block and of the identity, read from the cell blocks the assembly wrote
+// (cblk[144 c + 12 r + j]: a group reads 576 contiguous bytes).  Per column:
+// each lane picks its best row, two butterfly shuffles pick the group's, the
+// pivot row (A then E) is broadcast from its lane, and every row is scaled or
+// eliminated with it.  Rows are never swapped: a row records the column it
+// pivoted, and its part of the inverse is stored as that row of the inverse,
+// SoA: inv[(12 r + j) * C + c] (entry-major: each of the 144 loads of a
+// wavefront in the apply reads one contiguous 256-byte segment).
 template <typename T>
 __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ cblk, T *__restrict__ inv) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = gid >> 4;
-  const int r = threadIdx.x & 15;
-  const bool live = (c < L.C) && (r < 12);
-  double A[12], E[12];
+  const int c = gid >> 2;
+  const int l = threadIdx.x & 3;
+  const bool live = c < L.C;
+  double A[3][12], E[3][12];
 #pragma unroll
-  for (int j = 0; j < 12; ++j) {
-    A[j] = 0.0;
-    E[j] = (j == r) ? 1.0 : 0.0;
-  }
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      E[i][j] = (j == 3 * l + i) ? 1.0 : 0.0;
+      A[i][j] = live ? 0.0 : E[i][j];
+    }
   if (live) {
-    const T *row = cblk + static_cast<size_t>(c) * 144 + 12 * r;
+    const T *row = cblk + static_cast<size_t>(c) * 144 + 36 * l;
 #pragma unroll
-    for (int j = 0; j < 12; ++j) A[j] = static_cast<double>(row[j]);
-  } else {
-    if (r < 12) A[r] = 1.0;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 12; ++j) A[i][j] = static_cast<double>(row[12 * i + j]);
   }
-  bool used = (r >= 12);
-  int order = 0;
+  bool used[3] = {false, false, false};
+  int order[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double val = used ? -1.0 : fabs(A[k]);
-    int idx = r;
+    double val = -2.0;
+    int idx = 12;
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(val, off, 16);
-      const int oi = __shfl_xor(idx, off, 16);
+    for (int i = 0; i < 3; ++i) {
+      const double v = used[i] ? -1.0 : fabs(A[i][k]);
+      if (v > val) {   // rows in increasing order: ties keep the lower row
+        val = v;
+        idx = 3 * l + i;
+      }
+    }
+#pragma unroll
+    for (int off = 2; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(val, off, 4);
+      const int oi = __shfl_xor(idx, off, 4);
       if (ov > val || (ov == val && oi < idx)) {
         val = ov;
         idx = oi;
       }
     }
-    double prow[12], pe[12];
+    const int owner = idx / 3, li = idx - 3 * owner;
+    double send[12], prow[12];
 #pragma unroll
-    for (int j = 0; j < 12; ++j) {
-      prow[j] = __shfl(A[j], idx, 16);
-      pe[j] = __shfl(E[j], idx, 16);
-    }
+    for (int j = 0; j < 12; ++j) send[j] = li == 0 ? A[0][j] : (li == 1 ? A[1][j] : A[2][j]);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) prow[j] = __shfl(send[j], owner, 4);
     const double piv = prow[k];
     const double ip = piv != 0.0 ? 1.0 / piv : 0.0;
-    if (r == idx) {
+    double fct[3];
 #pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        A[j] *= ip;
-        E[j] *= ip;
+    for (int i = 0; i < 3; ++i) {
+      const bool me = 3 * l + i == idx;
+      fct[i] = me ? ip : A[i][k] * ip;
+      if (me) {
+        used[i] = true;
+        order[i] = k;
       }
-      used = true;
-      order = k;
-    } else {
-      const double fct = A[k] * ip;
 #pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        A[j] -= fct * prow[j];
-        E[j] -= fct * pe[j];
-      }
+      for (int j = 0; j < 12; ++j) A[i][j] = me ? A[i][j] * ip : A[i][j] - fct[i] * prow[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) send[j] = li == 0 ? E[0][j] : (li == 1 ? E[1][j] : E[2][j]);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) prow[j] = __shfl(send[j], owner, 4);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const bool me = 3 * l + i == idx;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) E[i][j] = me ? E[i][j] * ip : E[i][j] - fct[i] * prow[j];
     }
   }
   if (live) {
 #pragma unroll
-    for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order + j) * L.C + c] = static_cast<T>(E[j]);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order[i] + j) * L.C + c] = static_cast<T>(E[i][j]);
   }
 }
 

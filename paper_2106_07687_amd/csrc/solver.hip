@@ -276,6 +276,9 @@ void Ctx::residual(int l, const double *x, const double *xo, const double *rhs, 
   ProfScope ps(prof, stream, "residual", l);
   hipLaunchKernelGGL(k_cell_vectors<0>, dim3(blocks(L.h.C, 256)), dim3(256), 0, stream, L.view(),
                      phys(dt, t_new), x, xo, rhs ? 0 : 1, E);
+  if (prm.delta0 > 0.0 && xo)
+    hipLaunchKernelGGL(k_conv_vectors, dim3(blocks(L.h.C, 256)), dim3(256), 0, stream, L.view(), phys(dt, t_new), x,
+                       xo, E);
   hipLaunchKernelGGL(k_lps_vectors, dim3(blocks(L.h.NP, 256)), dim3(256), 0, stream, L.view(), sP, x, S);
   hipLaunchKernelGGL(k_residual_nodes, dim3(blocks(L.h.N, 256)), dim3(256), 0, stream, L.view(),
                      phys(dt, t_new), x, rhs, S, E, Rout, L.large_order());
@@ -679,7 +682,7 @@ void Solver<T>::autotune() {
 }
 
 template <typename T>
-void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) {
+void Solver<T>::linearize(const double *x_dev, const double *xo_dev, int level, double dt, bool full) {
   hipStream_t s = ctx_->stream;
   kept_key_ = 0;
   if (level < c_) throw DnnmgError{DNNMG_EINVAL, "solve level below coarse_level"};
@@ -696,12 +699,12 @@ void Solver<T>::linearize(const double *x_dev, int level, double dt, bool full) 
       if (lds > 65536) throw DnnmgError{DNNMG_EINVAL, "node rows too wide for the LDS assembly"};
       ProfScope ps(ctx_->prof, s, "assemble", l);
       hipLaunchKernelGGL(k_assemble<T>, dim3(L.h.nslice), dim3(kS), lds, s, L.view(), ctx_->phys(dt, 0.0), x_dev,
-                         sP, o.JQ.p, o.JX.p, full && l > c_ ? cblk_.p : nullptr);
+                         sP, xo_dev, o.JQ.p, o.JX.p, full && l > c_ ? cblk_.p : nullptr);
     }
     LAUNCH_CHECK("k_assemble");
     if (full && l > c_) {
       ProfScope ps(ctx_->prof, s, "vanka_factor", l);
-      hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 16, 256)),
+      hipLaunchKernelGGL(k_vanka_factor<T>, dim3(blocks(static_cast<size_t>(L.h.C) * 4, 256)),
                          dim3(256), 0, s, L.view(), cblk_.p, o.inv.p);
       LAUNCH_CHECK("k_vanka_factor");
     }

@@ -133,3 +133,39 @@ def test_dnnmg_correction_at_full_size():
     st.close()
     net.close()
     ctx.close()
+
+
+@pytest.mark.slow
+def test_level5_step_from_developed_inflow_matches_oracle_direct_newton():
+    """Config 2's comparison with the FP64 oracle on level 5 (260k DoFs): one
+    time step (dt 0.005, t = 1 -> 1.005, the inflow fully ramped) from an
+    analytic state, the fully developed channel profile u = 6 y (H - y) / H^2,
+    v = 0, p = 0 at every node (written from the oracle's coordinates, not by
+    the HIP path).  The GPU's mixed-precision and FP64 steps (Newton to 1e-12)
+    against the oracle's Newton with direct sparse solves (1e-12): relative L2
+    per field <= 1e-5 (mixed) and <= 1e-10 (FP64)."""
+    import paper_2106_07687_amd as P
+    from oracle import solver
+    macro = channel_obstacle(0)
+    level = 5
+    L = mesh.hierarchy(macro, level)[level]
+    H = fem.CHANNEL_H
+    y = L.xy[:, 1]
+    x0 = np.zeros((L.n_nodes, 3))
+    x0[:, 0] = 6.0 * y * (H - y) / H ** 2
+    x0 = x0.reshape(-1)
+    prob = fem.Problem(nu=macro.nu, dt=DT)
+    print(f"[level5] oracle direct Newton on {3 * L.n_nodes} DoFs", flush=True)
+    x_ref, hist = solver.newton_step(L, prob, x0, 1.0 + DT, tol=1e-12, return_history=True)
+    print(f"[level5] oracle Newton residuals {['%.1e' % h for h in hist]}", flush=True)
+    for precision, bar in ((1, 1e-5), (0, 1e-10)):
+        ctx = P.Context(precision=precision, nu=macro.nu, newton_tol=1e-12, jacobian_reuse=1, newton_predictor=1)
+        ctx.setup_mesh(macro, level)
+        st = ctx.state(level)
+        st.set(x0, 1.0)
+        info = ctx.step(st, DT)
+        err = _fields(st.get()[0], x_ref)
+        print(f"[level5] precision {precision}: rel {err:.2e} ({info})", flush=True)
+        assert info["converged"] == 1 and err <= bar, (precision, err)
+        st.close()
+        ctx.close()

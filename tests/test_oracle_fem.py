@@ -253,3 +253,101 @@ def test_unsteady_manufactured_solution_temporal_order():
         xh, xe = _unsteady_run(lev[lvl], nu, 0.5, 0.01, T)
         errs.append(_vel_norm(lev[lvl], xh - xe))
     assert np.log2(errs[0] / errs[1]) >= 1.8, errs
+
+
+def _uniform_level(nx, ny, Lx, Ly, level):
+    return mesh.hierarchy(rectangle(nx, ny, Lx, Ly, nu=0.01), level)[level]
+
+
+def test_convective_stabilisation_closed_form_on_uniform_grid():
+    """Quadratic form of the convective term for u = x y on a uniform grid of
+    hx x hy cells (Q1 holds x y exactly): with b = (1, 0) the streamline
+    derivative is y, its fluctuation y - y_c, so u^T S u = sum_T delta_T
+    hx hy^3 / 12; with b = (0, 1) it is delta_T hx^3 hy / 12 (2x2 Gauss is
+    exact for these quadratics), delta_T = delta0 / (nu / h_T^2 + |b| / h_T)."""
+    L = _uniform_level(3, 2, 1.5, 0.8, 2)              # level 0 = macro refined once: 24 x 16 cells
+    hx, hy = 1.5 / 24, 0.8 / 16
+    assert L.n_cells == 24 * 16
+    nu, d0 = 0.01, 0.7
+    prob = fem.Problem(nu=nu, dt=np.inf, delta0=d0)
+    X, Y = L.xy[:, 0], L.xy[:, 1]
+    u = X * Y
+    area = hx * hy
+    for bvec, form in (((1.0, 0.0), hx * hy ** 3 / 12), ((0.0, 1.0), hx ** 3 * hy / 12),
+                       ((0.6, 0.8), None)):
+        xo = np.zeros((L.n_nodes, 3))
+        xo[:, 0], xo[:, 1] = bvec
+        Sc = fem.convective_matrices(L, prob, xo.reshape(-1))
+        q = float(np.einsum('ca,cab,cb->', u[L.cells], Sc, u[L.cells]))
+        delta = d0 / (nu / area + 1.0 / np.sqrt(area))
+        if form is None:   # b = (0.6, 0.8): fluctuation 0.6 (y - y_c) + 0.8 (x - x_c)
+            form = (0.36 * hx * hy ** 3 + 0.64 * hx ** 3 * hy) / 12
+        assert abs(q - L.n_cells * delta * form) <= 1e-12 * q, (bvec, q, L.n_cells * delta * form)
+
+
+def test_convective_stabilisation_vanishes_on_linear_fields_of_parallelograms():
+    """On parallelogram cells a linear velocity has a constant gradient, so
+    b . grad v is constant per cell and its fluctuation vanishes: the
+    residual with delta0 > 0 equals the one without, for any old state."""
+    m = rectangle(4, 2, 1.6, 0.41, nu=0.01)
+    m.xy = m.xy.copy()
+    m.xy[:, 0] += 0.35 * m.xy[:, 1]
+    L = mesh.hierarchy(m, 2)[2]
+    X, Y = L.xy[:, 0], L.xy[:, 1]
+    x = np.stack([0.3 + 0.5 * X - 0.2 * Y, -0.1 + 0.4 * X + 0.7 * Y, np.sin(3 * X)], 1).reshape(-1)
+    xo = np.random.default_rng(3).uniform(-1, 1, 3 * L.n_nodes)
+    r0 = fem.residual(L, fem.Problem(nu=0.01, dt=0.02), x, xo, 0.3)
+    r1 = fem.residual(L, fem.Problem(nu=0.01, dt=0.02, delta0=0.9), x, xo, 0.3)
+    assert np.abs(r1 - r0).max() <= 1e-13 * np.abs(r0).max()
+    # and it does not vanish for a bilinear field
+    x2 = x.reshape(-1, 3).copy()
+    x2[:, 0] += 2.0 * X * Y
+    r2a = fem.residual(L, fem.Problem(nu=0.01, dt=0.02), x2.reshape(-1), xo, 0.3)
+    r2b = fem.residual(L, fem.Problem(nu=0.01, dt=0.02, delta0=0.9), x2.reshape(-1), xo, 0.3)
+    assert np.abs(r2b - r2a).max() > 1e-6
+
+
+def test_convective_stabilisation_jacobian_matches_finite_differences():
+    m = channel_obstacle(2)
+    L = mesh.hierarchy(m, 1)[-1]
+    prob = fem.Problem(nu=m.nu, dt=0.01, delta0=0.5)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, 3 * L.n_nodes)
+    xo = rng.uniform(-1, 1, 3 * L.n_nodes)
+    w = rng.uniform(-1, 1, 3 * L.n_nodes)
+    dn = L.dirichlet_nodes()
+    w.reshape(-1, 3)[dn, :2] = 0.0
+    J = fem.jacobian(L, prob, x, xo)
+    eps = 1e-6
+    fd = -(fem.residual(L, prob, x + eps * w, xo, 0.3) - fem.residual(L, prob, x - eps * w, xo, 0.3)) / (2 * eps)
+    free = np.ones(3 * L.n_nodes, bool)
+    free.reshape(-1, 3)[dn, :2] = False
+    Jw = J @ w
+    assert np.linalg.norm(Jw[free] - fd[free]) <= 1e-8 * np.linalg.norm(Jw[free])
+    # the term is present: the Jacobian differs from the one without it
+    J0 = fem.jacobian(L, fem.Problem(nu=m.nu, dt=0.01), x, xo)
+    assert np.linalg.norm((J - J0) @ w) > 1e-3 * np.linalg.norm(Jw)
+
+
+@pytest.mark.slow
+def test_convective_stabilisation_keeps_manufactured_solution_convergence():
+    """The manufactured solution of the steady pin with the convective term
+    on (delta0 = 0.5, frozen field = the exact velocity): the velocity error
+    still falls at second order (the term is consistent to higher order than
+    the discretisation)."""
+    nu = 0.1
+    u, v, p, fx, fy = _mms(nu)
+    bc = lambda X, Y, t: (u(X, Y) + 0 * X, v(X, Y) + 0 * X)
+    force = lambda X, Y, t: (fx(X, Y) + 0 * X, fy(X, Y) + 0 * X)
+    lev = mesh.hierarchy(rectangle(2, 2, 1.0, 1.0, nu=nu), 4)
+    prob = fem.Problem(nu=nu, dt=np.inf, theta=1.0, force=force, dirichlet=bc, delta0=0.5)
+    errs = []
+    for L in lev[1:]:
+        X, Y = L.xy[:, 0], L.xy[:, 1]
+        xe = np.stack([u(X, Y) + 0 * X, v(X, Y) + 0 * X, p(X, Y) + 0 * X], 1).reshape(-1)
+        xh = solver.newton_step(L, prob, xe, 0.0, tol=1e-11)
+        M = fem.mass_matrix(L)
+        d = (xh - xe).reshape(-1, 3)
+        errs.append(np.sqrt(sum(d[:, f] @ (M @ d[:, f]) for f in range(2))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] >= 1.9, (errs, rates)
