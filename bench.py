@@ -864,9 +864,9 @@ def main():
     ap.add_argument("--nu-coarse", type=int, default=0,
                     help="full-depth GMG leg: sweeps before and after on the V-cycle levels below the "
                          "one GMRES works on (0: the same V(2,2) on every level)")
-    ap.add_argument("--dnnmg-sweeps", default="2,1,1",
+    ap.add_argument("--dnnmg-sweeps", default="2,2,0",
                     help="pre,post,coarse sweeps of the V-cycles of the level-L solves (MG(L) and "
-                         "DNN-MG legs; the GMG leg keeps V(2,2) throughout)")
+                         "DNN-MG legs; coarse 0: pre/post on every level, as the GMG leg's V(2,2))")
     ap.add_argument("--direct-level", type=int, default=1, choices=(0, 1, 2),
                     help="level of the direct (FP64 dense inverse) solve at the bottom of every V-cycle")
     ap.add_argument("--smoother", type=int, default=0, choices=(0, 1),
@@ -1179,7 +1179,8 @@ def main():
                    "newton_predictor": args.newton_predictor, "jacobian_reuse": args.jacobian_reuse,
                    "smoother": args.smoother, "direct_solve_level": args.direct_level,
                    "v_cycle": {"gmg": f"V(2,2), {args.nu_coarse or 'same'} below the top",
-                               "mg_coarse_and_dnnmg": f"V({pre},{post}), V({coarse},{coarse}) below the top"}},
+                               "mg_coarse_and_dnnmg": f"V({pre},{post}), "
+                                                      f"{f'V({coarse},{coarse})' if coarse else 'same'} below the top"}},
         "roofline": roof,
         "mfma": mfma,
         "train": train,

@@ -245,7 +245,7 @@ class Solver {
   // blocked Gauss-Jordan: panel width (0: one pivot + one elimination launch
   // per column), second workspace, panel transforms, pivot rows, used-row
   // flags, and the compact inverse read by the coarse solve
-  int gj_b_ = 0;
+  int gj_b_ = 0, gj_rpt_ = 1;      // rows per panel thread: 1 (<= 1024 unknowns) or 2
   int nblk_ = 1, nb_ = 0;          // level-0 blocks and their padded size (unknowns)
   DevBuf<double> W2_, Zp_, Ainv_;
   DevBuf<int> piv_, used_, g2l_, blk_, bdof_;

@@ -1468,18 +1468,25 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ W, const double *__
 // largest |value| (see the panel's pivot key), recorded in piv[k].  After
 // all columns, row piv[k] of the right half is row k of A^{-1}.
 //
-// Panel step (one workgroup of 64 * ceil(n / 64) <= 1024 threads, thread i
-// holds row i of the panel's kGjB columns in registers): the panel's column
-// steps are run on the panel alone, in place.  Their composite is
+// Panel step (one workgroup; thread t holds rows t + r * blockDim, r < RPT,
+// of the panel's kGjB columns in registers): the panel's column steps are
+// run on the panel alone, in place.  Their composite is
 // G = I + sum_r (G e_{p_r} - e_{p_r}) e_{p_r}^T (p_r the panel's pivot rows),
 // and G e_{p_r} is the unit column e_{p_r} carried along from step r on (the
 // steps before r leave it unchanged): in place, column r of the panel turns
 // into G e_{p_r} at step r (the classic in-place inversion update).  Output
 // Z = [G e_{p_r}] - [e_{p_r}] and the pivot rows.  The pivot is chosen on a
-// 32-bit key: |value| rounded to FP32 with its 10 low mantissa bits replaced
-// by 1023 - row (rows within 2^-13 relative count as equal; the lower row
-// wins), reduced by one integer maximum.
+// 32-bit key: |value| rounded to FP32 with its low kGjRowBits<RPT> mantissa
+// bits replaced by (2^bits - 1 - row) (rows within 2^-13 relative for
+// RPT = 1, 2^-12 for RPT = 2, count as equal; the lower row wins), reduced by
+// one integer maximum.  RPT = 1 takes
+// n <= 1024 (1024 threads), RPT = 2 takes n <= 1536 (768 threads: three
+// wavefronts per SIMD leave room for the 64 FP64 panel values per thread).
 constexpr int kGjB = 32;
+template <int RPT>
+constexpr int kGjRowBits = RPT == 1 ? 10 : 11;
+template <int RPT>
+constexpr int kGjMaxRows = RPT == 1 ? 1024 : 1536;
 // a[c] for a runtime c without dynamic register indexing
 __device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
   double v = 0.0;
@@ -1488,9 +1495,11 @@ __device__ __forceinline__ double gj_pick(const double (&a)[kGjB], int c) {
   return v;
 }
 
-__global__ void __launch_bounds__(1024) k_gjb_panel(int n, int k0, int b, const double *__restrict__ W,
-                                                   int *__restrict__ used_g, int *__restrict__ piv,
-                                                   double *__restrict__ Z) {
+template <int RPT>
+__global__ void __launch_bounds__(RPT == 1 ? 1024 : 768)
+    k_gjb_panel(int n, int k0, int b, const double *__restrict__ W, int *__restrict__ used_g, int *__restrict__ piv,
+                double *__restrict__ Z) {
+  constexpr unsigned kMask = (1u << kGjRowBits<RPT>) - 1u;
   // block blockIdx.x of a block-diagonal batch: its own workspace and records
   W += static_cast<size_t>(blockIdx.x) * n * 2 * n;
   used_g += static_cast<size_t>(blockIdx.x) * n;
@@ -1499,50 +1508,72 @@ __global__ void __launch_bounds__(1024) k_gjb_panel(int n, int k0, int b, const 
   __shared__ double prow[2][kGjB];
   __shared__ unsigned rk[2][16];
   __shared__ int spiv[kGjB];
-  const int i = threadIdx.x;
-  const int nw = blockDim.x >> 6;
-  const bool live = i < n;
+  const int nt = blockDim.x;
+  const int nw = nt >> 6;
   const size_t w2 = 2 * static_cast<size_t>(n);
-  double R[kGjB];
+  double R[RPT][kGjB];
+  bool used[RPT], live[RPT];
+  int row[RPT];
 #pragma unroll
-  for (int c = 0; c < kGjB; ++c) R[c] = (live && c < b) ? W[i * w2 + k0 + c] : 0.0;
-  bool used = !live || (k0 > 0 && used_g[i] != 0);
+  for (int r = 0; r < RPT; ++r) {
+    row[r] = threadIdx.x + r * nt;
+    live[r] = row[r] < n;
+#pragma unroll
+    for (int c = 0; c < kGjB; ++c) R[r][c] = (live[r] && c < b) ? W[row[r] * w2 + k0 + c] : 0.0;
+    used[r] = !live[r] || (k0 > 0 && used_g[row[r]] != 0);
+  }
   for (int c = 0; c < b; ++c) {
     const int q = c & 1;
-    const double rc = gj_pick(R, c);
-    unsigned key = used ? 0u
-                        : ((__float_as_uint(fabsf(static_cast<float>(rc))) & ~0x3FFu) |
-                           (1023u - static_cast<unsigned>(i)));
+    double rc[RPT];
+    unsigned key = 0u;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      rc[r] = gj_pick(R[r], c);
+      const unsigned kr = used[r] ? 0u
+                                  : ((__float_as_uint(fabsf(static_cast<float>(rc[r]))) & ~kMask) |
+                                     (kMask - static_cast<unsigned>(row[r])));
+      key = max(key, kr);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) key = max(key, static_cast<unsigned>(__shfl_xor(static_cast<int>(key), off)));
-    if ((i & 63) == 0) rk[q][i >> 6] = key;
+    if ((threadIdx.x & 63) == 0) rk[q][threadIdx.x >> 6] = key;
     __syncthreads();
     key = rk[q][0];
     for (int w = 1; w < nw; ++w) key = max(key, rk[q][w]);
-    const int p = 1023 - static_cast<int>(key & 0x3FFu);
-    if (i == p) {
-      const double ip = 1.0 / rc;
+    const int p = static_cast<int>(kMask - (key & kMask));
 #pragma unroll
-      for (int cc = 0; cc < kGjB; ++cc) {
-        R[cc] = (cc == c) ? ip : R[cc] * ip;
-        prow[q][cc] = R[cc];
+    for (int r = 0; r < RPT; ++r) {
+      if (row[r] == p) {
+        const double ip = 1.0 / rc[r];
+#pragma unroll
+        for (int cc = 0; cc < kGjB; ++cc) {
+          R[r][cc] = (cc == c) ? ip : R[r][cc] * ip;
+          prow[q][cc] = R[r][cc];
+        }
+        used[r] = true;
+        piv[k0 + c] = p;
+        spiv[c] = p;
       }
-      used = true;
-      piv[k0 + c] = p;
-      spiv[c] = p;
     }
     __syncthreads();
-    if (i != p && live) {
 #pragma unroll
-      for (int cc = 0; cc < kGjB; ++cc) R[cc] = ((cc == c) ? 0.0 : R[cc]) - rc * prow[q][cc];
+    for (int r = 0; r < RPT; ++r) {
+      if (row[r] != p && live[r]) {
+#pragma unroll
+        for (int cc = 0; cc < kGjB; ++cc) R[r][cc] = ((cc == c) ? 0.0 : R[r][cc]) - rc[r] * prow[q][cc];
+      }
     }
   }
-  if (live) used_g[i] = used ? 1 : 0;
-  __syncthreads();   // spiv[] of the last step is visible
-  if (live) {
 #pragma unroll
-    for (int r = 0; r < kGjB; ++r)
-      if (r < b) Z[static_cast<size_t>(i) * b + r] = R[r] - ((i == spiv[r]) ? 1.0 : 0.0);
+  for (int r = 0; r < RPT; ++r)
+    if (live[r]) used_g[row[r]] = used[r] ? 1 : 0;
+  __syncthreads();   // spiv[] of the last step is visible
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (!live[r]) continue;
+#pragma unroll
+    for (int t = 0; t < kGjB; ++t)
+      if (t < b) Z[static_cast<size_t>(row[r]) * b + t] = R[r][t] - ((row[r] == spiv[t]) ? 1.0 : 0.0);
   }
 }
 

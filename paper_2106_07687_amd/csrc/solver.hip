@@ -406,9 +406,9 @@ void Solver<T>::setup(int finest) {
   n0_ = 3 * ctx_->levels[c_]->h.N;
   // Coarse blocks: one per simulation of a batch (its nodes are those of its
   // own mesh), a single block otherwise.  A block is solved by blocked
-  // Gauss-Jordan (panels of kGjB columns, one thread per row) when it has at
-  // most 1024 unknowns; a single larger block falls back to one pivot and one
-  // elimination launch per column.
+  // Gauss-Jordan (panels of kGjB columns; one thread per row up to 1024
+  // unknowns, two up to 1536); a single larger block falls back to one pivot
+  // and one elimination launch per column.
   const int N0 = ctx_->levels[c_]->h.N;
   std::vector<int> blk(N0, 0);
   if (!ctx_->blk0.empty()) {
@@ -420,9 +420,10 @@ void Solver<T>::setup(int finest) {
   std::vector<int> cnt(nblk_, 0), g2l(N0);
   for (int i = 0; i < N0; ++i) g2l[i] = cnt[blk[i]]++;
   nb_ = 3 * *std::max_element(cnt.begin(), cnt.end());
-  gj_b_ = nb_ <= 1024 ? kGjB : 0;
+  gj_rpt_ = nb_ <= kGjMaxRows<1> ? 1 : 2;
+  gj_b_ = nb_ <= kGjMaxRows<2> ? kGjB : 0;
   if (gj_b_ == 0 && nblk_ > 1)
-    throw DnnmgError{DNNMG_EINVAL, "a level-0 block of the batch exceeds 1024 unknowns"};
+    throw DnnmgError{DNNMG_EINVAL, "a level-0 block of the batch exceeds 1536 unknowns"};
   if (gj_b_ > 0) {
     std::vector<int> bdof(static_cast<size_t>(nblk_) * nb_, -1);
     for (int i = 0; i < N0; ++i)
@@ -734,8 +735,12 @@ void Solver<T>::coarse_inverse() {
     double *wo = W_.p, *wn = W2_.p;
     for (int k0 = 0; k0 < nb; k0 += gj_b_) {
       const int b = std::min(gj_b_, nb - k0);
-      hipLaunchKernelGGL(k_gjb_panel, dim3(nblk_), dim3(64 * blocks(nb, 64)), 0, s, nb, k0, b, wo, used_.p,
-                         piv_.p, Zp_.p);
+      if (gj_rpt_ == 1)
+        hipLaunchKernelGGL(k_gjb_panel<1>, dim3(nblk_), dim3(64 * blocks(nb, 64)), 0, s, nb, k0, b, wo, used_.p,
+                           piv_.p, Zp_.p);
+      else
+        hipLaunchKernelGGL(k_gjb_panel<2>, dim3(nblk_), dim3(64 * blocks(blocks(nb, 2), 64)), 0, s, nb, k0, b, wo,
+                           used_.p, piv_.p, Zp_.p);
       const dim3 ug(blocks(2 * nb - k0 - b, 64), blocks(nb, 16), nblk_);
       hipLaunchKernelGGL(k_gjb_update, ug, dim3(256), 0, s, nb, k0, b, wo, Zp_.p, piv_.p, wn);
       std::swap(wo, wn);
@@ -934,7 +939,13 @@ bool Solver<T>::vcycle_body(int l, const T *b, T *x, bool defer) {
   hipStream_t s = ctx_->stream;
   if (l == c_) {
     ProfScope ps(ctx_->prof, s, "coarse_solve", c_);
-    if (gj_b_ > 0)
+    // a single block above level 0 (no padding, unknowns in order): one
+    // wavefront per row; level 0 keeps the per-block rows the single-workgroup
+    // bottom cycle also uses
+    if (gj_b_ > 0 && nblk_ == 1 && c_ > 0)
+      hipLaunchKernelGGL(k_dense_solve_w<T>, dim3(blocks(nb_, 4)), dim3(256), 0, s, nb_, Ainv_.p,
+                         static_cast<size_t>(nb_), b, x);
+    else if (gj_b_ > 0)
       hipLaunchKernelGGL(k_dense_solve_blk<T>, dim3(blocks(static_cast<size_t>(nblk_) * nb_, 8)), dim3(256), 0,
                          s, nblk_, nb_, Ainv_.p, bdof_.p, b, x);
     else

@@ -310,8 +310,9 @@ def test_coarse_sweep_count_parity(c1):
 @pytest.mark.parametrize("coarse", [1, 2])
 def test_coarse_level_direct_solve_parity(coarse):
     """coarse_level = c: the FP64 dense inverse sits on level c (level 1: one
-    block of more than 1024 unknowns, the per-column Gauss-Jordan; level 2
-    the same); V-cycles called on levels 3 .. c match the oracle's hierarchy
+    block of 1140 unknowns, the blocked Gauss-Jordan with two rows per panel
+    thread; level 2: more than 1536 unknowns, one pivot and one elimination
+    launch per column); V-cycles called on levels 3 .. c match the oracle's hierarchy
     with its direct solve on level c (1e-10, FP64; on level c the exact
     solve), a cycle below c is refused, and FP64 time steps reach the
     oracle's x_n (1e-10)."""
