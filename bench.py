@@ -400,31 +400,41 @@ class Minibatches:
     """Device-resident training sequences in minibatch-major layout
     (nb, seq, B, n): each minibatch is contiguous, as the training entry point
     takes it (T x B rows, step-major).  Sequences are shuffled into
-    minibatches with a seeded permutation; the remainder is dropped."""
+    minibatches with a seeded permutation; the remainder is dropped.  Only
+    the shuffled copy is kept: added sequences are joined to it and the whole
+    set is shuffled again."""
 
     def __init__(self, X, D, batch, seed):
-        import torch
-        self.X, self.D = X, D              # (seq, Btot, n) device tensors
         self.batch, self.seed = batch, seed
-        self.build()
+        self.build(X, D)
 
     def add(self, X, D):
         import torch
-        self.X = torch.cat([self.X, X], dim=1)
-        self.D = torch.cat([self.D, D], dim=1)
-        self.build()
+        seq = self.Xm.shape[1]
 
-    def build(self):
+        def flat(A):
+            return A.permute(1, 0, 2, 3).reshape(seq, -1, A.shape[3])
+        X = torch.cat([flat(self.Xm), X], dim=1)
+        del self.Xm
+        D = torch.cat([flat(self.Dm), D], dim=1)
+        del self.Dm
+        self.build(X, D)
+
+    def build(self, X, D):
         import torch
-        seq, tot = self.X.shape[0], self.X.shape[1]
+        seq, tot = X.shape[0], X.shape[1]
         B = min(self.batch, tot)
         self.nb = tot // B
+        self.n_seq = self.nb * B
         g = torch.Generator(device="cpu").manual_seed(self.seed + tot)
-        perm = torch.randperm(tot, generator=g)[:self.nb * B].to(self.X.device)
+        perm = torch.randperm(tot, generator=g)[:self.n_seq].to(X.device)
 
         def mb(A):
             return A.index_select(1, perm).reshape(seq, self.nb, B, A.shape[2]).permute(1, 0, 2, 3).contiguous()
-        self.Xm, self.Dm, self.B = mb(self.X), mb(self.D), B
+        self.Xm = mb(X)
+        del X
+        self.Dm = mb(D)
+        self.B = B
 
     def fit(self, net, iters, lr, ckpt=8):
         """Adam iterations over the minibatches in turn (lr drops to 0.3 lr for
@@ -450,8 +460,12 @@ def train_on_geometries(P, args, log, stream):
     free DNN-MG runs on the same geometries, each step's target the
     correction that one fine step started from the run's own fine state gives
     (targets from the original fine trajectory would ask the network to undo
-    the run's accumulated drift in one step).  Returns the trained weights, standardisation and a
-    summary."""
+    the run's accumulated drift in one step).  The free run of a geometry
+    starts at the start of its fine trajectory and each round carries it on
+    from where the previous round stopped (coarse state, hidden state and
+    corrected fine state kept), so the last round's states lie as far from
+    the start as the evaluation window's.  Returns the trained weights,
+    standardisation and a summary."""
     import numpy as np
     import torch
 
@@ -489,31 +503,34 @@ def train_on_geometries(P, args, log, stream):
     Dd = torch.cat([torch.from_numpy(sequences(D / os_f, seq)).to(dev) for D in Dr], dim=1)
     del Xr, Dr
     data = Minibatches(Xd, Dd, args.train_batch, args.seed)
+    del Xd, Dd
     w0 = gru_weights(net0.n_in, args.hidden, args.layers, net0.n_out, seed=args.seed, scale=0.5)
     net0.set_weights(w0, mu=mu, sigma=sg, out_scale=osc)
     loss, sec, its = data.fit(net0, args.train_net_iters, 2e-3)
     fit_sec, fit_its = sec, its
-    log(f"net training (teacher forcing): loss {loss:.2f}, {data.X.shape[1]} sequences of {seq} steps, "
+    log(f"net training (teacher forcing): loss {loss:.2f}, {data.n_seq} sequences of {seq} steps, "
         f"{data.nb} minibatches of {data.B}, {1e3 * sec / its:.2f} ms per iteration")
+    runs = {}
     for rnd in range(args.dagger):
         # free DNN-MG runs with the current network; the target of each step is
         # the correction that one fine step, started from the run's own fine
         # state (the corrected velocity of the previous step), gives
         w = net0.get_weights()
         Xc_all, Dc_all = [], []
-        for g in geoms:
-            # each round starts its free runs further along the geometry's fine trajectory
-            k0 = min(20 * (rnd + 1), len(g["xF"]) - 1)
-            ctx, net, x0, t0 = g["ctx"], g["net"], g["xF"][k0], g["t0"] + k0 * dt
+        for i, g in enumerate(geoms):
+            ctx, net = g["ctx"], g["net"]
             if net is not net0:
                 net.set_weights(w, mu=mu, sigma=sg, out_scale=osc)
-            nL = ctx.level_info(L)[0]
-            st = ctx.state(L)
-            st.set(x0[:3 * nL], t0)
-            net.reset(st)
-            net.rhs_from_fine(st, x0, dt)
-            sf = ctx.state(F)
-            vc = x0
+            if i not in runs:
+                # the free run starts where the geometry's fine trajectory starts
+                x0, t0 = g["xF"][0], g["t0"]
+                nL = ctx.level_info(L)[0]
+                st = ctx.state(L)
+                st.set(x0[:3 * nL], t0)
+                net.reset(st)
+                net.rhs_from_fine(st, x0, dt)
+                runs[i] = [st, ctx.state(F), x0]
+            st, sf, vc = runs[i]
             Xc, Dc = [], []
             for n in range(args.dagger_steps):
                 t = st.get()[1]
@@ -527,8 +544,7 @@ def train_on_geometries(P, args, log, stream):
                 xt = fine_state(ctx, st.get()[0], L, F).reshape(-1, 3).copy()
                 xt[:, :2] += out["correction"]
                 vc = xt.reshape(-1)
-            sf.close()
-            st.close()
+            runs[i][2] = vc
             Xc_all.append(torch.from_numpy(sequences(np.stack(Xc), seq)).to(dev))
             Dc_all.append(torch.from_numpy(sequences(np.stack(Dc), seq)).to(dev))
             log(f"free-run round {rnd + 1}, seed {g['seed']}: {args.dagger_steps} steps, "
@@ -538,19 +554,23 @@ def train_on_geometries(P, args, log, stream):
         fit_sec += sec
         fit_its += its
         log(f"net training (round {rnd + 1}, free DNN-MG states added): loss {loss:.2f}, "
-            f"{data.X.shape[1]} sequences")
+            f"{data.n_seq} sequences")
+    for st, sf, _ in runs.values():
+        sf.close()
+        st.close()
     w = net0.get_weights()
     info = {"geometries": [{"seed": g["seed"], "re": g["re"]} for g in geoms],
             "t_start": [round(g["t0"], 4) for g in geoms], "fine_steps_per_geometry": args.train_steps,
-            "sequences": int(data.X.shape[1]), "seq": seq, "batch": data.B, "rounds": 1 + args.dagger,
+            "sequences": int(data.n_seq), "seq": seq, "batch": data.B, "rounds": 1 + args.dagger,
             "free_run_steps_per_round": args.dagger_steps,
+            "free_run_horizon_steps": args.dagger * args.dagger_steps,
             "adam_iters": fit_its, "final_loss": round(float(loss), 4),
             "bptt_ms_per_iter": round(1e3 * fit_sec / fit_its, 3),
             "wall_s": round(time.perf_counter() - t_all, 1)}
     for g in geoms:
         g["net"].close()
         g["ctx"].close()
-    del data, Xd, Dd
+    del data
     torch.cuda.empty_cache()
     return w, (mu, sg, osc), info
 
@@ -832,10 +852,10 @@ def main():
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
     ap.add_argument("--train-net-iters", type=int, default=400)
-    ap.add_argument("--dagger", type=int, default=2,
+    ap.add_argument("--dagger", type=int, default=3,
                     help="training rounds on free DNN-MG runs of the training geometries (targets from one "
-                         "fine step started from the run's own state)")
-    ap.add_argument("--dagger-steps", type=int, default=64)
+                         "fine step started from the run's own state; each round carries the runs on)")
+    ap.add_argument("--dagger-steps", type=int, default=64, help="free-run steps per geometry and round")
     ap.add_argument("--dagger-iters", type=int, default=300)
     ap.add_argument("--extra-eval-seeds", default="",
                     help="comma-separated channel seeds (e.g. 300,301,302,303) evaluated like the main "
