@@ -1522,45 +1522,51 @@ __global__ void __launch_bounds__(RPT == 1 ? 1024 : 768)
     for (int c = 0; c < kGjB; ++c) R[r][c] = (live[r] && c < b) ? W[row[r] * w2 + k0 + c] : 0.0;
     used[r] = !live[r] || (k0 > 0 && used_g[row[r]] != 0);
   }
-  for (int c = 0; c < b; ++c) {
-    const int q = c & 1;
-    double rc[RPT];
-    unsigned key = 0u;
+  // fully unrolled over the panel's columns: every register index below is a
+  // constant (b is the same for the whole workgroup, so the barriers inside
+  // the guard are reached by every thread)
+#pragma clang loop unroll(full)
+  for (int c = 0; c < kGjB; ++c) {
+    if (c < b) {
+      const int q = c & 1;
+      double rc[RPT];
+      unsigned key = 0u;
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      rc[r] = gj_pick(R[r], c);
-      const unsigned kr = used[r] ? 0u
-                                  : ((__float_as_uint(fabsf(static_cast<float>(rc[r]))) & ~kMask) |
-                                     (kMask - static_cast<unsigned>(row[r])));
-      key = max(key, kr);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) key = max(key, static_cast<unsigned>(__shfl_xor(static_cast<int>(key), off)));
-    if ((threadIdx.x & 63) == 0) rk[q][threadIdx.x >> 6] = key;
-    __syncthreads();
-    key = rk[q][0];
-    for (int w = 1; w < nw; ++w) key = max(key, rk[q][w]);
-    const int p = static_cast<int>(kMask - (key & kMask));
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      if (row[r] == p) {
-        const double ip = 1.0 / rc[r];
-#pragma unroll
-        for (int cc = 0; cc < kGjB; ++cc) {
-          R[r][cc] = (cc == c) ? ip : R[r][cc] * ip;
-          prow[q][cc] = R[r][cc];
-        }
-        used[r] = true;
-        piv[k0 + c] = p;
-        spiv[c] = p;
+      for (int r = 0; r < RPT; ++r) {
+        rc[r] = gj_pick(R[r], c);
+        const unsigned kr = used[r] ? 0u
+                                    : ((__float_as_uint(fabsf(static_cast<float>(rc[r]))) & ~kMask) |
+                                       (kMask - static_cast<unsigned>(row[r])));
+        key = max(key, kr);
       }
-    }
-    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      if (row[r] != p && live[r]) {
+      for (int off = 32; off > 0; off >>= 1) key = max(key, static_cast<unsigned>(__shfl_xor(static_cast<int>(key), off)));
+      if ((threadIdx.x & 63) == 0) rk[q][threadIdx.x >> 6] = key;
+      __syncthreads();
+      key = rk[q][0];
+      for (int w = 1; w < nw; ++w) key = max(key, rk[q][w]);
+      const int p = static_cast<int>(kMask - (key & kMask));
 #pragma unroll
-        for (int cc = 0; cc < kGjB; ++cc) R[r][cc] = ((cc == c) ? 0.0 : R[r][cc]) - rc[r] * prow[q][cc];
+      for (int r = 0; r < RPT; ++r) {
+        if (row[r] == p) {
+          const double ip = 1.0 / rc[r];
+#pragma unroll
+          for (int cc = 0; cc < kGjB; ++cc) {
+            R[r][cc] = (cc == c) ? ip : R[r][cc] * ip;
+            prow[q][cc] = R[r][cc];
+          }
+          used[r] = true;
+          piv[k0 + c] = p;
+          spiv[c] = p;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        if (row[r] != p && live[r]) {
+#pragma unroll
+          for (int cc = 0; cc < kGjB; ++cc) R[r][cc] = ((cc == c) ? 0.0 : R[r][cc]) - rc[r] * prow[q][cc];
+        }
       }
     }
   }
