@@ -833,39 +833,42 @@ __global__ void __launch_bounds__(256) k_spmv4(LevelView L, const T *__restrict_
 // -------------------------------------------------------------- Vanka
 // Factorisation of the 12x12 cell blocks J|_{c,c} (4 nodes x 3 fields) by
 // Gauss-Jordan elimination with partial pivoting (largest |entry| of the
-// column among the rows not yet used as pivots, the lowest row on ties).  A
-// group of 4 lanes works on one cell; lane l holds rows 3 l .. 3 l + 2 of the
-// block and of the identity, read from the cell blocks the assembly wrote
-// (cblk[144 c + 12 r + j]: a group reads 576 contiguous bytes).  Per column:
-// each lane picks its best row, two butterfly shuffles pick the group's, the
-// pivot row (A then E) is broadcast from its lane, and every row is scaled or
-// eliminated with it.  Rows are never swapped: a row records the column it
-// pivoted, and its part of the inverse is stored as that row of the inverse,
-// SoA: inv[(12 r + j) * C + c] (entry-major: each of the 144 loads of a
-// wavefront in the apply reads one contiguous 256-byte segment).
+// column among the rows not yet used as pivots, the lowest row on ties), in
+// place.  A group of 4 lanes works on one cell; lane l holds rows
+// 3 l .. 3 l + 2 of the block, read from the cell blocks the assembly wrote
+// (cblk[144 c + 12 r + j]: a group reads 576 contiguous bytes).  Per column
+// k: each lane picks its best row, two butterfly shuffles pick the group's
+// row p, the pivot row is broadcast from its lane, scaled by 1 / a_pk and
+// subtracted from every other row, and column k turns into the column of
+// the identity's unit vector e_p (the classic in-place inversion: it holds
+// 1 / a_pk in row p and -a_ik / a_pk elsewhere).  Rows are never swapped: a
+// row records the column it pivoted (order) and the group the row that
+// pivoted each column (pc), so that at the end entry (i, k) of the array is
+// entry (order[i], pc[k]) of the inverse, stored SoA:
+// inv[(12 r + j) * C + c] (entry-major: each of the 144 loads of a wavefront
+// in the apply reads one contiguous 256-byte segment).
 template <typename T>
 __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__restrict__ cblk, T *__restrict__ inv) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = gid >> 2;
   const int l = threadIdx.x & 3;
   const bool live = c < L.C;
-  double A[3][12], E[3][12];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 12; ++j) {
-      E[i][j] = (j == 3 * l + i) ? 1.0 : 0.0;
-      A[i][j] = live ? 0.0 : E[i][j];
-    }
+  double A[3][12];
   if (live) {
     const T *row = cblk + static_cast<size_t>(c) * 144 + 36 * l;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 12; ++j) A[i][j] = static_cast<double>(row[12 * i + j]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 12; ++j) A[i][j] = (j == 3 * l + i) ? 1.0 : 0.0;
   }
   bool used[3] = {false, false, false};
   int order[3] = {0, 0, 0};
+  int pc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     double val = -2.0;
@@ -887,42 +890,39 @@ __global__ void __launch_bounds__(256) k_vanka_factor(LevelView L, const T *__re
         idx = oi;
       }
     }
+    pc[k] = idx;
     const int owner = idx / 3, li = idx - 3 * owner;
-    double send[12], prow[12];
+    double pr[12];
 #pragma unroll
-    for (int j = 0; j < 12; ++j) send[j] = li == 0 ? A[0][j] : (li == 1 ? A[1][j] : A[2][j]);
-#pragma unroll
-    for (int j = 0; j < 12; ++j) prow[j] = __shfl(send[j], owner, 4);
-    const double piv = prow[k];
+    for (int j = 0; j < 12; ++j) {
+      const double send = li == 0 ? A[0][j] : (li == 1 ? A[1][j] : A[2][j]);
+      pr[j] = __shfl(send, owner, 4);
+    }
+    const double piv = pr[k];
     const double ip = piv != 0.0 ? 1.0 / piv : 0.0;
-    double fct[3];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) pr[j] = (j == k) ? ip : pr[j] * ip;   // the new pivot row
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const bool me = 3 * l + i == idx;
-      fct[i] = me ? ip : A[i][k] * ip;
       if (me) {
         used[i] = true;
         order[i] = k;
       }
+      const double f = A[i][k];
 #pragma unroll
-      for (int j = 0; j < 12; ++j) A[i][j] = me ? A[i][j] * ip : A[i][j] - fct[i] * prow[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 12; ++j) send[j] = li == 0 ? E[0][j] : (li == 1 ? E[1][j] : E[2][j]);
-#pragma unroll
-    for (int j = 0; j < 12; ++j) prow[j] = __shfl(send[j], owner, 4);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const bool me = 3 * l + i == idx;
-#pragma unroll
-      for (int j = 0; j < 12; ++j) E[i][j] = me ? E[i][j] * ip : E[i][j] - fct[i] * prow[j];
+      for (int j = 0; j < 12; ++j) {
+        const double e = (j == k) ? 0.0 : A[i][j];   // column k of the other rows: 0 - f / a_pk
+        A[i][j] = me ? pr[j] : e - f * pr[j];
+      }
     }
   }
   if (live) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 12; ++j) inv[static_cast<size_t>(12 * order[i] + j) * L.C + c] = static_cast<T>(E[i][j]);
+      for (int k = 0; k < 12; ++k)
+        inv[static_cast<size_t>(12 * order[i] + pc[k]) * L.C + c] = static_cast<T>(A[i][k]);
   }
 }
 
