@@ -1002,6 +1002,8 @@ def main():
         ref_stats.append(s_)
         ref_sec += sec
         sf.get_dev(ref[n].data_ptr())
+        if (n + 1) % 250 == 0 and n + 1 < E:
+            log(f"reference: {n + 1} of {E} steps")
     stream.synchronize()
     sf.close()
     log(f"reference: {E} level-{F} steps, {E / ref_sec:.2f} steps/s sustained, "
@@ -1039,6 +1041,8 @@ def main():
         mgl_stats.append(s_)
         mgl_sec += sec
         mgl_err.append(rel_errors(ctx.velocity_error(L, sc.device_ptr(), F, ref[n].data_ptr())))
+        if (n + 1) % 500 == 0 and n + 1 < E:
+            log(f"MG({L}): {n + 1} of {E} steps")
     sc.close()
     n_off = max(1, int(round(2 * np.median([s_["newton_iters"] for s_ in mgl_stats[:10]]))))
     ctx.set_params(nu_pre=pre, nu_post=post, nu_coarse=coarse, switch_off_newton=n_off)
@@ -1078,6 +1082,8 @@ def main():
             stats.append(s_)
             total += sec
             errs.append(rel_errors(ctx.velocity_error(F, the_net.fine_velocity_ptr(), F, ref[n].data_ptr())))
+            if (n + 1) % 500 == 0 and n + 1 < E:
+                log(f"DNN-MG window: {n + 1} of {E} steps")
         sc.close()
         return stats, total, errs
 
