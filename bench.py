@@ -464,8 +464,12 @@ def train_on_geometries(P, args, log, stream):
     starts at the start of its fine trajectory and each round carries it on
     from where the previous round stopped (coarse state, hidden state and
     corrected fine state kept), so the last round's states lie as far from
-    the start as the evaluation window's.  Returns the trained weights,
-    standardisation and a summary."""
+    the start as the evaluation window's.  With `val_steps`, a validation
+    geometry of the same generator (the next seed, not trained on) is run
+    with the weights of every round (teacher forcing, then each free-run
+    round) against its own level-F trajectory, and the weights with the
+    lowest mean velocity error there are returned.  Returns the trained
+    weights, standardisation and a summary."""
     import numpy as np
     import torch
 
@@ -498,6 +502,43 @@ def train_on_geometries(P, args, log, stream):
             f"{X.shape[1]} patches, {time.perf_counter() - t_all:.1f} s so far")
     net0 = geoms[0]["net"]
     (mu, sg, osc), (mu_f, sg_f, os_f) = standardisation(net0, Xr, Dr)
+    val = None
+    if args.val_steps > 0:
+        vseed = args.train_seed0 + args.train_geoms
+        vmacro = training_channel(vseed)
+        vctx = make_context(P, vmacro, args, stream.cuda_stream)
+        vctx.setup_mesh(vmacro, F)
+        vnet = P.Net(vctx, L, m, args.hidden, args.layers)
+        vx0, vt0 = spin_up(vctx, L, F, args.t_dev + args.train_stagger * args.train_geoms, args.relax, dt, log,
+                           f"validation seed {vseed} (Re {0.1 / vmacro.nu:.1f})")
+        vref = torch.empty((args.val_steps, 3 * vctx.level_info(F)[0]), dtype=torch.float64, device="cuda")
+        sf = vctx.state(F)
+        sf.set(vx0, vt0)
+        for n in range(args.val_steps):
+            vctx.step(sf, dt)
+            sf.get_dev(vref[n].data_ptr())
+        stream.synchronize()
+        sf.close()
+        val = {"seed": vseed, "re": round(0.1 / vmacro.nu, 2), "t_start": vt0, "ctx": vctx, "net": vnet,
+               "x0": vx0, "ref": vref}
+
+    def validate(w):
+        """Mean mass-weighted velocity error of a free DNN-MG run with
+        weights w on the validation geometry."""
+        vctx, vnet = val["ctx"], val["net"]
+        vnet.set_weights(w, mu=mu, sigma=sg, out_scale=osc)
+        st = vctx.state(L)
+        st.set(val["x0"][:3 * vctx.level_info(L)[0]], val["t_start"])
+        vnet.reset(st)
+        vnet.rhs_from_fine(st, val["x0"], dt)
+        errs = []
+        for n in range(args.val_steps):
+            vctx.step(st, dt)
+            vnet.correct(st, dt)
+            errs.append(rel_errors(vctx.velocity_error(F, vnet.fine_velocity_ptr(), F,
+                                                       val["ref"][n].data_ptr()))["l2"])
+        st.close()
+        return float(np.mean(errs))
     dev = torch.device("cuda")
     Xd = torch.cat([torch.from_numpy(sequences((X - mu_f) / sg_f, seq)).to(dev) for X in Xr], dim=1)
     Dd = torch.cat([torch.from_numpy(sequences(D / os_f, seq)).to(dev) for D in Dr], dim=1)
@@ -510,6 +551,12 @@ def train_on_geometries(P, args, log, stream):
     fit_sec, fit_its = sec, its
     log(f"net training (teacher forcing): loss {loss:.2f}, {data.n_seq} sequences of {seq} steps, "
         f"{data.nb} minibatches of {data.B}, {1e3 * sec / its:.2f} ms per iteration")
+    val_err, best = [], None
+    if val:
+        w = net0.get_weights()
+        val_err.append(validate(w))
+        best = (val_err[-1], 0, w)
+        log(f"validation (teacher forcing): mean velocity error {val_err[-1]:.3e}")
     runs = {}
     for rnd in range(args.dagger):
         # free DNN-MG runs with the current network; the target of each step is
@@ -555,10 +602,16 @@ def train_on_geometries(P, args, log, stream):
         fit_its += its
         log(f"net training (round {rnd + 1}, free DNN-MG states added): loss {loss:.2f}, "
             f"{data.n_seq} sequences")
+        if val:
+            w = net0.get_weights()
+            val_err.append(validate(w))
+            if val_err[-1] < best[0]:
+                best = (val_err[-1], rnd + 1, w)
+            log(f"validation (round {rnd + 1}): mean velocity error {val_err[-1]:.3e}")
     for st, sf, _ in runs.values():
         sf.close()
         st.close()
-    w = net0.get_weights()
+    w = best[2] if val else net0.get_weights()
     info = {"geometries": [{"seed": g["seed"], "re": g["re"]} for g in geoms],
             "t_start": [round(g["t0"], 4) for g in geoms], "fine_steps_per_geometry": args.train_steps,
             "sequences": int(data.n_seq), "seq": seq, "batch": data.B, "rounds": 1 + args.dagger,
@@ -567,6 +620,13 @@ def train_on_geometries(P, args, log, stream):
             "adam_iters": fit_its, "final_loss": round(float(loss), 4),
             "bptt_ms_per_iter": round(1e3 * fit_sec / fit_its, 3),
             "wall_s": round(time.perf_counter() - t_all, 1)}
+    if val:
+        info["validation"] = {"seed": val["seed"], "re": val["re"], "t_start": round(val["t_start"], 4),
+                              "steps": args.val_steps, "mean_l2_per_round": [float(f"{e:.4e}") for e in val_err],
+                              "kept_round": best[1]}
+        val["net"].close()
+        val["ctx"].close()
+        del val["ref"]
     for g in geoms:
         g["net"].close()
         g["ctx"].close()
@@ -857,6 +917,9 @@ def main():
                          "fine step started from the run's own state; each round carries the runs on)")
     ap.add_argument("--dagger-steps", type=int, default=64, help="free-run steps per geometry and round")
     ap.add_argument("--dagger-iters", type=int, default=300)
+    ap.add_argument("--val-steps", type=int, default=200,
+                    help="steps of the validation run (training generator seed train-seed0 + train-geoms, not "
+                         "trained on) that picks the round whose weights are kept; 0: the last round's")
     ap.add_argument("--extra-eval-seeds", default="",
                     help="comma-separated channel seeds (e.g. 300,301,302,303) evaluated like the main "
                          "geometry (error window only) with the same trained network")

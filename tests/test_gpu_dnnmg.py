@@ -223,15 +223,19 @@ def test_dnnmg_trajectory_matches_oracle(setup):
     net.close()
 
 
-@pytest.mark.parametrize("L,m,patch,hidden,layers,T", [(1, 2, "block", 64, 2, 16), (1, 2, "block", 128, 2, 32),
-                                                        (1, 2, "block", 256, 2, 16), (2, 1, "cell", 32, 3, 16),
-                                                        (2, 1, "cell", 64, 1, 16)])
-def test_bptt_gradient_matches_oracle(setup, L, m, patch, hidden, layers, T):
+@pytest.mark.parametrize("L,m,patch,hidden,layers,T,B", [(1, 2, "block", 64, 2, 16, 64), (1, 2, "block", 128, 2, 32, 64),
+                                                          (1, 2, "block", 256, 2, 16, 64), (2, 1, "cell", 32, 3, 16, 64),
+                                                          (2, 1, "cell", 64, 1, 16, 64),
+                                                          (1, 2, "block", 128, 2, 8, 2048)])
+def test_bptt_gradient_matches_oracle(setup, L, m, patch, hidden, layers, T, B):
     """Hand-written BPTT (BF16 MFMA GEMMs, FP32 gates, checkpoints every 8
-    steps) against the FP64 oracle gradient on a 64-sequence batch: relative
-    L2 <= 3e-2 and cosine >= 0.999 (BF16 bar); the loss to 1e-2.  Shapes: the
-    block-patch nets of the training workload (H = 64, 128 at its 32-step
-    sequences, 256) and two of Table 1's cell-patch nets (I = 51, O = 18)."""
+    steps) against the FP64 oracle gradient: relative L2 <= 3e-2 and cosine
+    >= 0.999 (BF16 bar); the loss to 1e-2.  Shapes: the block-patch nets of
+    the training workload (H = 64, 128 at its 32-step sequences, 256) and two
+    of Table 1's cell-patch nets (I = 51, O = 18) on 64 sequences; H = 128 on
+    2,048 sequences, whose input projections (8 x 2,048 rows, 384 gate
+    columns) take the 128 x 128 tile GEMM (the 64 x 64 one with checkpoints
+    every 4 steps)."""
     P, macro, lev, ctx, prob = setup
     net = P.Net(ctx, L, m, hidden=hidden, layers=layers, patch=patch)
     dims = (net.n_in, hidden, layers, net.n_out)
@@ -239,7 +243,6 @@ def test_bptt_gradient_matches_oracle(setup, L, m, patch, hidden, layers, T):
     w = gru_weights(*dims, seed=21).astype(np.float32).astype(np.float64)
     net.set_weights(w)
     rng = np.random.default_rng(5)
-    B = 64
     X = rng.standard_normal((T, B, net.n_in)).astype(np.float32)
     Dt = (0.3 * rng.standard_normal((T, B, net.n_out))).astype(np.float32)
     loss_g, g_gpu = net.gradient(X, Dt, ckpt=8)
