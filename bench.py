@@ -911,12 +911,12 @@ def main():
     ap.add_argument("--train-steps", type=int, default=64, help="fine steps per training geometry")
     ap.add_argument("--train-seq", type=int, default=32)
     ap.add_argument("--train-batch", type=int, default=8192)
-    ap.add_argument("--train-net-iters", type=int, default=400)
+    ap.add_argument("--train-net-iters", type=int, default=1500, help="Adam iterations on the teacher-forced data")
     ap.add_argument("--dagger", type=int, default=3,
                     help="training rounds on free DNN-MG runs of the training geometries (targets from one "
                          "fine step started from the run's own state; each round carries the runs on)")
     ap.add_argument("--dagger-steps", type=int, default=64, help="free-run steps per geometry and round")
-    ap.add_argument("--dagger-iters", type=int, default=300)
+    ap.add_argument("--dagger-iters", type=int, default=1000, help="Adam iterations after each free-run round")
     ap.add_argument("--val-steps", type=int, default=200,
                     help="steps of the validation run (training generator seed train-seed0 + train-geoms, not "
                          "trained on) that picks the round whose weights are kept; 0: the last round's")
