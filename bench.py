@@ -960,6 +960,7 @@ def main():
                     help="batched plain solves: simulations (0 skips the leg)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-solve leg")
+    ap.add_argument("--table1-only", action="store_true", help="run only the network-size sweep")
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--table1", type=int, default=0, choices=(0, 1),
                     help="network-size sweep (Table 1 shapes on cell patches, untimed leg)")
@@ -1006,6 +1007,9 @@ def main():
 
     if args.batch_only:     # only the batched-solve leg (profiling runs)
         print(json.dumps({"batch": run_batch(P, args, log)}), flush=True)
+        return
+    if args.table1_only:    # only the network-size sweep
+        print(json.dumps({"table1": run_table1(P, args, log)}), flush=True)
         return
 
     # ---- network training on held-out geometries (untimed)
