@@ -969,7 +969,7 @@ def main():
     ap.add_argument("--t1-train-from", type=float, default=4.0)
     ap.add_argument("--t1-start", type=float, default=7.0)
     ap.add_argument("--t1-end", type=float, default=10.0)
-    ap.add_argument("--t1-iters", type=int, default=600)
+    ap.add_argument("--t1-iters", type=int, default=3000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="device copy of this many MiB before the run (calibrates "
                          "hardware traffic counters against a known byte count)")
