@@ -207,15 +207,14 @@ def _oracle_run(job):
 
 
 def cpu_baseline(args, log):
-    """The FP64 oracle on the host's cores.  Config 1 (the FP64 parity
-    workload: seed 0, level 3, dt 0.01, 10 steps from rest) in full on one
-    core; the same run for seeds 0..P-1 as P independent single-core processes
+    """The FP64 oracle on the host's cores.  The FP64 parity workload (seed 0,
+    level 3, dt 0.01, 10 steps from rest) in full on one core; the same run for seeds 0..P-1 as P independent single-core processes
     (all cores); optionally level-5 steps of the same geometry (dt 0.005)."""
     import multiprocessing as mp
     nproc = os.cpu_count() or 1
     sec, dofs, newton = _oracle_run((0, 3, 0.01, 10))
     out = {"value": round(10 / sec, 4), "unit": "time steps/s", "cores": 1, "kind": "oracle",
-           "sample": (f"config 1 in full: FP64 oracle (numpy einsum assembly, SuperLU direct solves), seed 0, "
+           "sample": (f"the FP64 parity workload in full: FP64 oracle (numpy einsum assembly, SuperLU direct solves), seed 0, "
                       f"level 3 ({dofs} DoFs), dt 0.01, 10 steps from rest, {newton} Newton iterations, "
                       f"{sec:.2f} s on one core; not the headline's level-5/7 workload (one oracle DNN-MG "
                       f"step there takes minutes)"),
@@ -453,8 +452,9 @@ class Minibatches:
 
 
 def train_on_geometries(P, args, log, stream):
-    """Training workload stand-in (config 5 at reduced count): for each seed
-    of the training generator, the developed flow on level F, a fine
+    """Training workload (seeded geometries of the training generator, a
+    reduced count): for each seed of the training generator, the developed
+    flow on level F, a fine
     trajectory of train_steps steps, teacher-forced coarse steps (inputs and
     targets), then BPTT + Adam on the GPU; `dagger` rounds add the states of
     free DNN-MG runs on the same geometries, each step's target the

@@ -103,12 +103,12 @@ def test_batch_set_get_is_per_member():
     batch.close()
 
 
-# config 3's depths: seeds with depth 4 (two members: one group of two), 5, 6, 7
+# the 64-simulation batch's depths: seeds with depth 4 (two members: one group of two), 5, 6, 7
 DEEP = [(102, 4), (111, 4), (103, 5), (105, 6), (100, 7)]
 
 
 def test_batch_at_config3_depths_follows_lone_runs():
-    """Members at config 3's depths 4-7 (seeds 102 and 111 at depth 4, 103 at
+    """Members at the 64-simulation batch's depths 4-7 (seeds 102 and 111 at depth 4, 103 at
     5, 105 at 6 and 100, three obstacles, at 7; Re 60-198): in mixed
     precision every member of the batch follows its lone context's trajectory
     to 1e-5 relative L2 per field over two steps of dt 0.005."""
@@ -139,7 +139,7 @@ def test_batch_at_config3_depths_follows_lone_runs():
 
 
 def test_batch_depth4_member_matches_oracle():
-    """FP64 batch of the two depth-4 members of config 3 (seeds 102, 111):
+    """FP64 batch of the two depth-4 members of the 64-simulation batch (seeds 102, 111):
     the first member's first step equals the oracle's direct Newton step to
     1e-10 relative L2 per field (GPU Newton 1e-14; oracle floor 4e-17)."""
     import paper_2106_07687_amd as P

@@ -137,7 +137,7 @@ def test_dnnmg_correction_at_full_size():
 
 @pytest.mark.slow
 def test_level5_step_from_developed_inflow_matches_oracle_direct_newton():
-    """Config 2's comparison with the FP64 oracle on level 5 (260k DoFs): one
+    """The level-5 comparison with the FP64 oracle (260k DoFs): one
     time step (dt 0.005, t = 1 -> 1.005, the inflow fully ramped) from an
     analytic state, the fully developed channel profile u = 6 y (H - y) / H^2,
     v = 0, p = 0 at every node (written from the oracle's coordinates, not by
