@@ -13,8 +13,11 @@ residual, update, coarse solve and Gram-Schmidt dots).
    GPU (untimed) on other geometries of the training generator (seeds 200..,
    Re ~ U[80, 120], each spun up the same way): teacher-forced sequences
    (Sec. 3.1 training data, eq. loss) plus rounds that add the states of free
-   DNN-MG runs, with targets from one fine step started from each such
-   state.  The evaluated geometry is never seen in training.
+   DNN-MG runs carried on from round to round, with targets from one fine
+   step started from each such state; the round whose weights give the
+   lowest velocity error on a validation geometry (the generator's next
+   seed, not trained on) is kept.  The evaluated geometry is never seen in
+   training.
 3. Timed legs (the benchmark contract): full-depth GMG on level 7, and DNN-MG
    (Newton-GMRES-GMG on level 5 + the network correcting level 7,
    Algorithm 1), W untimed + K timed steps each from x7.  `value` is the
@@ -31,8 +34,10 @@ stream over the timed GMG steps (the dominant kernel by total time, its
 launches of both forms merged); `cpu_baseline` times the FP64 oracle on the
 host: the FP64 parity workload (level 3, 10 steps) in full on one core and,
 as independent runs, on all cores (optionally also level-5 steps).
-Optional legs: batched plain solves (--batch-sims) and the network-size sweep
-of Table 1 (--table1).
+Optional legs: batched plain solves (--batch-sims, or alone with
+--batch-only), the network-size sweep of Table 1 (--table1, or alone with
+--table1-only), the switch-off study (--switchoff-study) and held-out
+geometries (--extra-eval-seeds).
 """
 from __future__ import annotations
 
