@@ -417,7 +417,7 @@ int dnnmg_velocity_error_noalloc(dnnmg_ctx *ctx, int level, const double *x_dev,
  * time step of eqs. nonlinearshort/newton on its own mesh and viscosity),
  * advanced together.  Simulations of equal depth are merged into one group
  * whose launches cover all of them (the level-0 direct solve is block
- * diagonal, one block per simulation, each at most 1024 unknowns); the groups
+ * diagonal, one block per simulation, each at most 1536 unknowns); the groups
  * run concurrently on streams the batch creates (params->stream is ignored).
  * A group's Newton and GMRES norms span its members: a group step converges
  * when the union's residual meets newton_tol, so each member's does. */
